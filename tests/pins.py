@@ -1,0 +1,94 @@
+"""Pin checks for the oracle, written as functions that return a residual so
+that the planted-mistake tests can show each pin rejects a wrong oracle.
+
+Each function cites the statement of the paper (or the textbook fact) it
+pins against.  None of them re-types the oracle's own formula: they compare
+against an independent route (an explicit Krylov basis, a dense
+factorization, a textbook recurrence, a theorem's inequality).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import synth
+from oracle import block_cg as ob
+from oracle import krylov as ok
+from oracle import quadrature as oq
+from oracle import truth as ot
+
+
+def small_spd(d, p=2.0, seed=0, scale=1.0):
+    g = np.random.default_rng(seed)
+    lam = scale * np.arange(1, d + 1, dtype=float) ** (-p)
+    Q = synth.orthogonal(d, g)
+    A = (Q * lam) @ Q.T
+    return 0.5 * (A + A.T), lam
+
+
+def definition_gap(d=36, k=2, ts=(1, 2, 3, 4), mu=1e-2, seed=1):
+    """max over t of the relative A_mu error between the block-Lanczos
+    oracle and the def. BCG Galerkin solution over an explicit basis."""
+    A, _ = small_spd(d, p=1.0, seed=seed)
+    g = np.random.default_rng(seed + 100)
+    b = g.standard_normal(d)
+    Om = g.standard_normal((k, d))
+    worst = 0.0
+    for t in ts:
+        X, _ = ob.bcg(A, [mu], b, Om, t)
+        xd = ob.bcg_definition(A, mu, b, Om, t)
+        worst = max(worst, ob.rel_a_err(A, mu, X[0], xd))
+    return worst
+
+
+def exact_termination_gap(d=60, k=5, t=10, mu=1e-3, seed=2):
+    """(k+1) t >= d: block-CG is exact; relative A_mu error against a dense
+    Cholesky solve."""
+    A, _ = small_spd(d, p=2.0, seed=seed)
+    g = np.random.default_rng(seed + 100)
+    b = g.standard_normal(d)
+    Om = g.standard_normal((k, d))
+    X, _ = ob.bcg(A, [mu], b, Om, t)
+    return ob.rel_a_err(A, mu, X[0], ot.solve_dense(A, mu, b))
+
+
+def cg_gap(d=80, t_max=10, mu=1e-2, seed=3):
+    """k = 0: block-CG reduces to CG; compare with the textbook
+    Hestenes-Stiefel recurrence at every t."""
+    A, _ = small_spd(d, p=1.0, seed=seed)
+    b = np.random.default_rng(seed + 100).standard_normal(d)
+    worst = 0.0
+    for t in range(1, t_max + 1):
+        X, _ = ob.bcg(A, [mu], b, None, t)
+        xc = ok.cg_hestenes_stiefel(A, mu, b, t)
+        worst = max(worst, ob.rel_a_err(A, mu, X[0], xc))
+    return worst
+
+
+def path_gap(d=40, k=3, t=3, seed=4):
+    """Shift invariance: the path from one Krylov space equals the
+    definition-tier solution at every shift (eq. shift_invariance, eq.
+    bcg_alg)."""
+    A, _ = small_spd(d, p=1.0, seed=seed)
+    g = np.random.default_rng(seed + 100)
+    b = g.standard_normal(d)
+    Om = g.standard_normal((k, d))
+    mus = [0.0, 1e-3, 1e-1, 1.0]
+    X, _ = ob.bcg(A, mus, b, Om, t)
+    return max(ob.rel_a_err(A, mu, X[i], ob.bcg_definition(A, mu, b, Om, t)) for i, mu in enumerate(mus))
+
+
+def sqrt_full_space_gap(d=48, m=8, t=6, seed=5):
+    """m t >= d: the block-Lanczos square root is exact; compare with
+    A^(1/2) B by eigendecomposition (def. blansq)."""
+    A, _ = small_spd(d, p=1.0, seed=seed)
+    B = np.random.default_rng(seed + 100).standard_normal((m, d))
+    Y, _ = ob.sqrt_apply_exact(A, B, t)
+    Yt = ot.sqrt_eig(A, B)
+    return float(np.max(np.linalg.norm(Y - Yt, axis=1) / np.linalg.norm(Yt, axis=1)))
+
+
+def quadrature_gap(m=1e-6, M=244.0, N=32):
+    """Scalar accuracy of the square-root rule on a log grid of [m, M]."""
+    s, w = oq.sqrt_rule(m, M, N)
+    lam = np.logspace(np.log10(m), np.log10(M), 301)
+    return float(np.max(np.abs(oq.apply_rule_scalar(lam, s, w) - np.sqrt(lam)) / np.sqrt(lam)))

@@ -1,0 +1,112 @@
+"""Planted mistakes, on the CPU only: each test swaps one step of the oracle
+for a plausible wrong variant and checks that at least one pin rejects it.
+This shows the pins are sharp enough to catch a dropped term, a wrong sign,
+a wrong index or a transposed operand."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import block_cg as ob
+from oracle import quadrature as oq
+
+import pins
+
+
+def _wrong_sign_shift(T, mu, rhs):
+    n = T.shape[0]
+    return np.linalg.solve(T - mu * np.eye(n) + 2 * abs(mu) * 0, rhs)
+
+
+def _dropped_shift(T, mu, rhs):
+    return np.linalg.solve(T, rhs)
+
+
+def _transposed_lower(T, mu, rhs):
+    # a non-symmetric T (only the lower triangle kept) as if one operand were transposed
+    n = T.shape[0]
+    return np.linalg.solve(np.tril(T) + mu * np.eye(n), rhs)
+
+
+@pytest.mark.parametrize("bad", [_wrong_sign_shift, _dropped_shift, _transposed_lower])
+def test_pins_reject_bad_shifted_solve(monkeypatch, bad):
+    monkeypatch.setattr(ob, "shifted_solve", bad)
+    assert max(pins.path_gap(), pins.exact_termination_gap()) > 1e-6
+
+
+def test_pins_reject_wrong_rhs_index(monkeypatch):
+    orig = ob.shifted_solve
+
+    def e2(T, mu, rhs):
+        r = np.roll(rhs, 1)
+        return orig(T, mu, r)
+    monkeypatch.setattr(ob, "shifted_solve", e2)
+    assert pins.definition_gap() > 1e-6
+
+
+def test_pins_reject_missing_reorthogonalisation(monkeypatch):
+    # dropping the projection altogether breaks orthogonality of the basis
+    monkeypatch.setattr(ob, "_project_out", lambda W, Q: W)
+    assert max(pins.definition_gap(), pins.exact_termination_gap()) > 1e-6
+
+
+def test_pins_reject_missing_operator_in_T(monkeypatch):
+    orig = ob.block_lanczos
+
+    def no_A(A, B, t, eta=ob.ETA, first_fixed=True):
+        lz = orig(A, B, t, eta=eta, first_fixed=first_fixed)
+        lz["T"] = lz["Q"].T @ lz["Q"]
+        return lz
+    monkeypatch.setattr(ob, "block_lanczos", no_A)
+    assert pins.definition_gap() > 1e-6
+
+
+def test_pins_reject_dropped_b_column(monkeypatch):
+    orig = ob.block_lanczos
+
+    def no_b(A, B, t, eta=ob.ETA, first_fixed=True):
+        B = np.array(B, copy=True)
+        if B.shape[1] > 1:
+            B[:, 0] = B[:, 1] + 1e-3 * B[:, 0]
+        return orig(A, B, t, eta=eta, first_fixed=first_fixed)
+    monkeypatch.setattr(ob, "block_lanczos", no_b)
+    assert pins.definition_gap() > 1e-6
+
+
+def test_pins_reject_sqrt_without_leading_A(monkeypatch):
+    orig = ob.block_lanczos
+
+    def wrong(A, B, t, eta=ob.ETA, first_fixed=True):
+        lz = orig(A, B, t, eta=eta, first_fixed=first_fixed)
+        lz["AQ"] = lz["Q"]          # drops the leading A of def. blansq
+        return lz
+    monkeypatch.setattr(ob, "block_lanczos", wrong)
+    assert pins.sqrt_full_space_gap() > 1e-6
+
+
+def test_pins_reject_quadrature_missing_factor(monkeypatch):
+    orig = oq.sqrt_rule
+
+    def wrong(m, M, N, dps=40):
+        s, w = orig(m, M, N, dps)
+        return s, w / np.sqrt(m)     # the sqrt(m) Jacobian factor dropped
+    monkeypatch.setattr(oq, "sqrt_rule", wrong)
+    assert pins.quadrature_gap() > 1e-6
+
+
+def test_pins_reject_quadrature_off_by_half_node(monkeypatch):
+    import mpmath as mp
+
+    def wrong(m, M, N, dps=40):
+        with mp.workdps(dps):
+            kp2 = 1 - mp.mpf(m) / mp.mpf(M)
+            Kp = mp.ellipk(kp2)
+            s = np.empty(N)
+            w = np.empty(N)
+            for j in range(N):
+                v = (j + 1) * Kp / (N + 1)       # trapezoid-like nodes with midpoint weights
+                sn, cn, dn = (mp.ellipfun(f, v, m=kp2) for f in ("sn", "cn", "dn"))
+                s[j] = float(m * (sn / cn) ** 2)
+                w[j] = float(2 / mp.pi * Kp / N * mp.sqrt(m) * dn / cn ** 2)
+        return s, w
+    monkeypatch.setattr(oq, "sqrt_rule", wrong)
+    assert pins.quadrature_gap() > 1e-6
