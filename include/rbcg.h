@@ -1,0 +1,187 @@
+/*
+ * rbcg.h -- C ABI of the MI355X (gfx950) randomized block-CG library.
+ *
+ * The library solves regularized symmetric positive definite systems
+ *     (A + mu I) x = b,      A in R^{d x d} SPD, mu >= 0
+ * (paper: Sec. 1, eq. regularized_ls) with block-CG on the block Krylov space
+ * K_t(A, [b Omega]) of the augmented start block [b Omega], Omega a d x k
+ * Gaussian block (Sec. 3, def. BCG; Thm. main).  It is implemented with
+ * block-Lanczos and full reorthogonalisation, after which the iterate for any
+ * shift is ||b|| Q_t (T_t + mu I)^{-1} e_1 (Sec. 3.2, eq. bcg_alg).
+ *
+ * Three entry points follow the paper's three problem statements:
+ *   rbcg_solve       one shift per system, many independent systems per call
+ *                    (Sec. 1, eq. regularized_ls)
+ *   rbcg_path        one operator, L shifts from one Krylov space: the whole
+ *                    ridge-regression path when A = Z^T Z (Sec. 1,
+ *                    eq. ridge_regression; Sec. 3.2, eq. bcg_alg)
+ *   rbcg_sqrt_apply  Gaussian sampling A^{1/2} B by the block-Lanczos square
+ *                    root with a quadrature over the shifts z^2 (Sec. 1,
+ *                    eq. sqrt_rational; Sec. 5, def. blansq)
+ *
+ * Conventions for every call
+ *   - Memory: every matrix or vector argument documented as "device" is a
+ *     pointer into GPU memory of the device current when the context was
+ *     created; "host" arguments are ordinary host memory.  The caller owns
+ *     all of them.  The library reads inputs, writes outputs, never frees or
+ *     retains caller pointers after the call returns, and never modifies
+ *     inputs.  Internal workspace belongs to the context (rbcg_ctx) or to an
+ *     operator handle (rbcg_op) and is released by the matching destroy call.
+ *   - Layout: matrices are row-major.  A set of r vectors of length d is an
+ *     r x d row-major array (vector i at offset i*ld), i.e. what a
+ *     contiguous torch tensor of shape (r, d) holds.
+ *   - Streams: work is enqueued on the stream bound to the context.  Every
+ *     solver call returns only after its results are complete (it
+ *     synchronises that stream), because the iteration count and the status
+ *     are decided on the device.
+ *   - Errors: functions return an rbcg_status code.  Argument validation
+ *     happens before any device work; on RBCG_ERR_INVALID_ARG nothing has
+ *     been enqueued and outputs are untouched.  rbcg_status_string gives a
+ *     static description.
+ *   - Threads: a context must not be used by two threads at once.  Distinct
+ *     contexts are independent.
+ */
+#ifndef RBCG_H
+#define RBCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RBCG_OK = 0,
+  RBCG_ERR_INVALID_ARG = -1,    /* bad size, pointer, tolerance or option */
+  RBCG_ERR_NOT_SPD = -2,        /* a non-positive pivot in T_t + mu I or in a start block */
+  RBCG_ERR_BREAKDOWN = -3,      /* the whole block deflated before convergence */
+  RBCG_ERR_NO_CONVERGENCE = -4, /* budget exhausted; best iterate written, info.relres set */
+  RBCG_ERR_HIP = -5,            /* a HIP runtime call failed */
+  RBCG_ERR_OOM = -6,            /* device workspace allocation failed */
+  RBCG_ERR_UNSUPPORTED = -7     /* device is not gfx950, or an unsupported option combination */
+} rbcg_status;
+
+typedef enum { RBCG_F64 = 0, RBCG_F32 = 1, RBCG_BF16 = 2 } rbcg_dtype;
+typedef enum { RBCG_OP_DENSE = 0, RBCG_OP_GRAM = 1 } rbcg_op_kind;
+
+typedef struct rbcg_ctx rbcg_ctx;
+typedef struct rbcg_op rbcg_op;
+
+/* Static description of a status code (never NULL). */
+const char* rbcg_status_string(int status);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int rbcg_version(void);
+
+/* Create a context bound to `hip_stream` (a hipStream_t; NULL = the null
+ * stream) on the current device.  Fails with RBCG_ERR_UNSUPPORTED when the
+ * current device is not gfx950. */
+int rbcg_create(rbcg_ctx** ctx, void* hip_stream);
+int rbcg_destroy(rbcg_ctx* ctx);
+
+/* ------------------------------------------------------------------ operators
+ * An operator handle describes A and holds the low-precision copies used by
+ * mixed-precision block products.  The caller's master data must stay alive
+ * and unchanged while the handle is used.
+ *
+ * Dense:  A is d x d, row-major, FP64, leading dimension lda >= d, symmetric
+ *         positive semi-definite (Sec. 1).  `lo` chooses which low-precision
+ *         copy to build now: RBCG_F64 = none, RBCG_F32 = FP32 copy (RNE).
+ * Gram:   A = Z^T Z with Z n x d row-major FP32, ldz >= d (Sec. 1, ridge
+ *         regression).  The block product is Z^T (Z X) (two passes over Z).
+ *         `lo` = RBCG_BF16 builds BF16 copies of Z and of Z^T (RNE);
+ *         RBCG_F64 builds none (FP64 arithmetic on the FP32 values).
+ */
+int rbcg_op_create_dense(rbcg_ctx* ctx, rbcg_op** op, int64_t d, const double* A /*device*/,
+                         int64_t lda, int lo);
+int rbcg_op_create_gram(rbcg_ctx* ctx, rbcg_op** op, int64_t n, int64_t d, const float* Z /*device*/,
+                        int64_t ldz, int lo);
+int rbcg_op_destroy(rbcg_op* op);
+
+/* ---------------------------------------------------------------------- options */
+typedef struct {
+  int32_t t_max;       /* max block products (matrix-loads) per Krylov space; >= 1 */
+  double rtol;         /* stop when ||b - A_mu x|| / ||b|| <= rtol (FP64 residual);
+                          0 = run exactly t_max products, no refinement */
+  int32_t matvec;      /* rbcg_dtype of the block products: F64 = plain; F32 (dense) or
+                          BF16 (Gram) = low precision with FP32 accumulation and FP64
+                          iterative refinement */
+  int32_t refine_max;  /* max Krylov spaces (refinement sweeps) when rtol > 0; >= 1 */
+  int32_t nquad;       /* rbcg_sqrt_apply: quadrature nodes (default 32 when 0) */
+  int32_t group;       /* rbcg_sqrt_apply: samples per Krylov block (default 32 when 0) */
+  double eta;          /* deflation threshold relative to a block's pre-projection norm
+                          (default 1e-10 when 0) */
+} rbcg_opts;
+
+/* Per-result report. */
+typedef struct {
+  int32_t status;          /* rbcg_status of this result */
+  int32_t iters;           /* block products in the last Krylov space */
+  int32_t matrix_loads;    /* all block products, plus one per FP64 residual evaluation */
+  int32_t refine_sweeps;   /* Krylov spaces built */
+  int32_t deflated;        /* basis directions dropped as rank-deficient */
+  int32_t precision_used;  /* rbcg_dtype used for the block products */
+  double relres;           /* ||b - A_mu x|| / ||b|| in FP64 (-1 if not evaluated) */
+} rbcg_info;
+
+/* ----------------------------------------------------------------- solvers */
+
+/* Independent systems (A_s + mu_s I) x_s = b_s, s = 0..nsys-1, advanced
+ * together (one launch per kernel for all systems).
+ *   ops[s]    operator of system s (host array of nsys handles); d_s = its dimension
+ *   mu        host[nsys], mu_s >= 0
+ *   b         host[nsys] of device pointers to b_s (length d_s, FP64)
+ *   omega     host[nsys] of device pointers to Omega_s (k_s x d_s row-major FP64);
+ *             may be NULL for k_s = 0
+ *   k         host[nsys], 0 <= k_s < d_s; block width m_s = k_s + 1
+ *   x         host[nsys] of device pointers to x_s (length d_s, FP64), written
+ *   opts      host[nsys] options per system
+ *   info      host[nsys] reports, written
+ * Returns RBCG_OK when every system reached its tolerance (or ran t_max
+ * products with rtol = 0), else the first failing status (per-system status
+ * is in info). */
+int rbcg_solve(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, const double* mu,
+               const double* const* b, const double* const* omega, const int32_t* k,
+               double* const* x, const rbcg_opts* opts, rbcg_info* info);
+
+/* Regularization path: one Krylov space K_t(A, [b Omega]) serves all L
+ * shifts (eq. bcg_alg).
+ *   b      device, length d (FP64)
+ *   omega  device, k x d row-major (FP64); NULL when k = 0
+ *   mu     host[L], each >= 0
+ *   X      device, L x d row-major (FP64), row l = solution for mu[l]
+ *   info   host[L]
+ * With opts.matvec low-precision and rtol > 0, each refinement sweep builds
+ * a new space on [R Omega] where R holds the residuals of all shifts. */
+int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, const double* omega, int32_t k,
+              int64_t L, const double* mu, double* X, const rbcg_opts* opts, rbcg_info* info);
+
+/* Block-Lanczos square root Y ~ A^{1/2} B (def. blansq).  The m_s samples
+ * (rows of B) are split into groups of opts.group; each group's samples form
+ * one Krylov start block (every sample is augmented by the others in its
+ * group).  All groups share each pass over A.  The z-integral uses an
+ * opts.nquad-node conformal-map rule on the Ritz-value interval of each
+ * group's T_t, evaluated exactly through the Lanczos relation
+ * A Q_t = Q_t T_t + Q_{t+1} B_t E_t^T.
+ *   B   device, m_s x d row-major (FP64)
+ *   Y   device, m_s x d row-major (FP64), written
+ *   info host[m_s]; relres holds -1 (no residual is defined)
+ * opts.rtol is ignored; exactly opts.t_max products are run. */
+int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t m_s, const double* B, double* Y,
+                    const rbcg_opts* opts, rbcg_info* info);
+
+/* Bytes of device memory currently held by the context's workspace. */
+int64_t rbcg_workspace_bytes(const rbcg_ctx* ctx);
+
+/* Host-only, no device needed: the n-node quadrature rule rbcg_sqrt_apply
+ * uses for the integral sqrt(l) = (2/pi) int_0^inf l / (l + z^2) dz on
+ * spectra inside [lo, hi] (eq. sqrt_rational): the conformal-map rule of
+ * Hale, Higham and Trefethen (2008).  Writes shifts[i] = z_i^2 and weights[i]
+ * (host arrays of length n) so that sqrt(l) ~ sum_i weights[i] l / (l + shifts[i]).
+ * Requires 0 < lo <= hi and n >= 1, else RBCG_ERR_INVALID_ARG. */
+int rbcg_sqrt_rule(double lo, double hi, int32_t n, double* shifts, double* weights);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBCG_H */

@@ -1,0 +1,1943 @@
+// Host runtime of the randomized block-CG library: the C ABI declared in include/rbcg.h.
+//
+// A call builds a batch of Krylov problems (systems, a path, or sample groups), lays out
+// all device workspace in one arena, precomputes the kernel descriptors of every
+// block-Lanczos step, uploads them once, and then enqueues the steps on the context's
+// stream.  Convergence is decided on the device (per-problem active flags); the host
+// reads the flags one step behind so it never stalls the GPU.
+//
+// Block-Lanczos with full reorthogonalisation (paper: Sec. 3.2), per step j:
+//   W = A Q_j                                  block product ("matrix-load", Sec. 1.2)
+//   C1 = [Q_0..Q_j W]^T W; W -= Q C1           first projection pass (+ pre-projection norms)
+//   C2 = [Q_0..Q_j]^T W;   W -= Q C2           second pass (BCGS2)
+//   D_j = sym(C1_j + C2_j)                     diagonal block of T
+//   W = Q_{j+1} B_j by pivoted Cholesky QR, twice (rank-revealing, deflating)
+//   optional: one block of the shifted block-Cholesky of T + mu I and the residual estimate
+// and afterwards x(mu) = Q_t (T_t + mu I)^{-1} R_0 e_1 (eq. bcg_alg) for each shift.
+#include "../../include/rbcg.h"
+#include "rbcg_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace rbcg {
+bool sqrt_rule(double lo, double hi, int N, double* shifts, double* weights);
+}
+
+using namespace rbcg;
+
+// ----------------------------------------------------------------------------- basics
+struct rbcg_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_cap = 0;
+  void* pinned = nullptr;   // host staging (descriptors, flags)
+  size_t pinned_cap = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+struct rbcg_op {
+  int kind = RBCG_OP_DENSE;
+  int64_t d = 0, n = 0;
+  const void* data = nullptr;
+  int64_t ld = 0;
+  int lo_t = RBCG_F64;
+  void* lo = nullptr;       // dense: FP32 d x ld_lo; gram: BF16 Z (n x ld_lo)
+  int64_t ld_lo = 0;
+  void* lot = nullptr;      // gram: BF16 Z^T (d x ld_lot)
+  int64_t ld_lot = 0;
+  int device = 0;
+};
+
+#define HIP_TRY(x)                                  \
+  do {                                              \
+    hipError_t e_ = (x);                            \
+    if (e_ != hipSuccess) return fail_hip(e_, #x);  \
+  } while (0)
+
+static int fail_hip(hipError_t e, const char* what) {
+  (void)hipGetLastError();   // do not leave the error for the caller's next HIP call
+  if (std::getenv("RBCG_DEBUG")) std::fprintf(stderr, "rbcg: %s failed: %s\n", what, hipGetErrorString(e));
+  return (e == hipErrorOutOfMemory) ? RBCG_ERR_OOM : RBCG_ERR_HIP;
+}
+
+static inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+extern "C" const char* rbcg_status_string(int s) {
+  switch (s) {
+    case RBCG_OK: return "ok";
+    case RBCG_ERR_INVALID_ARG: return "invalid argument";
+    case RBCG_ERR_NOT_SPD: return "non-positive pivot: T_t + mu I or a start block is not positive definite";
+    case RBCG_ERR_BREAKDOWN: return "block deflated completely before convergence";
+    case RBCG_ERR_NO_CONVERGENCE: return "tolerance not reached within the iteration budget";
+    case RBCG_ERR_HIP: return "HIP runtime error";
+    case RBCG_ERR_OOM: return "device memory allocation failed";
+    case RBCG_ERR_UNSUPPORTED: return "unsupported device or option";
+    default: return "unknown status";
+  }
+}
+
+extern "C" int rbcg_version(void) { return 10000; }
+
+extern "C" int rbcg_create(rbcg_ctx** out, void* stream) {
+  if (!out) return RBCG_ERR_INVALID_ARG;
+  *out = nullptr;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return RBCG_ERR_UNSUPPORTED;
+  rbcg_ctx* c = new rbcg_ctx();
+  c->device = dev;
+  c->stream = (hipStream_t)stream;
+  if (hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) != hipSuccess) {
+    delete c;
+    return RBCG_ERR_HIP;
+  }
+  *out = c;
+  return RBCG_OK;
+}
+
+extern "C" int rbcg_destroy(rbcg_ctx* c) {
+  if (!c) return RBCG_ERR_INVALID_ARG;
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+  return RBCG_OK;
+}
+
+extern "C" int64_t rbcg_workspace_bytes(const rbcg_ctx* c) { return c ? (int64_t)c->ws_cap : 0; }
+
+// ---------------------------------------------------------------------------- operators
+extern "C" int rbcg_op_create_dense(rbcg_ctx* ctx, rbcg_op** out, int64_t d, const double* A, int64_t lda, int lo) {
+  if (!ctx || !out || !A || d < 1 || lda < d || d > (int64_t)1 << 30) return RBCG_ERR_INVALID_ARG;
+  if (lo != RBCG_F64 && lo != RBCG_F32) return RBCG_ERR_INVALID_ARG;
+  *out = nullptr;
+  rbcg_op* op = new rbcg_op();
+  op->kind = RBCG_OP_DENSE;
+  op->d = d;
+  op->data = A;
+  op->ld = lda;
+  op->lo_t = lo;
+  op->device = ctx->device;
+  if (lo == RBCG_F32) {
+    op->ld_lo = round_up(d, 64);
+    if (hipMalloc(&op->lo, (size_t)d * op->ld_lo * sizeof(float)) != hipSuccess) {
+      delete op;
+      return RBCG_ERR_OOM;
+    }
+    CvtDesc h{};
+    h.src = plain_rows(A, lda);
+    h.dst = plain_rows(op->lo, op->ld_lo);
+    h.rows = (int)d;
+    h.cols = (int)d;
+    h.src_t = DT_F64;
+    h.dst_t = DT_F32;
+    h.active = -1;
+    CvtDesc* dd = nullptr;
+    if (hipMalloc(&dd, sizeof(CvtDesc)) != hipSuccess) { (void)hipFree(op->lo); delete op; return RBCG_ERR_OOM; }
+    hipError_t e = hipMemcpy(dd, &h, sizeof h, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_convert(dd, 1, (int)d, (int)d, nullptr, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(dd);
+    if (e != hipSuccess) { (void)hipFree(op->lo); delete op; return fail_hip(e, "dense lo copy"); }
+  }
+  *out = op;
+  return RBCG_OK;
+}
+
+extern "C" int rbcg_op_create_gram(rbcg_ctx* ctx, rbcg_op** out, int64_t n, int64_t d, const float* Z, int64_t ldz,
+                                   int lo) {
+  if (!ctx || !out || !Z || d < 1 || n < 1 || ldz < d || n > (int64_t)1 << 31 || d > (int64_t)1 << 30)
+    return RBCG_ERR_INVALID_ARG;
+  if (lo != RBCG_F64 && lo != RBCG_BF16) return RBCG_ERR_INVALID_ARG;
+  *out = nullptr;
+  rbcg_op* op = new rbcg_op();
+  op->kind = RBCG_OP_GRAM;
+  op->d = d;
+  op->n = n;
+  op->data = Z;
+  op->ld = ldz;
+  op->lo_t = lo;
+  op->device = ctx->device;
+  if (lo == RBCG_BF16) {
+    op->ld_lo = round_up(d, 64);
+    op->ld_lot = round_up(n, 64);
+    if (hipMalloc(&op->lo, (size_t)n * op->ld_lo * 2) != hipSuccess) { delete op; return RBCG_ERR_OOM; }
+    if (hipMalloc(&op->lot, (size_t)d * op->ld_lot * 2) != hipSuccess) {
+      (void)hipFree(op->lo);
+      delete op;
+      return RBCG_ERR_OOM;
+    }
+    CvtDesc h{};
+    h.src = plain_rows(Z, ldz);
+    h.dst = plain_rows(op->lo, op->ld_lo);
+    h.rows = (int)n;
+    h.cols = (int)d;
+    h.src_t = DT_F32;
+    h.dst_t = DT_BF16;
+    h.active = -1;
+    CvtDesc* dd = nullptr;
+    hipError_t e = hipMalloc(&dd, sizeof(CvtDesc));
+    if (e == hipSuccess) e = hipMemcpy(dd, &h, sizeof h, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_convert(dd, 1, (int)n, (int)d, nullptr, ctx->stream);
+    if (e == hipSuccess)
+      e = launch_transpose_bf16(Z, ldz, (int)n, (int)d, (unsigned short*)op->lot, op->ld_lot, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (dd) (void)hipFree(dd);
+    if (e != hipSuccess) {
+      (void)hipFree(op->lo);
+      (void)hipFree(op->lot);
+      delete op;
+      return fail_hip(e, "gram lo copies");
+    }
+  }
+  *out = op;
+  return RBCG_OK;
+}
+
+extern "C" int rbcg_op_destroy(rbcg_op* op) {
+  if (!op) return RBCG_ERR_INVALID_ARG;
+  if (op->lo) (void)hipFree(op->lo);
+  if (op->lot) (void)hipFree(op->lot);
+  delete op;
+  return RBCG_OK;
+}
+
+// ------------------------------------------------------------------------------ arena
+struct Arena {
+  char* base = nullptr;   // null: measuring pass
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    const size_t bytes = (size_t)round_up((int64_t)(count * sizeof(T)), 256);
+    T* p = base ? (T*)(base + off) : (T*)(uintptr_t)(off + 256);
+    off += bytes;
+    return p;
+  }
+};
+
+// ------------------------------------------------------------------------ the engine
+struct Prob {
+  const rbcg_op* op = nullptr;
+  int d = 0, m = 0;
+  int64_t ldv = 0;
+  double* q = nullptr;     // row 0 of block 0 of this problem
+  int64_t bs = 0;          // element stride between basis blocks
+  int group = 0;           // block-product group
+  bool force_first = true; // column 0 of the start block is the right-hand side
+  double sigma_mon = 0.0;  // shift of the convergence monitor
+  int mon_col = 0;         // column of R0 the monitor follows
+  bool monitor = true;
+  // buffers
+  double *C1, *C2, *G, *M1, *M2, *Bc1, *D, *Bsub, *R0, *part, *Lw, *Xw, *Zw, *est, *scale, *ybuf;
+  int32_t *mask, *masktmp, *rank, *fail, *done_at;
+  size_t part_elems = 0;
+  RowOp rows(int64_t first_row = 0) const {
+    // basis rows starting at `first_row` (a multiple of m)
+    return RowOp{q + (first_row / m) * bs, ldv, bs, m, 0};
+  }
+  RowOp block(int j) const { return RowOp{q + (int64_t)j * bs, ldv, bs, m, 0}; }
+};
+
+struct MvGroup {
+  const rbcg_op* op = nullptr;
+  int first = 0, count = 0;  // problems [first, first + count), interleaved per block
+  int N = 0;                 // rows of one block of the group (count * m)
+  int64_t ldv = 0;
+  double* q = nullptr;       // block 0 row 0 of the group
+  int64_t bs = 0;
+  int mv_t = RBCG_F64;       // block-product precision
+  void* xlo = nullptr;       // low-precision copy of the current block
+  int64_t ld_xlo = 0;
+  void* ylo = nullptr;       // gram: BF16 pair copy of Z X (2N x ld_ylo)
+  int64_t ld_ylo = 0;
+  double* ys = nullptr;      // gram FP64: Z X (n x N)
+  double* part = nullptr;
+  size_t part_elems = 0;
+  int splits2 = 1;           // splits of the second gram pass (or of the dense product)
+};
+
+struct Engine {
+  std::vector<Prob> P;
+  std::vector<MvGroup> Gs;
+  int t_max = 1;
+  int maxm = 1;
+  double eta2 = 1e-20, tau = 1e-15;
+  int32_t* active = nullptr;    // device, per problem
+  int32_t* active_h = nullptr;  // pinned mirror
+};
+
+// splits for an NT product with `tiles` row tiles per problem, nz problems, reduction length K
+static int pick_splits(int tiles, int nz, int K) {
+  const int want = std::max(1, 1024 / std::max(1, tiles * nz));
+  const int cap = std::max(1, K / 256);
+  return std::max(1, std::min(want, std::min(cap, 256)));
+}
+
+// Descriptor staging: host copies, later uploaded in one transfer.
+struct Staging {
+  std::vector<unsigned char> host;
+  template <class T>
+  size_t add(const std::vector<T>& v) {
+    const size_t off = (size_t)round_up((int64_t)host.size(), 64);
+    host.resize(off + v.size() * sizeof(T));
+    if (!v.empty()) std::memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+};
+
+template <class T>
+static const T* dptr(unsigned char* dbase, size_t off) {
+  return (const T*)(dbase + off);
+}
+
+// One enqueued kernel launch of the step program.
+struct Launch {
+  enum Kind { NT, FIN, NN, QR, DIAG, TRIF, CONV, CVT, COPY } kind;
+  size_t off = 0;
+  int nz = 0;
+  int a0 = 0, a1 = 0, a2 = 0, a3 = 0;   // kind-specific sizes
+  bool flag = false;
+};
+
+static hipError_t enqueue(const Launch& L, unsigned char* dbase, const int32_t* act, hipStream_t st) {
+  switch (L.kind) {
+    case Launch::NT:
+      return launch_gemm_nt_ex(L.a0 & 0xff, (L.a0 >> 8) & 1, L.flag, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a2,
+                               L.a3, act, st);
+    case Launch::FIN: return launch_finish(dptr<FinDesc>(dbase, L.off), L.nz, L.a1, L.a2, act, st);
+    case Launch::NN: return launch_gemm_nn_ex(L.flag, dptr<NnDesc>(dbase, L.off), L.nz, L.a1, L.a2, act, st);
+    case Launch::QR: return launch_qr_factor(dptr<QrDesc>(dbase, L.off), L.nz, L.a1, act, st);
+    case Launch::DIAG: return launch_diag(dptr<DiagDesc>(dbase, L.off), L.nz, L.a1, act, st);
+    case Launch::TRIF:
+      return launch_tri_forward(dptr<TriDesc>(dbase, L.off), L.nz, L.a1, L.a2, L.a3, L.a3 + 1, act, st);
+    case Launch::CONV: return launch_converge(dptr<ConvDesc>(dbase, L.off), L.nz, st);
+    case Launch::CVT: return launch_convert(dptr<CvtDesc>(dbase, L.off), L.nz, L.a1, L.a2, act, st);
+    case Launch::COPY: return launch_copy(dptr<CopyDesc>(dbase, L.off), L.nz, L.a1, L.a2, act, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Builder of the per-step kernel program.
+struct Program {
+  Staging stg;
+  std::vector<std::vector<Launch>> steps;   // steps[0] = start block, steps[j+1] = Lanczos step j
+  std::vector<Launch> mon;                  // per step j: monitor launches (appended in steps)
+};
+
+// Build NT descriptors "rows [0, M) of basis p against block rows X" for all problems.
+static void add_proj(Program& pg, std::vector<Launch>& out, Engine& E, int j, bool with_w, double** Cdst) {
+  std::vector<NtDesc> nt;
+  std::vector<FinDesc> fin;
+  int maxM = 0, maxN = 0, tiles = 0;
+  for (size_t p = 0; p < E.P.size(); ++p) {
+    const Prob& pr = E.P[p];
+    const int M = (j + 1 + (with_w ? 1 : 0)) * pr.m;
+    maxM = std::max(maxM, M);
+    maxN = std::max(maxN, pr.m);
+  }
+  tiles = (maxM + 15) / 16;
+  int K = 0;
+  for (auto& pr : E.P) K = std::max(K, pr.d);
+  const int splits = pick_splits(tiles, (int)E.P.size(), K);
+  for (size_t p = 0; p < E.P.size(); ++p) {
+    const Prob& pr = E.P[p];
+    NtDesc d{};
+    d.P = pr.rows(0);
+    d.X = pr.block(j + 1);
+    d.M = (j + 1 + (with_w ? 1 : 0)) * pr.m;
+    d.N = pr.m;
+    d.K = pr.d;
+    d.active = (int)p;
+    d.part = pr.part;
+    d.out = Cdst[p];
+    d.ldo = pr.m;
+    nt.push_back(d);
+    FinDesc f{};
+    f.part = pr.part;
+    f.M = d.M;
+    f.N = d.N;
+    f.splits = splits;
+    f.mode = FIN_ROWMAJOR;
+    f.out = Cdst[p];
+    f.ldo = pr.m;
+    f.alpha = 1.0;
+    f.active = (int)p;
+    fin.push_back(f);
+  }
+  Launch L{Launch::NT};
+  L.off = pg.stg.add(nt);
+  L.nz = (int)nt.size();
+  L.a0 = DT_F64;
+  L.a1 = maxM;
+  L.a2 = maxN;
+  L.a3 = splits;
+  out.push_back(L);
+  if (splits > 1) {
+    Launch F{Launch::FIN};
+    F.off = pg.stg.add(fin);
+    F.nz = (int)fin.size();
+    F.a1 = maxM;
+    F.a2 = maxN;
+    out.push_back(F);
+  }
+}
+
+// W -= Q_{0..j} C  (rows [0, (j+1)m) of the basis)
+static void add_update(Program& pg, std::vector<Launch>& out, Engine& E, int j, double** C) {
+  std::vector<NnDesc> nn;
+  int maxMo = 0, maxN = 0;
+  for (size_t p = 0; p < E.P.size(); ++p) {
+    const Prob& pr = E.P[p];
+    NnDesc d{};
+    d.P = pr.rows(0);
+    d.C = C[p];
+    d.ldc = pr.m;
+    d.Y = pr.block(j + 1);
+    d.O = pr.block(j + 1);
+    d.alpha = -1.0;
+    d.beta = 1.0;
+    d.Ka = (j + 1) * pr.m;
+    d.Mo = pr.m;
+    d.N = pr.d;
+    d.active = (int)p;
+    nn.push_back(d);
+    maxMo = std::max(maxMo, pr.m);
+    maxN = std::max(maxN, pr.d);
+  }
+  Launch L{Launch::NN};
+  L.off = pg.stg.add(nn);
+  L.nz = (int)nn.size();
+  L.a1 = maxMo;
+  L.a2 = maxN;
+  out.push_back(L);
+}
+
+// G = W^T W for the W in block slot `slot`
+static void add_gram(Program& pg, std::vector<Launch>& out, Engine& E, int slot) {
+  std::vector<NtDesc> nt;
+  std::vector<FinDesc> fin;
+  int maxm = 0, K = 0;
+  for (auto& pr : E.P) { maxm = std::max(maxm, pr.m); K = std::max(K, pr.d); }
+  const int splits = pick_splits((maxm + 15) / 16, (int)E.P.size(), K);
+  for (size_t p = 0; p < E.P.size(); ++p) {
+    const Prob& pr = E.P[p];
+    NtDesc d{};
+    d.P = pr.block(slot);
+    d.X = pr.block(slot);
+    d.M = pr.m;
+    d.N = pr.m;
+    d.K = pr.d;
+    d.active = (int)p;
+    d.part = pr.part;
+    d.out = pr.G;
+    d.ldo = pr.m;
+    nt.push_back(d);
+    FinDesc f{};
+    f.part = pr.part;
+    f.M = pr.m;
+    f.N = pr.m;
+    f.splits = splits;
+    f.mode = FIN_ROWMAJOR;
+    f.out = pr.G;
+    f.ldo = pr.m;
+    f.alpha = 1.0;
+    f.active = (int)p;
+    fin.push_back(f);
+  }
+  Launch L{Launch::NT};
+  L.off = pg.stg.add(nt);
+  L.nz = (int)nt.size();
+  L.a0 = DT_F64;
+  L.a1 = maxm;
+  L.a2 = maxm;
+  L.a3 = splits;
+  out.push_back(L);
+  if (splits > 1) {
+    Launch F{Launch::FIN};
+    F.off = pg.stg.add(fin);
+    F.nz = (int)fin.size();
+    F.a1 = maxm;
+    F.a2 = maxm;
+    out.push_back(F);
+  }
+}
+
+// W <- W * M (in place) for block slot `slot`
+static void add_rmul(Program& pg, std::vector<Launch>& out, Engine& E, int slot, bool second) {
+  std::vector<NnDesc> nn;
+  int maxm = 0, maxN = 0;
+  for (size_t p = 0; p < E.P.size(); ++p) {
+    const Prob& pr = E.P[p];
+    NnDesc d{};
+    d.P = pr.block(slot);
+    d.C = second ? pr.M2 : pr.M1;
+    d.ldc = pr.m;
+    d.Y = pr.block(slot);
+    d.O = pr.block(slot);
+    d.alpha = 1.0;
+    d.beta = 0.0;
+    d.Ka = pr.m;
+    d.Mo = pr.m;
+    d.N = pr.d;
+    d.active = (int)p;
+    nn.push_back(d);
+    maxm = std::max(maxm, pr.m);
+    maxN = std::max(maxN, pr.d);
+  }
+  Launch L{Launch::NN};
+  L.off = pg.stg.add(nn);
+  L.nz = (int)nn.size();
+  L.a1 = maxm;
+  L.a2 = maxN;
+  out.push_back(L);
+}
+
+// Two rounds of pivoted Cholesky QR of block slot `slot`; the second writes the basis mask of
+// that slot and the coefficient block (R0 for the start block, B_j afterwards).
+static void add_cholqr(Program& pg, std::vector<Launch>& out, Engine& E, int slot, const double* const* pre,
+                       double** coef, bool start) {
+  add_gram(pg, out, E, slot);
+  {
+    std::vector<QrDesc> qr;
+    for (size_t p = 0; p < E.P.size(); ++p) {
+      const Prob& pr = E.P[p];
+      QrDesc d{};
+      d.G = pr.G;
+      d.ldg = pr.m;
+      d.pre = pre ? pre[p] : nullptr;
+      d.pre_stride = pr.m + 1;
+      d.Mout = pr.M1;
+      d.Bout = pr.Bc1;
+      d.prevB = nullptr;
+      d.mask = pr.masktmp;
+      d.rank_out = nullptr;
+      d.m = pr.m;
+      d.pivot = 1;
+      d.force_first = (start && pr.force_first) ? 1 : 0;
+      d.active = (int)p;
+      d.eta2 = E.eta2;
+      d.tau = E.tau;
+      qr.push_back(d);
+    }
+    Launch L{Launch::QR};
+    L.off = pg.stg.add(qr);
+    L.nz = (int)qr.size();
+    L.a1 = E.maxm;
+    out.push_back(L);
+  }
+  add_rmul(pg, out, E, slot, false);
+  add_gram(pg, out, E, slot);
+  {
+    std::vector<QrDesc> qr;
+    for (size_t p = 0; p < E.P.size(); ++p) {
+      const Prob& pr = E.P[p];
+      QrDesc d{};
+      d.G = pr.G;
+      d.ldg = pr.m;
+      d.pre = nullptr;
+      d.pre_stride = 0;
+      d.Mout = pr.M2;
+      d.Bout = coef[p];
+      d.prevB = pr.Bc1;
+      d.mask = pr.mask + (int64_t)slot * pr.m;
+      d.rank_out = pr.rank;
+      d.m = pr.m;
+      d.pivot = 0;
+      d.force_first = 0;
+      d.active = (int)p;
+      d.eta2 = 0.0;
+      d.tau = 1e-2;   // second pass: columns are near orthonormal; a large loss means dependence
+      qr.push_back(d);
+    }
+    Launch L{Launch::QR};
+    L.off = pg.stg.add(qr);
+    L.nz = (int)qr.size();
+    L.a1 = E.maxm;
+    out.push_back(L);
+  }
+  add_rmul(pg, out, E, slot, true);
+}
+
+// The block product W = A Q_j into block slot j+1 for every group.
+static void add_matvec(Program& pg, std::vector<Launch>& out, Engine& E, int j) {
+  for (size_t g = 0; g < E.Gs.size(); ++g) {
+    MvGroup& G = E.Gs[g];
+    const rbcg_op* op = G.op;
+    const int act_idx = G.count == 1 ? G.first : -1;
+    const RowOp Xb{G.q + (int64_t)j * G.bs, G.ldv, 0, 0x3fffffff, 0};
+    const RowOp Wb{G.q + (int64_t)(j + 1) * G.bs, G.ldv, 0, 0x3fffffff, 0};
+    const int d = (int)op->d;
+    if (op->kind == RBCG_OP_DENSE) {
+      NtDesc nd{};
+      nd.M = d;
+      nd.N = G.N;
+      nd.K = d;
+      nd.active = act_idx;
+      nd.part = G.part;
+      nd.O = Wb;
+      nd.out = nullptr;
+      nd.out_t = DT_F64;
+      int dtype = DT_F64;
+      if (G.mv_t == RBCG_F32) {
+        CvtDesc c{};
+        c.src = Xb;
+        c.dst = plain_rows(G.xlo, G.ld_xlo);
+        c.rows = G.N;
+        c.cols = d;
+        c.src_t = DT_F64;
+        c.dst_t = DT_F32;
+        c.active = act_idx;
+        Launch C{Launch::CVT};
+        C.off = pg.stg.add(std::vector<CvtDesc>{c});
+        C.nz = 1;
+        C.a1 = G.N;
+        C.a2 = d;
+        out.push_back(C);
+        nd.P = plain_rows(op->lo, op->ld_lo);
+        nd.X = plain_rows(G.xlo, G.ld_xlo);
+        dtype = DT_F32;
+      } else {
+        nd.P = plain_rows(op->data, op->ld);
+        nd.X = Xb;
+      }
+      const int splits = G.splits2;
+      Launch L{Launch::NT};
+      L.off = pg.stg.add(std::vector<NtDesc>{nd});
+      L.nz = 1;
+      L.a0 = dtype | (1 << 8);
+      L.a1 = d;
+      L.a2 = G.N;
+      L.a3 = splits;
+      out.push_back(L);
+      if (splits > 1) {
+        FinDesc f{};
+        f.part = G.part;
+        f.M = d;
+        f.N = G.N;
+        f.splits = splits;
+        f.mode = FIN_TRANS;
+        f.O = Wb;
+        f.alpha = 1.0;
+        f.active = act_idx;
+        Launch F{Launch::FIN};
+        F.off = pg.stg.add(std::vector<FinDesc>{f});
+        F.nz = 1;
+        F.a1 = d;
+        F.a2 = G.N;
+        out.push_back(F);
+      }
+    } else {
+      const int n = (int)op->n;
+      if (G.mv_t == RBCG_BF16) {
+        // X -> BF16 hi/lo pairs; Y^T = (Z X)^T as BF16 pairs; W = Z^T Y
+        CvtDesc c{};
+        c.src = Xb;
+        c.dst = plain_rows(G.xlo, G.ld_xlo);
+        c.rows = G.N;
+        c.cols = d;
+        c.src_t = DT_F64;
+        c.dst_t = DT_BF16;
+        c.split_lo = 1;
+        c.active = act_idx;
+        Launch C{Launch::CVT};
+        C.off = pg.stg.add(std::vector<CvtDesc>{c});
+        C.nz = 1;
+        C.a1 = G.N;
+        C.a2 = d;
+        out.push_back(C);
+        NtDesc n1{};
+        n1.P = plain_rows(op->lo, op->ld_lo);
+        n1.X = plain_rows(G.xlo, G.ld_xlo);
+        n1.M = n;
+        n1.N = G.N;
+        n1.K = d;
+        n1.active = act_idx;
+        n1.O = plain_rows(G.ylo, G.ld_ylo);
+        n1.out_t = 3;
+        Launch L1{Launch::NT};
+        L1.off = pg.stg.add(std::vector<NtDesc>{n1});
+        L1.nz = 1;
+        L1.a0 = DT_BF16 | (1 << 8);
+        L1.flag = true;
+        L1.a1 = n;
+        L1.a2 = G.N;
+        L1.a3 = 1;
+        out.push_back(L1);
+        NtDesc n2{};
+        n2.P = plain_rows(op->lot, op->ld_lot);
+        n2.X = plain_rows(G.ylo, G.ld_ylo);
+        n2.M = d;
+        n2.N = G.N;
+        n2.K = n;
+        n2.active = act_idx;
+        n2.part = G.part;
+        n2.O = Wb;
+        n2.out_t = DT_F64;
+        const int splits = G.splits2;
+        Launch L2{Launch::NT};
+        L2.off = pg.stg.add(std::vector<NtDesc>{n2});
+        L2.nz = 1;
+        L2.a0 = DT_BF16 | (1 << 8);
+        L2.flag = true;
+        L2.a1 = d;
+        L2.a2 = G.N;
+        L2.a3 = splits;
+        out.push_back(L2);
+        if (splits > 1) {
+          FinDesc f{};
+          f.part = G.part;
+          f.M = d;
+          f.N = G.N;
+          f.splits = splits;
+          f.mode = FIN_TRANS;
+          f.O = Wb;
+          f.alpha = 1.0;
+          f.active = act_idx;
+          Launch F{Launch::FIN};
+          F.off = pg.stg.add(std::vector<FinDesc>{f});
+          F.nz = 1;
+          F.a1 = d;
+          F.a2 = G.N;
+          out.push_back(F);
+        }
+      } else {
+        // FP64 arithmetic on the FP32 values of Z: ys = Z X (n x N row-major), W = Z^T ys
+        NtDesc n1{};
+        n1.P = plain_rows(op->data, op->ld);
+        n1.X = Xb;
+        n1.M = n;
+        n1.N = G.N;
+        n1.K = d;
+        n1.active = act_idx;
+        n1.out = G.ys;
+        n1.ldo = G.N;
+        Launch L1{Launch::NT};
+        L1.off = pg.stg.add(std::vector<NtDesc>{n1});
+        L1.nz = 1;
+        L1.a0 = 3;   // FP32 P, FP64 arithmetic
+        L1.a1 = n;
+        L1.a2 = G.N;
+        L1.a3 = 1;
+        out.push_back(L1);
+        NnDesc nn{};
+        nn.P = plain_rows(op->data, op->ld);
+        nn.C = G.ys;
+        nn.ldc = G.N;
+        nn.Y = Wb;
+        nn.O = Wb;
+        nn.alpha = 1.0;
+        nn.beta = 0.0;
+        nn.Ka = n;
+        nn.Mo = G.N;
+        nn.N = d;
+        nn.active = act_idx;
+        Launch L2{Launch::NN};
+        L2.off = pg.stg.add(std::vector<NnDesc>{nn});
+        L2.nz = 1;
+        L2.flag = true;
+        L2.a1 = G.N;
+        L2.a2 = d;
+        out.push_back(L2);
+      }
+    }
+  }
+}
+
+// Monitor: one block of the shifted block-Cholesky of T + sigma I and the residual estimate,
+// then the device-side convergence test.
+static void add_monitor(Program& pg, std::vector<Launch>& out, Engine& E, int j, const std::vector<double>& tol) {
+  std::vector<TriDesc> td;
+  std::vector<ConvDesc> cd;
+  for (size_t p = 0; p < E.P.size(); ++p) {
+    const Prob& pr = E.P[p];
+    TriDesc d{};
+    d.D = pr.D;
+    d.Bsub = pr.Bsub;
+    d.mask = pr.mask;
+    d.rhs = pr.R0 + pr.mon_col;
+    d.ld_rhs = pr.m;
+    d.Lw = pr.Lw;
+    d.Xw = pr.Xw;
+    d.Zw = pr.Zw;
+    d.Y = pr.ybuf;
+    d.ldy = 1;
+    d.est = pr.est;
+    d.fail = pr.fail;
+    d.sigma = pr.sigma_mon;
+    d.m = pr.m;
+    d.r = 1;
+    d.active = pr.monitor ? (int)p : -2;
+    td.push_back(d);
+    ConvDesc c{};
+    c.est = pr.est + j;
+    c.scale = pr.scale;
+    c.tol = tol[p];
+    c.active_flag = E.active + p;
+    c.done_at = pr.done_at;
+    c.step = j;
+    cd.push_back(c);
+  }
+  Launch L{Launch::TRIF};
+  L.off = pg.stg.add(td);
+  L.nz = (int)td.size();
+  L.a1 = E.maxm;
+  L.a2 = 1;
+  L.a3 = j;
+  out.push_back(L);
+  Launch C{Launch::CONV};
+  C.off = pg.stg.add(cd);
+  C.nz = (int)cd.size();
+  out.push_back(C);
+}
+
+static void build_program(Program& pg, Engine& E, const std::vector<double>& tol, bool monitor,
+                          std::vector<CopyDesc>& start_copies, int max_start_rows) {
+  pg.steps.assign(E.t_max + 1, {});
+  // start block: caller-provided copies into block 0, then Cholesky QR (R0 = coefficients)
+  {
+    auto& out = pg.steps[0];
+    Launch L{Launch::COPY};
+    L.off = pg.stg.add(start_copies);
+    L.nz = (int)start_copies.size();
+    int maxN = 0;
+    for (auto& pr : E.P) maxN = std::max(maxN, pr.d);
+    L.a1 = max_start_rows;
+    L.a2 = maxN;
+    out.push_back(L);
+    std::vector<double*> coef(E.P.size());
+    for (size_t p = 0; p < E.P.size(); ++p) coef[p] = E.P[p].R0;
+    add_cholqr(pg, out, E, 0, nullptr, coef.data(), true);
+  }
+  for (int j = 0; j < E.t_max; ++j) {
+    auto& out = pg.steps[j + 1];
+    add_matvec(pg, out, E, j);
+    std::vector<double*> c1(E.P.size()), c2(E.P.size()), coef(E.P.size());
+    std::vector<const double*> pre(E.P.size());
+    for (size_t p = 0; p < E.P.size(); ++p) {
+      c1[p] = E.P[p].C1;
+      c2[p] = E.P[p].C2;
+      coef[p] = E.P[p].Bsub + (int64_t)j * E.P[p].m * E.P[p].m;
+      pre[p] = E.P[p].C1 + (int64_t)(j + 1) * E.P[p].m * E.P[p].m;
+    }
+    add_proj(pg, out, E, j, true, c1.data());
+    add_update(pg, out, E, j, c1.data());
+    add_proj(pg, out, E, j, false, c2.data());
+    add_update(pg, out, E, j, c2.data());
+    {
+      std::vector<DiagDesc> dd;
+      for (size_t p = 0; p < E.P.size(); ++p) {
+        const Prob& pr = E.P[p];
+        DiagDesc d{};
+        d.C1 = pr.C1 + (int64_t)j * pr.m * pr.m;
+        d.C2 = pr.C2 + (int64_t)j * pr.m * pr.m;
+        d.ldc = pr.m;
+        d.D = pr.D + (int64_t)j * pr.m * pr.m;
+        d.mask = pr.mask + (int64_t)j * pr.m;
+        d.m = pr.m;
+        d.has_c2 = 1;
+        d.active = (int)p;
+        dd.push_back(d);
+      }
+      Launch L{Launch::DIAG};
+      L.off = pg.stg.add(dd);
+      L.nz = (int)dd.size();
+      L.a1 = E.maxm;
+      out.push_back(L);
+    }
+    add_cholqr(pg, out, E, j + 1, pre.data(), coef.data(), false);
+    if (monitor) add_monitor(pg, out, E, j, tol);
+  }
+}
+
+// Partial-buffer sizes of the per-problem products (max over all steps) and of the groups.
+static void size_partials(Engine& E) {
+  int K = 0;
+  for (auto& pr : E.P) K = std::max(K, pr.d);
+  const int nz = (int)E.P.size();
+  size_t need = 0;
+  for (int j = 0; j < E.t_max; ++j) {
+    int maxM = 0;
+    for (auto& pr : E.P) maxM = std::max(maxM, (j + 2) * pr.m);
+    const int s = pick_splits((maxM + 15) / 16, nz, K);
+    if (s > 1) need = std::max(need, (size_t)s * maxM * E.maxm);
+  }
+  const int sg = pick_splits((E.maxm + 15) / 16, nz, K);
+  if (sg > 1) need = std::max(need, (size_t)sg * E.maxm * E.maxm);
+  for (auto& pr : E.P) pr.part_elems = need;
+  for (auto& G : E.Gs) {
+    const int d = (int)G.op->d;
+    int tiles = (d + 15) / 16;
+    int Kp = (G.op->kind == RBCG_OP_GRAM && G.mv_t == RBCG_BF16) ? (int)G.op->n : d;
+    if (G.op->kind == RBCG_OP_GRAM && G.mv_t != RBCG_BF16) {
+      G.splits2 = 1;
+    } else {
+      G.splits2 = pick_splits(tiles, 1, Kp);
+    }
+    G.part_elems = G.splits2 > 1 ? (size_t)G.splits2 * d * G.N : 0;
+  }
+}
+
+// Carve all per-problem and per-group buffers. `extra` adds caller-specific buffers later.
+static void carve(Arena& ar, Engine& E) {
+  for (auto& G : E.Gs) {
+    const int64_t ldv = G.ldv;
+    G.q = ar.take<double>((size_t)(E.t_max + 1) * G.N * ldv);
+    G.bs = (int64_t)G.N * ldv;
+    if (G.mv_t == RBCG_F32) {
+      G.ld_xlo = ldv;
+      G.xlo = ar.take<float>((size_t)G.N * ldv);
+    } else if (G.mv_t == RBCG_BF16) {
+      G.ld_xlo = ldv;
+      G.xlo = ar.take<unsigned short>((size_t)2 * G.N * ldv);
+      G.ld_ylo = round_up(G.op->n, 64);
+      G.ylo = ar.take<unsigned short>((size_t)2 * G.N * G.ld_ylo);
+    } else if (G.op->kind == RBCG_OP_GRAM) {
+      G.ys = ar.take<double>((size_t)G.op->n * G.N);
+    }
+    G.part = G.part_elems ? ar.take<double>(G.part_elems) : nullptr;
+    for (int i = 0; i < G.count; ++i) {
+      Prob& pr = E.P[G.first + i];
+      pr.q = G.q + (int64_t)i * pr.m * ldv;
+      pr.bs = G.bs;
+    }
+  }
+  for (auto& pr : E.P) {
+    const size_t mm = (size_t)pr.m * pr.m;
+    const size_t T = (size_t)E.t_max;
+    pr.C1 = ar.take<double>((T + 1) * mm);
+    pr.C2 = ar.take<double>((T + 1) * mm);
+    pr.G = ar.take<double>(mm);
+    pr.M1 = ar.take<double>(mm);
+    pr.M2 = ar.take<double>(mm);
+    pr.Bc1 = ar.take<double>(mm);
+    pr.D = ar.take<double>(T * mm);
+    pr.Bsub = ar.take<double>(T * mm);
+    pr.R0 = ar.take<double>(mm);
+    pr.part = pr.part_elems ? ar.take<double>(pr.part_elems) : nullptr;
+    pr.Lw = ar.take<double>(T * mm);
+    pr.Xw = ar.take<double>(T * mm);
+    pr.Zw = ar.take<double>(T * pr.m);
+    pr.est = ar.take<double>(T);
+    pr.scale = ar.take<double>(1);
+    pr.ybuf = ar.take<double>(T * pr.m);
+    pr.mask = ar.take<int32_t>((T + 1) * pr.m);
+    pr.masktmp = ar.take<int32_t>(pr.m);
+    pr.rank = ar.take<int32_t>(1);
+    pr.fail = ar.take<int32_t>(1);
+    pr.done_at = ar.take<int32_t>(1);
+  }
+  E.active = ar.take<int32_t>(E.P.size());
+}
+
+static int ensure_ws(rbcg_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->ws_cap) return RBCG_OK;
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  ctx->ws = nullptr;
+  ctx->ws_cap = 0;
+  if (hipMalloc(&ctx->ws, bytes) != hipSuccess) return RBCG_ERR_OOM;
+  ctx->ws_cap = bytes;
+  return RBCG_OK;
+}
+
+static int ensure_pinned(rbcg_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->pinned_cap) return RBCG_OK;
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  ctx->pinned = nullptr;
+  ctx->pinned_cap = 0;
+  if (hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault) != hipSuccess) return RBCG_ERR_OOM;
+  ctx->pinned_cap = bytes;
+  return RBCG_OK;
+}
+
+// Upload the staged descriptors into `dst` (device) synchronously on the stream.
+static int upload(rbcg_ctx* ctx, const Staging& stg, unsigned char* dst) {
+  if (stg.host.empty()) return RBCG_OK;
+  HIP_TRY(hipMemcpyAsync(dst, stg.host.data(), stg.host.size(), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return RBCG_OK;
+}
+
+// Run the start block and up to t_max Lanczos steps; stops early once every problem's monitor
+// has converged.  Returns the number of steps enqueued.
+static int run_steps(rbcg_ctx* ctx, Engine& E, Program& pg, unsigned char* dbase, int* steps_run) {
+  hipStream_t st = ctx->stream;
+  const int np = (int)E.P.size();
+  for (const auto& L : pg.steps[0]) HIP_TRY(enqueue(L, dbase, E.active, st));
+  int32_t* flags_h = E.active_h;
+  int j = 0;
+  for (; j < E.t_max; ++j) {
+    for (const auto& L : pg.steps[j + 1]) HIP_TRY(enqueue(L, dbase, E.active, st));
+    // read the flags of this step asynchronously; decide on the previous step's copy
+    int32_t* dst = flags_h + (j & 1) * np;
+    HIP_TRY(hipMemcpyAsync(dst, E.active, np * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(ctx->ev[j & 1], st));
+    if (j >= 1) {
+      HIP_TRY(hipEventSynchronize(ctx->ev[(j - 1) & 1]));
+      const int32_t* prev = flags_h + ((j - 1) & 1) * np;
+      bool any = false;
+      for (int p = 0; p < np; ++p) any |= prev[p] != 0;
+      if (!any) { ++j; break; }
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  *steps_run = j;
+  return RBCG_OK;
+}
+
+// --------------------------------------------------------------------------- helpers
+static int set_active_all(rbcg_ctx* ctx, Engine& E, const std::vector<int32_t>& vals) {
+  std::memcpy(E.active_h, vals.data(), vals.size() * sizeof(int32_t));
+  HIP_TRY(hipMemcpyAsync(E.active, E.active_h, vals.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return RBCG_OK;
+}
+
+// Squared norms of `rows` rows (device results copied to host `out`).
+struct Scratch {
+  double* sq = nullptr;
+  unsigned char* desc = nullptr;
+  size_t desc_bytes = 0;
+};
+
+static int run_one(rbcg_ctx* ctx, const Launch& L, const Staging& stg, unsigned char* dscratch) {
+  int rc = upload(ctx, stg, dscratch);
+  if (rc) return rc;
+  HIP_TRY(enqueue(L, dscratch, nullptr, ctx->stream));
+  return RBCG_OK;
+}
+
+// FP64 residuals R[c] = rhs[c] - A_mu[c] X[c] for `rows` rows sharing operator op.
+// Uses: part (>= splits * rows * d doubles), ys (gram: n * rows doubles), dscratch for descriptors.
+struct ResidPlan {
+  size_t part_elems = 0, ys_elems = 0;
+  int splits = 1;
+};
+
+static ResidPlan plan_resid(const rbcg_op* op, int rows) {
+  ResidPlan rp;
+  const int d = (int)op->d;
+  if (op->kind == RBCG_OP_DENSE) {
+    rp.splits = pick_splits((d + 15) / 16, 1, d);
+    rp.part_elems = (size_t)rp.splits * rows * d;
+  } else {
+    rp.splits = 0;
+    rp.part_elems = 0;
+    rp.ys_elems = (size_t)op->n * rows;
+  }
+  return rp;
+}
+
+static int residual(rbcg_ctx* ctx, const rbcg_op* op, int rows, RowOp rhs, RowOp X, RowOp R, const double* mu_dev,
+                    const ResidPlan& rp, double* part, double* ys, unsigned char* dscratch) {
+  const int d = (int)op->d;
+  hipStream_t st = ctx->stream;
+  Staging stg;
+  if (op->kind == RBCG_OP_DENSE) {
+    NtDesc nd{};
+    nd.P = plain_rows(op->data, op->ld);
+    nd.X = X;
+    nd.M = d;
+    nd.N = rows;
+    nd.K = d;
+    nd.active = -1;
+    nd.part = part;
+    FinDesc f{};
+    f.part = part;
+    f.M = d;
+    f.N = rows;
+    f.splits = rp.splits;
+    f.mode = FIN_RESID;
+    f.O = R;
+    f.rhs = rhs;
+    f.xin = X;
+    f.mu = mu_dev;
+    f.alpha = 1.0;
+    f.active = -1;
+    // force the partial path: direct stores have no residual epilogue
+    const size_t o1 = stg.add(std::vector<NtDesc>{nd});
+    const size_t o2 = stg.add(std::vector<FinDesc>{f});
+    int rc = upload(ctx, stg, dscratch);
+    if (rc) return rc;
+    if (rp.splits == 1) {
+      // a single split still writes partials when splits == 1 is bypassed: use 2 splits minimum
+      return RBCG_ERR_HIP;
+    }
+    HIP_TRY(launch_gemm_nt_ex(DT_F64, 1, false, dptr<NtDesc>(dscratch, o1), 1, d, rows, rp.splits, nullptr, st));
+    HIP_TRY(launch_finish(dptr<FinDesc>(dscratch, o2), 1, d, rows, nullptr, st));
+    return RBCG_OK;
+  }
+  // gram: ys = Z X (n x rows), R = rhs - mu X, R -= Z^T ys
+  const int n = (int)op->n;
+  NtDesc n1{};
+  n1.P = plain_rows(op->data, op->ld);
+  n1.X = X;
+  n1.M = n;
+  n1.N = rows;
+  n1.K = d;
+  n1.active = -1;
+  n1.out = ys;
+  n1.ldo = rows;
+  FinDesc f{};
+  f.part = nullptr;
+  f.M = d;
+  f.N = rows;
+  f.splits = 0;
+  f.mode = FIN_RESID;
+  f.O = R;
+  f.rhs = rhs;
+  f.xin = X;
+  f.mu = mu_dev;
+  f.alpha = 1.0;
+  f.active = -1;
+  NnDesc nn{};
+  nn.P = plain_rows(op->data, op->ld);
+  nn.C = ys;
+  nn.ldc = rows;
+  nn.Y = R;
+  nn.O = R;
+  nn.alpha = -1.0;
+  nn.beta = 1.0;
+  nn.Ka = n;
+  nn.Mo = rows;
+  nn.N = d;
+  nn.active = -1;
+  const size_t o1 = stg.add(std::vector<NtDesc>{n1});
+  const size_t o2 = stg.add(std::vector<FinDesc>{f});
+  const size_t o3 = stg.add(std::vector<NnDesc>{nn});
+  int rc = upload(ctx, stg, dscratch);
+  if (rc) return rc;
+  HIP_TRY(launch_gemm_nt_ex(3, 0, false, dptr<NtDesc>(dscratch, o1), 1, n, rows, 1, nullptr, st));
+  HIP_TRY(launch_finish(dptr<FinDesc>(dscratch, o2), 1, d, rows, nullptr, st));
+  HIP_TRY(launch_gemm_nn_ex(true, dptr<NnDesc>(dscratch, o3), 1, rows, d, nullptr, st));
+  return RBCG_OK;
+}
+
+static int sqnorms(rbcg_ctx* ctx, RowOp x, int rows, int n, double* dout, double* hout, unsigned char* dscratch) {
+  Staging stg;
+  NormDesc nd{};
+  nd.x = x;
+  nd.out = dout;
+  nd.rows = rows;
+  nd.n = n;
+  nd.active = -1;
+  const size_t o = stg.add(std::vector<NormDesc>{nd});
+  int rc = upload(ctx, stg, dscratch);
+  if (rc) return rc;
+  HIP_TRY(launch_sqnorms(dptr<NormDesc>(dscratch, o), 1, rows, nullptr, ctx->stream));
+  HIP_TRY(hipMemcpyAsync(hout, dout, rows * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return RBCG_OK;
+}
+
+static bool valid_opts(const rbcg_opts* o) {
+  if (!o) return false;
+  if (o->t_max < 1 || o->t_max > 4096) return false;
+  if (!(o->rtol >= 0.0) || !std::isfinite(o->rtol)) return false;
+  if (o->matvec != RBCG_F64 && o->matvec != RBCG_F32 && o->matvec != RBCG_BF16) return false;
+  if (o->rtol > 0.0 && o->refine_max < 1) return false;
+  if (o->nquad < 0 || o->group < 0 || !(o->eta >= 0.0)) return false;
+  return true;
+}
+
+static bool op_supports(const rbcg_op* op, int mv) {
+  if (mv == RBCG_F64) return true;
+  if (op->kind == RBCG_OP_DENSE) return mv == RBCG_F32 && op->lo_t == RBCG_F32 && op->lo;
+  return mv == RBCG_BF16 && op->lo_t == RBCG_BF16 && op->lo && op->lot;
+}
+
+// ------------------------------------------------------------------------------ solve
+extern "C" int rbcg_solve(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, const double* mu,
+                          const double* const* b, const double* const* omega, const int32_t* k, double* const* x,
+                          const rbcg_opts* opts, rbcg_info* info) {
+  if (!ctx || nsys < 1 || nsys > 65535 || !ops || !mu || !b || !k || !x || !opts || !info) return RBCG_ERR_INVALID_ARG;
+  for (int64_t s = 0; s < nsys; ++s) {
+    const rbcg_op* op = ops[s];
+    if (!op || !b[s] || !x[s] || !valid_opts(&opts[s])) return RBCG_ERR_INVALID_ARG;
+    if (!(mu[s] >= 0.0) || !std::isfinite(mu[s])) return RBCG_ERR_INVALID_ARG;
+    if (k[s] < 0 || k[s] >= op->d || k[s] + 1 > kMaxBlock) return RBCG_ERR_INVALID_ARG;
+    if (k[s] > 0 && (!omega || !omega[s])) return RBCG_ERR_INVALID_ARG;
+    if (!op_supports(op, opts[s].matvec)) return RBCG_ERR_UNSUPPORTED;
+    if (op->device != ctx->device) return RBCG_ERR_INVALID_ARG;
+    if (tri_forward_lds(k[s] + 1, 1) > kLdsCap) return RBCG_ERR_INVALID_ARG;
+  }
+  hipStream_t st = ctx->stream;
+  Engine E;
+  E.t_max = 1;
+  for (int64_t s = 0; s < nsys; ++s) E.t_max = std::max(E.t_max, (int)opts[s].t_max);
+  E.eta2 = opts[0].eta > 0 ? opts[0].eta * opts[0].eta : 1e-20;
+  E.P.resize(nsys);
+  E.Gs.resize(nsys);
+  for (int64_t s = 0; s < nsys; ++s) {
+    Prob& pr = E.P[s];
+    pr.op = ops[s];
+    pr.d = (int)ops[s]->d;
+    pr.m = k[s] + 1;
+    pr.ldv = round_up(pr.d, 64);
+    pr.group = (int)s;
+    pr.sigma_mon = mu[s];
+    E.maxm = std::max(E.maxm, pr.m);
+    MvGroup& G = E.Gs[s];
+    G.op = ops[s];
+    G.first = (int)s;
+    G.count = 1;
+    G.N = pr.m;
+    G.ldv = pr.ldv;
+    G.mv_t = opts[s].matvec;
+  }
+  size_partials(E);
+  // FP64 residual plans (the dense residual always goes through split partials)
+  std::vector<ResidPlan> rplan(nsys);
+  size_t rpart = 0, rys = 0;
+  for (int64_t s = 0; s < nsys; ++s) {
+    rplan[s] = plan_resid(ops[s], 1);
+    if (ops[s]->kind == RBCG_OP_DENSE && rplan[s].splits < 2) {
+      rplan[s].splits = 2;
+      rplan[s].part_elems = (size_t)2 * ops[s]->d;
+    }
+    rpart = std::max(rpart, rplan[s].part_elems);
+    rys = std::max(rys, rplan[s].ys_elems);
+  }
+  std::vector<double*> rbuf(nsys);
+  double *rpart_p = nullptr, *rys_p = nullptr, *mu_dev = nullptr, *sq_dev = nullptr;
+  unsigned char* dscr = nullptr;
+  auto carve_all = [&](Arena& a) {
+    carve(a, E);
+    for (int64_t s = 0; s < nsys; ++s) rbuf[s] = a.take<double>(E.P[s].ldv);
+    rpart_p = a.take<double>(std::max<size_t>(rpart, 1));
+    rys_p = a.take<double>(std::max<size_t>(rys, 1));
+    mu_dev = a.take<double>(nsys);
+    sq_dev = a.take<double>(nsys);
+    dscr = a.take<unsigned char>(1 << 16);
+  };
+  Arena a0;
+  carve_all(a0);
+  Program pg;
+  {
+    std::vector<double> tol(nsys, 0.0);
+    std::vector<CopyDesc> cps(2 * nsys);
+    build_program(pg, E, tol, true, cps, E.maxm);
+  }
+  const size_t desc_off = (size_t)round_up((int64_t)a0.off, 256);
+  int rc = ensure_ws(ctx, desc_off + pg.stg.host.size() + 65536);
+  if (rc) return rc;
+  Arena a1;
+  a1.base = ctx->ws;
+  carve_all(a1);
+  unsigned char* ddesc = (unsigned char*)ctx->ws + desc_off;
+  rc = ensure_pinned(ctx, (size_t)nsys * 64 + 4096);
+  if (rc) return rc;
+  E.active_h = (int32_t*)ctx->pinned;
+  double* host_sq = (double*)((char*)ctx->pinned + round_up(nsys * 2 * sizeof(int32_t), 64));
+  HIP_TRY(hipMemcpyAsync(mu_dev, mu, nsys * sizeof(double), hipMemcpyHostToDevice, st));
+
+  // ||b||
+  std::vector<double> bnorm(nsys), relres(nsys, -1.0);
+  for (int64_t s = 0; s < nsys; ++s) {
+    rc = sqnorms(ctx, plain_rows(b[s], E.P[s].d), 1, E.P[s].d, sq_dev + s, host_sq + s, dscr);
+    if (rc) return rc;
+    bnorm[s] = std::sqrt(host_sq[s]);
+    if (!(bnorm[s] > 0.0) || !std::isfinite(bnorm[s])) return RBCG_ERR_INVALID_ARG;
+  }
+  std::vector<int> status(nsys, RBCG_OK), loads(nsys, 0), sweeps(nsys, 0), iters(nsys, 0), deflated(nsys, 0);
+  std::vector<char> done(nsys, 0);
+  int max_sweeps = 1;
+  for (int64_t s = 0; s < nsys; ++s) max_sweeps = std::max(max_sweeps, opts[s].rtol > 0 ? (int)opts[s].refine_max : 1);
+
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    // systems taking part in this sweep
+    std::vector<int32_t> act(nsys, 0);
+    bool any = false;
+    for (int64_t s = 0; s < nsys; ++s) {
+      const bool fixed = opts[s].rtol == 0.0;
+      act[s] = (!done[s] && (sweep == 0 || !fixed)) ? 1 : 0;
+      any |= act[s] != 0;
+    }
+    if (!any) break;
+    // start block copies: row 0 = current residual (b on the first sweep), rows 1.. = Omega
+    std::vector<CopyDesc> cps;
+    std::vector<double> tol(nsys, 0.0);
+    std::vector<double> rnorm(nsys, 0.0);
+    for (int64_t s = 0; s < nsys; ++s) {
+      const Prob& pr = E.P[s];
+      CopyDesc c{};
+      c.src = plain_rows(sweep == 0 ? b[s] : rbuf[s], pr.d);
+      c.dst = pr.block(0);
+      c.alpha = 1.0;
+      c.rows = 1;
+      c.rows_total = 1;
+      c.n = pr.d;
+      c.active = (int)s;
+      cps.push_back(c);
+      CopyDesc o{};
+      o.src = plain_rows(k[s] > 0 ? omega[s] : b[s], pr.d);
+      o.dst = RowOp{pr.q + pr.ldv, pr.ldv, pr.bs, pr.m, 0};   // rows 1.. of block 0
+      o.alpha = 1.0;
+      o.rows = k[s];
+      o.rows_total = k[s];
+      o.n = pr.d;
+      o.active = k[s] > 0 ? (int)s : -2;
+      cps.push_back(o);
+      rnorm[s] = sweep == 0 ? bnorm[s] : relres[s] * bnorm[s];
+      if (opts[s].rtol > 0.0) {
+        double t = 0.5 * opts[s].rtol * bnorm[s] / std::max(rnorm[s], 1e-300);
+        if (opts[s].matvec == RBCG_F32) t = std::max(t, 1e-6);
+        if (opts[s].matvec == RBCG_BF16) t = std::max(t, 1e-3);
+        tol[s] = std::min(t, 0.5);
+      }
+    }
+    // copy descriptors with inactive systems disabled: a copy whose active index is -2 is skipped
+    for (auto& c : cps)
+      if (c.active == -2) c.rows = 0, c.rows_total = 0, c.active = -1;
+    pg = Program();
+    build_program(pg, E, tol, true, cps, E.maxm);
+    if (pg.stg.host.size() + desc_off + 65536 > ctx->ws_cap) return RBCG_ERR_OOM;
+    rc = upload(ctx, pg.stg, ddesc);
+    if (rc) return rc;
+    rc = set_active_all(ctx, E, act);
+    if (rc) return rc;
+    // monitor scale: ||r|| of the start vector = R0[0][0] is computed on device; use the host norm
+    for (int64_t s = 0; s < nsys; ++s) {
+      HIP_TRY(hipMemcpyAsync(E.P[s].scale, &rnorm[s], sizeof(double), hipMemcpyHostToDevice, st));
+      HIP_TRY(hipMemsetAsync(E.P[s].fail, 0, sizeof(int32_t), st));
+      const int32_t tm = opts[s].t_max - 1;
+      HIP_TRY(hipMemcpyAsync(E.P[s].done_at, &tm, sizeof(int32_t), hipMemcpyHostToDevice, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    // per-system step limits: a system stops at its own t_max (converge kernel cannot see it), so
+    // the engine runs max t_max; systems with smaller t_max are handled by rtol==0 semantics.
+    int steps = 0;
+    rc = run_steps(ctx, E, pg, ddesc, &steps);
+    if (rc) return rc;
+    // steps used per system
+    std::vector<int32_t> done_at(nsys), fail(nsys), rank(nsys);
+    for (int64_t s = 0; s < nsys; ++s) {
+      HIP_TRY(hipMemcpyAsync(&done_at[s], E.P[s].done_at, 4, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(&fail[s], E.P[s].fail, 4, hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    // backward sweeps (each system its own t) and x (+)= Q y
+    for (int64_t s = 0; s < nsys; ++s) {
+      if (!act[s]) continue;
+      const Prob& pr = E.P[s];
+      const int t = std::min(std::min((int)done_at[s] + 1, steps), (int)opts[s].t_max);
+      iters[s] = t;
+      loads[s] += t;
+      sweeps[s] += 1;
+      if (fail[s]) status[s] = RBCG_ERR_NOT_SPD;
+      Staging stg;
+      TriDesc td{};
+      td.D = pr.D;
+      td.Bsub = pr.Bsub;
+      td.mask = pr.mask;
+      td.rhs = pr.R0;
+      td.ld_rhs = pr.m;
+      td.Lw = pr.Lw;
+      td.Xw = pr.Xw;
+      td.Zw = pr.Zw;
+      td.Y = pr.ybuf;
+      td.ldy = 1;
+      td.m = pr.m;
+      td.r = 1;
+      td.active = -1;
+      NnDesc nn{};
+      nn.P = pr.rows(0);
+      nn.C = pr.ybuf;
+      nn.ldc = 1;
+      nn.Y = plain_rows(x[s], pr.d);
+      nn.O = plain_rows(x[s], pr.d);
+      nn.alpha = 1.0;
+      nn.beta = sweep == 0 ? 0.0 : 1.0;
+      nn.Ka = t * pr.m;
+      nn.Mo = 1;
+      nn.N = pr.d;
+      nn.active = -1;
+      const size_t o1 = stg.add(std::vector<TriDesc>{td});
+      const size_t o2 = stg.add(std::vector<NnDesc>{nn});
+      rc = upload(ctx, stg, dscr);
+      if (rc) return rc;
+      HIP_TRY(launch_tri_backward(dptr<TriDesc>(dscr, o1), 1, pr.m, 1, t, nullptr, st));
+      HIP_TRY(launch_gemm_nn_ex(false, dptr<NnDesc>(dscr, o2), 1, 1, pr.d, nullptr, st));
+    }
+    // FP64 residuals
+    for (int64_t s = 0; s < nsys; ++s) {
+      if (!act[s]) continue;
+      const Prob& pr = E.P[s];
+      rc = residual(ctx, pr.op, 1, plain_rows(b[s], pr.d), plain_rows(x[s], pr.d), plain_rows(rbuf[s], pr.d),
+                    mu_dev + s, rplan[s], rpart_p, rys_p, dscr);
+      if (rc) return rc;
+      loads[s] += 1;
+      rc = sqnorms(ctx, plain_rows(rbuf[s], pr.d), 1, pr.d, sq_dev + s, host_sq + s, dscr);
+      if (rc) return rc;
+      relres[s] = std::sqrt(host_sq[s]) / bnorm[s];
+      if (opts[s].rtol == 0.0 || relres[s] <= opts[s].rtol) done[s] = 1;
+    }
+  }
+  int ret = RBCG_OK;
+  for (int64_t s = 0; s < nsys; ++s) {
+    if (status[s] == RBCG_OK && opts[s].rtol > 0.0 && !(relres[s] <= opts[s].rtol)) status[s] = RBCG_ERR_NO_CONVERGENCE;
+    info[s].status = status[s];
+    info[s].iters = iters[s];
+    info[s].matrix_loads = loads[s];
+    info[s].refine_sweeps = sweeps[s];
+    info[s].deflated = deflated[s];
+    info[s].precision_used = opts[s].matvec;
+    info[s].relres = relres[s];
+    if (ret == RBCG_OK && status[s] != RBCG_OK) ret = status[s];
+  }
+  return ret;
+}
+
+// -------------------------------------------------------------------------------- path
+extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, const double* omega, int32_t k, int64_t L,
+                         const double* mu, double* X, const rbcg_opts* opts, rbcg_info* info) {
+  if (!ctx || !op || !b || !mu || !X || !opts || !info || L < 1 || L > 256 || !valid_opts(opts))
+    return RBCG_ERR_INVALID_ARG;
+  if (k < 0 || k >= op->d || k + 1 > kMaxBlock || (k > 0 && !omega)) return RBCG_ERR_INVALID_ARG;
+  for (int64_t l = 0; l < L; ++l)
+    if (!(mu[l] >= 0.0) || !std::isfinite(mu[l])) return RBCG_ERR_INVALID_ARG;
+  if (!op_supports(op, opts->matvec)) return RBCG_ERR_UNSUPPORTED;
+  if (op->device != ctx->device) return RBCG_ERR_INVALID_ARG;
+  const int m = k + 1;
+  if (tri_forward_lds(m, 1) > kLdsCap) return RBCG_ERR_INVALID_ARG;
+  // refinement sweeps start from [R Omega'] with R the L residuals: needs L < m
+  const bool refine = opts->rtol > 0.0;
+  if (refine && opts->refine_max > 1 && L + 1 > m) return RBCG_ERR_UNSUPPORTED;
+  hipStream_t st = ctx->stream;
+  const int d = (int)op->d;
+  Engine E;
+  E.t_max = opts->t_max;
+  E.eta2 = opts->eta > 0 ? opts->eta * opts->eta : 1e-20;
+  E.maxm = m;
+  E.P.resize(1);
+  E.Gs.resize(1);
+  Prob& pr = E.P[0];
+  pr.op = op;
+  pr.d = d;
+  pr.m = m;
+  pr.ldv = round_up(d, 64);
+  // monitor the smallest shift: its system is the worst conditioned
+  double mu_min = mu[0];
+  int l_min = 0;
+  for (int64_t l = 1; l < L; ++l)
+    if (mu[l] < mu_min) { mu_min = mu[l]; l_min = (int)l; }
+  pr.sigma_mon = mu_min;
+  pr.monitor = refine;
+  MvGroup& G = E.Gs[0];
+  G.op = op;
+  G.first = 0;
+  G.count = 1;
+  G.N = m;
+  G.ldv = pr.ldv;
+  G.mv_t = opts->matvec;
+  size_partials(E);
+  ResidPlan rp = plan_resid(op, (int)L);
+  if (op->kind == RBCG_OP_DENSE && rp.splits == 1) {
+    rp.splits = 2;
+    rp.part_elems = (size_t)2 * L * d;
+  }
+  const int64_t ldv = pr.ldv;
+  const size_t T = (size_t)E.t_max;
+  const size_t mm = (size_t)m * m;
+  double *Rbuf, *rpart, *rys, *mu_dev, *sq_dev, *Lws, *Xws, *Zws, *Yall, *Bhat;
+  unsigned char* dscr;
+  int32_t* failL;
+  auto carve_all = [&](Arena& a) {
+    carve(a, E);
+    Rbuf = a.take<double>((size_t)L * ldv);
+    rpart = a.take<double>(std::max<size_t>(rp.part_elems, 1));
+    rys = a.take<double>(std::max<size_t>(rp.ys_elems, 1));
+    mu_dev = a.take<double>(L);
+    sq_dev = a.take<double>(L);
+    Lws = a.take<double>(L * T * mm);
+    Xws = a.take<double>(L * T * mm);
+    Zws = a.take<double>(L * T * m);
+    Yall = a.take<double>(T * m * L);
+    Bhat = a.take<double>((size_t)L * m);
+    failL = a.take<int32_t>(L);
+    dscr = a.take<unsigned char>(1 << 20);
+  };
+  Arena a0;
+  carve_all(a0);
+  Program pg0;
+  {
+    std::vector<double> tol(1, 0.0);
+    std::vector<CopyDesc> cps(2);
+    build_program(pg0, E, tol, refine, cps, m);
+  }
+  const size_t desc_off = (size_t)round_up((int64_t)a0.off, 256);
+  int rc = ensure_ws(ctx, desc_off + pg0.stg.host.size() + 65536);
+  if (rc) return rc;
+  Arena a1;
+  a1.base = ctx->ws;
+  carve_all(a1);
+  unsigned char* ddesc = (unsigned char*)ctx->ws + desc_off;
+  rc = ensure_pinned(ctx, (size_t)L * 16 + 4096);
+  if (rc) return rc;
+  E.active_h = (int32_t*)ctx->pinned;
+  double* host_sq = (double*)((char*)ctx->pinned + 256);
+  HIP_TRY(hipMemcpyAsync(mu_dev, mu, L * sizeof(double), hipMemcpyHostToDevice, st));
+  rc = sqnorms(ctx, plain_rows(b, d), 1, d, sq_dev, host_sq, dscr);
+  if (rc) return rc;
+  const double bnorm = std::sqrt(host_sq[0]);
+  if (!(bnorm > 0.0) || !std::isfinite(bnorm)) return RBCG_ERR_INVALID_ARG;
+  std::vector<double> relres(L, -1.0);
+  std::vector<int> status(L, RBCG_OK);
+  int loads = 0, sweeps = 0, iters = 0;
+  const int max_sweeps = refine ? opts->refine_max : 1;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    std::vector<CopyDesc> cps;
+    int nstart;
+    if (sweep == 0) {
+      CopyDesc c{};
+      c.src = plain_rows(b, d);
+      c.dst = pr.block(0);
+      c.alpha = 1.0;
+      c.rows = 1;
+      c.rows_total = 1;
+      c.n = d;
+      c.active = -1;
+      cps.push_back(c);
+      CopyDesc o{};
+      o.src = plain_rows(k > 0 ? omega : b, d);
+      o.dst = RowOp{pr.q + ldv, ldv, pr.bs, m, 0};
+      o.alpha = 1.0;
+      o.rows = k;
+      o.rows_total = k;
+      o.n = d;
+      o.active = -1;
+      cps.push_back(o);
+      pr.force_first = true;
+      pr.mon_col = 0;
+      nstart = 1;
+    } else {
+      // [R, Omega[0 : m - L]]: every shift's residual is in the start block
+      CopyDesc c{};
+      c.src = plain_rows(Rbuf, ldv);
+      c.dst = pr.block(0);
+      c.alpha = 1.0;
+      c.rows = (int)L;
+      c.rows_total = (int)L;
+      c.n = d;
+      c.active = -1;
+      cps.push_back(c);
+      CopyDesc o{};
+      o.src = plain_rows(k > 0 ? omega : b, d);
+      o.dst = RowOp{pr.q + L * ldv, ldv, pr.bs, m, 0};
+      o.alpha = 1.0;
+      o.rows = m - (int)L;
+      o.rows_total = m - (int)L;
+      o.n = d;
+      o.active = -1;
+      cps.push_back(o);
+      pr.force_first = false;
+      pr.mon_col = l_min;
+      nstart = (int)L;
+    }
+    std::vector<double> tol(1, 0.0);
+    double rmax = bnorm;
+    if (refine) {
+      if (sweep > 0) rmax = relres[l_min] * bnorm;
+      double t = 0.5 * opts->rtol * bnorm / std::max(rmax, 1e-300);
+      if (opts->matvec == RBCG_F32) t = std::max(t, 1e-6);
+      if (opts->matvec == RBCG_BF16) t = std::max(t, 1e-3);
+      tol[0] = std::min(t, 0.5);
+    }
+    Program pg;
+    build_program(pg, E, tol, refine, cps, std::max(nstart, m));
+    if (desc_off + pg.stg.host.size() > ctx->ws_cap) return RBCG_ERR_OOM;
+    rc = upload(ctx, pg.stg, ddesc);
+    if (rc) return rc;
+    rc = set_active_all(ctx, E, std::vector<int32_t>{1});
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(pr.scale, &rmax, sizeof(double), hipMemcpyHostToDevice, st));
+    const int32_t tm = E.t_max - 1;
+    HIP_TRY(hipMemcpyAsync(pr.done_at, &tm, 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemsetAsync(failL, 0, L * sizeof(int32_t), st));
+    int steps = 0;
+    rc = run_steps(ctx, E, pg, ddesc, &steps);
+    if (rc) return rc;
+    int32_t done_at = 0;
+    HIP_TRY(hipMemcpy(&done_at, pr.done_at, 4, hipMemcpyDeviceToHost));
+    const int t = std::min(steps, (int)done_at + 1);
+    iters = t;
+    loads += t;
+    sweeps += 1;
+    // all shifts: forward + backward sweeps; rhs = column l of R0 (sweep > 0) or column 0
+    Staging stg;
+    std::vector<TriDesc> tds;
+    for (int64_t l = 0; l < L; ++l) {
+      TriDesc td{};
+      td.D = pr.D;
+      td.Bsub = pr.Bsub;
+      td.mask = pr.mask;
+      td.rhs = pr.R0 + (sweep == 0 ? 0 : l);
+      td.ld_rhs = m;
+      td.Lw = Lws + l * T * mm;
+      td.Xw = Xws + l * T * mm;
+      td.Zw = Zws + l * T * m;
+      td.Y = Yall + l;
+      td.ldy = L;
+      td.est = nullptr;
+      td.fail = failL + l;
+      td.sigma = mu[l];
+      td.m = m;
+      td.r = 1;
+      td.active = -1;
+      tds.push_back(td);
+    }
+    NnDesc nn{};
+    nn.P = pr.rows(0);
+    nn.C = Yall;
+    nn.ldc = L;
+    nn.Y = plain_rows(X, d);
+    nn.O = plain_rows(X, d);
+    nn.alpha = 1.0;
+    nn.beta = sweep == 0 ? 0.0 : 1.0;
+    nn.Ka = t * m;
+    nn.Mo = (int)L;
+    nn.N = d;
+    nn.active = -1;
+    const size_t o1 = stg.add(tds);
+    const size_t o2 = stg.add(std::vector<NnDesc>{nn});
+    rc = upload(ctx, stg, dscr);
+    if (rc) return rc;
+    HIP_TRY(launch_tri_forward(dptr<TriDesc>(dscr, o1), (int)L, m, 1, 0, t, nullptr, st));
+    HIP_TRY(launch_tri_backward(dptr<TriDesc>(dscr, o1), (int)L, m, 1, t, nullptr, st));
+    HIP_TRY(launch_gemm_nn_ex(false, dptr<NnDesc>(dscr, o2), 1, (int)L, d, nullptr, st));
+    std::vector<int32_t> fh(L);
+    HIP_TRY(hipMemcpyAsync(fh.data(), failL, L * 4, hipMemcpyDeviceToHost, st));
+    // residuals of every shift (FP64)
+    rc = residual(ctx, op, (int)L, RowOp{b, 0, 0, 0x3fffffff, 0}, plain_rows(X, d), plain_rows(Rbuf, ldv), mu_dev, rp,
+                  rpart, rys, dscr);
+    if (rc) return rc;
+    loads += 1;
+    rc = sqnorms(ctx, plain_rows(Rbuf, ldv), (int)L, d, sq_dev, host_sq, dscr);
+    if (rc) return rc;
+    bool all = true;
+    for (int64_t l = 0; l < L; ++l) {
+      relres[l] = std::sqrt(host_sq[l]) / bnorm;
+      if (fh[l]) status[l] = RBCG_ERR_NOT_SPD;
+      if (refine && !(relres[l] <= opts->rtol)) all = false;
+    }
+    if (!refine || all) break;
+  }
+  int ret = RBCG_OK;
+  for (int64_t l = 0; l < L; ++l) {
+    if (status[l] == RBCG_OK && refine && !(relres[l] <= opts->rtol)) status[l] = RBCG_ERR_NO_CONVERGENCE;
+    info[l].status = status[l];
+    info[l].iters = iters;
+    info[l].matrix_loads = loads;
+    info[l].refine_sweeps = sweeps;
+    info[l].deflated = 0;
+    info[l].precision_used = opts->matvec;
+    info[l].relres = relres[l];
+    if (ret == RBCG_OK && status[l] != RBCG_OK) ret = status[l];
+  }
+  return ret;
+}
+
+// ------------------------------------------------------------------------------- sqrt
+extern "C" int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, const double* B, double* Y,
+                               const rbcg_opts* opts, rbcg_info* info) {
+  if (!ctx || !op || !B || !Y || !opts || !info || ms < 1 || !valid_opts(opts)) return RBCG_ERR_INVALID_ARG;
+  if (!op_supports(op, opts->matvec)) return RBCG_ERR_UNSUPPORTED;
+  if (op->device != ctx->device) return RBCG_ERR_INVALID_ARG;
+  const int gs = opts->group > 0 ? opts->group : 32;
+  const int nq = opts->nquad > 0 ? opts->nquad : 32;
+  if (gs > kMaxBlock || gs > op->d || nq > 512) return RBCG_ERR_INVALID_ARG;
+  const int m = (int)std::min<int64_t>(gs, ms);
+  if (tri_forward_lds(m, m) > kLdsCap || tri_backward_lds(m, m) > kLdsCap) return RBCG_ERR_INVALID_ARG;
+  const int ngroups = (int)((ms + m - 1) / m);
+  if (ngroups * m > 16 * 16 * 4 && ngroups * m > 256) {
+    // block products of all groups are fused into one product with N = ngroups * m <= 256
+    return RBCG_ERR_UNSUPPORTED;
+  }
+  hipStream_t st = ctx->stream;
+  const int d = (int)op->d;
+  Engine E;
+  E.t_max = opts->t_max;
+  E.eta2 = opts->eta > 0 ? opts->eta * opts->eta : 1e-20;
+  E.maxm = m;
+  E.P.resize(ngroups);
+  E.Gs.resize(1);
+  const int64_t ldv = round_up(d, 64);
+  for (int g = 0; g < ngroups; ++g) {
+    Prob& pr = E.P[g];
+    pr.op = op;
+    pr.d = d;
+    pr.m = m;
+    pr.ldv = ldv;
+    pr.force_first = false;
+    pr.monitor = false;
+  }
+  MvGroup& G = E.Gs[0];
+  G.op = op;
+  G.first = 0;
+  G.count = ngroups;
+  G.N = ngroups * m;
+  G.ldv = ldv;
+  G.mv_t = opts->matvec;
+  size_partials(E);
+  const int t = E.t_max;
+  const size_t T = (size_t)t, mm = (size_t)m * m;
+  const int ntr = 64;   // spectral-bound trials per group
+  double *Lws, *Xws, *Zws, *Ynodes, *Ybar, *Cq, *wdev, *sig_dev;
+  int32_t *failT, *failN;
+  unsigned char* dscr;
+  auto carve_all = [&](Arena& a) {
+    carve(a, E);
+    const size_t nz = std::max((size_t)ngroups * nq, (size_t)ngroups * ntr);
+    Lws = a.take<double>(nz * T * mm);
+    Xws = a.take<double>(nz * T * mm);
+    Zws = a.take<double>(nz * T * mm);
+    Ynodes = a.take<double>((size_t)ngroups * nq * T * mm);
+    Ybar = a.take<double>((size_t)ngroups * T * mm);
+    Cq = a.take<double>((size_t)ngroups * (T + 1) * mm);
+    wdev = a.take<double>((size_t)ngroups * nq);
+    sig_dev = a.take<double>(1);
+    failT = a.take<int32_t>((size_t)ngroups * ntr);
+    failN = a.take<int32_t>((size_t)ngroups * nq);
+    dscr = a.take<unsigned char>(1 << 22);
+  };
+  Arena a0;
+  carve_all(a0);
+  std::vector<CopyDesc> cps;
+  for (int g = 0; g < ngroups; ++g) {
+    CopyDesc c{};
+    c.src = plain_rows(B + (int64_t)g * m * d, d);
+    c.rows = (int)std::min<int64_t>(m, ms - (int64_t)g * m);
+    c.rows_total = m;
+    c.n = d;
+    c.alpha = 1.0;
+    c.active = -1;
+    cps.push_back(c);
+  }
+  Program pg0;
+  {
+    std::vector<double> tol(ngroups, 0.0);
+    build_program(pg0, E, tol, false, cps, m);
+  }
+  const size_t desc_off = (size_t)round_up((int64_t)a0.off, 256);
+  int rc = ensure_ws(ctx, desc_off + pg0.stg.host.size() + 65536);
+  if (rc) return rc;
+  Arena a1;
+  a1.base = ctx->ws;
+  carve_all(a1);
+  unsigned char* ddesc = (unsigned char*)ctx->ws + desc_off;
+  rc = ensure_pinned(ctx, (size_t)ngroups * (ntr + nq) * 8 + 65536);
+  if (rc) return rc;
+  E.active_h = (int32_t*)ctx->pinned;
+  for (int g = 0; g < ngroups; ++g) cps[g].dst = E.P[g].block(0);
+  Program pg;
+  {
+    std::vector<double> tol(ngroups, 0.0);
+    build_program(pg, E, tol, false, cps, m);
+  }
+  rc = upload(ctx, pg.stg, ddesc);
+  if (rc) return rc;
+  rc = set_active_all(ctx, E, std::vector<int32_t>(ngroups, 1));
+  if (rc) return rc;
+  int steps = 0;
+  rc = run_steps(ctx, E, pg, ddesc, &steps);
+  if (rc) return rc;
+  // ---- spectral interval of each T_t by trial block-Cholesky factorizations:
+  //      T - tau I is positive definite iff tau < lambda_min(T); tau I - T iff tau > lambda_max(T).
+  //      Upper estimate first: ||T||_F >= lambda_max.
+  std::vector<double> lo(ngroups), hi(ngroups);
+  {
+    std::vector<double> Dh((size_t)ngroups * T * mm), Bh((size_t)ngroups * T * mm);
+    for (int g = 0; g < ngroups; ++g) {
+      HIP_TRY(hipMemcpyAsync(Dh.data() + g * T * mm, E.P[g].D, T * mm * 8, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(Bh.data() + g * T * mm, E.P[g].Bsub, T * mm * 8, hipMemcpyDeviceToHost, st));
+    }
+    std::vector<int32_t> mk((size_t)ngroups * (T + 1) * m);
+    for (int g = 0; g < ngroups; ++g)
+      HIP_TRY(hipMemcpyAsync(mk.data() + g * (T + 1) * m, E.P[g].mask, (T + 1) * m * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int g = 0; g < ngroups; ++g) {
+      // Gershgorin upper bound on the true T (deflated rows are zero rows of T)
+      double ub = 0.0;
+      for (int j = 0; j < t; ++j) {
+        for (int a = 0; a < m; ++a) {
+          if (mk[g * (T + 1) * m + (size_t)j * m + a]) continue;
+          double rs = 0.0;
+          const double* Dj = Dh.data() + g * T * mm + (size_t)j * mm;
+          for (int u = 0; u < m; ++u) rs += std::fabs(Dj[a * m + u]);
+          if (j > 0) {
+            const double* Bp = Bh.data() + g * T * mm + (size_t)(j - 1) * mm;
+            for (int u = 0; u < m; ++u) rs += std::fabs(Bp[a * m + u]);
+          }
+          if (j + 1 < t) {
+            const double* Bj = Bh.data() + g * T * mm + (size_t)j * mm;
+            for (int u = 0; u < m; ++u) rs += std::fabs(Bj[u * m + a]);
+          }
+          ub = std::max(ub, rs);
+        }
+      }
+      hi[g] = ub > 0 ? ub : 1.0;
+    }
+    // two rounds of trials for the lower end: coarse (factor 4) then fine within the bracket
+    double base_hi = 0;
+    for (int g = 0; g < ngroups; ++g) base_hi = std::max(base_hi, hi[g]);
+    for (int round = 0; round < 2; ++round) {
+      std::vector<TriDesc> tds;
+      std::vector<double> taus((size_t)ngroups * ntr);
+      for (int g = 0; g < ngroups; ++g) {
+        for (int i = 0; i < ntr; ++i) {
+          double tau;
+          if (round == 0) tau = hi[g] * std::pow(0.5, 1.0 + i * (60.0 / ntr));
+          else tau = lo[g] * std::pow(4.0, (double)(i + 1) / ntr);   // within [lo, 4 lo]
+          taus[(size_t)g * ntr + i] = tau;
+          TriDesc td{};
+          td.D = E.P[g].D;
+          td.Bsub = E.P[g].Bsub;
+          td.mask = E.P[g].mask;
+          td.rhs = nullptr;
+          td.Lw = Lws + ((size_t)g * ntr + i) * T * mm;
+          td.Xw = Xws + ((size_t)g * ntr + i) * T * mm;
+          td.Zw = Zws + ((size_t)g * ntr + i) * T * mm;
+          td.fail = failT + g * ntr + i;
+          td.sigma = -tau;
+          td.m = m;
+          td.r = 0;
+          td.active = -1;
+          tds.push_back(td);
+        }
+      }
+      Staging stg;
+      const size_t o = stg.add(tds);
+      rc = upload(ctx, stg, dscr);
+      if (rc) return rc;
+      HIP_TRY(hipMemsetAsync(failT, 0, (size_t)ngroups * ntr * 4, st));
+      HIP_TRY(launch_tri_forward(dptr<TriDesc>(dscr, o), ngroups * ntr, m, 1, 0, t, nullptr, st));
+      std::vector<int32_t> fh((size_t)ngroups * ntr);
+      HIP_TRY(hipMemcpyAsync(fh.data(), failT, fh.size() * 4, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      for (int g = 0; g < ngroups; ++g) {
+        // the largest tau whose factorization succeeded is a lower bound of lambda_min
+        double best = 0.0;
+        for (int i = 0; i < ntr; ++i)
+          if (!fh[(size_t)g * ntr + i]) best = std::max(best, taus[(size_t)g * ntr + i]);
+        if (round == 0) lo[g] = best > 0 ? best : hi[g] * std::pow(0.5, 61.0);
+        else if (best > 0) lo[g] = std::max(lo[g], best);
+      }
+    }
+  }
+  // ---- quadrature nodes per group and shifted solves for all (group, node)
+  std::vector<double> wts((size_t)ngroups * nq), sg((size_t)ngroups * nq);
+  for (int g = 0; g < ngroups; ++g)
+    if (!sqrt_rule(lo[g], std::max(hi[g], lo[g]), nq, sg.data() + (size_t)g * nq, wts.data() + (size_t)g * nq))
+      return RBCG_ERR_NOT_SPD;
+  HIP_TRY(hipMemcpyAsync(wdev, wts.data(), wts.size() * 8, hipMemcpyHostToDevice, st));
+  {
+    std::vector<TriDesc> tds;
+    for (int g = 0; g < ngroups; ++g) {
+      for (int i = 0; i < nq; ++i) {
+        const size_t z = (size_t)g * nq + i;
+        TriDesc td{};
+        td.D = E.P[g].D;
+        td.Bsub = E.P[g].Bsub;
+        td.mask = E.P[g].mask;
+        td.rhs = E.P[g].R0;
+        td.ld_rhs = m;
+        td.Lw = Lws + z * T * mm;
+        td.Xw = Xws + z * T * mm;
+        td.Zw = Zws + z * T * mm;
+        td.Y = Ynodes + z * T * mm;
+        td.ldy = m;
+        td.fail = failN + z;
+        td.sigma = sg[z];
+        td.m = m;
+        td.r = m;
+        td.active = -1;
+        tds.push_back(td);
+      }
+    }
+    std::vector<WsumDesc> wds;
+    std::vector<TmulDesc> tms;
+    std::vector<NnDesc> nns;
+    for (int g = 0; g < ngroups; ++g) {
+      WsumDesc w{};
+      w.Y = Ynodes + (size_t)g * nq * T * mm;
+      w.node_stride = (int64_t)(T * mm);
+      w.w = wdev + (size_t)g * nq;
+      w.nq = nq;
+      w.n = t * m;
+      w.r = m;
+      w.active = -1;
+      w.out = Ybar + (size_t)g * T * mm;
+      wds.push_back(w);
+      TmulDesc tm{};
+      tm.D = E.P[g].D;
+      tm.Bsub = E.P[g].Bsub;
+      tm.Y = Ybar + (size_t)g * T * mm;
+      tm.out = Cq + (size_t)g * (T + 1) * mm;
+      tm.t = t;
+      tm.m = m;
+      tm.r = m;
+      tm.active = -1;
+      tms.push_back(tm);
+      NnDesc nn{};
+      nn.P = E.P[g].rows(0);
+      nn.C = Cq + (size_t)g * (T + 1) * mm;
+      nn.ldc = m;
+      nn.Y = plain_rows(Y + (int64_t)g * m * d, d);
+      nn.O = plain_rows(Y + (int64_t)g * m * d, d);
+      nn.alpha = 1.0;
+      nn.beta = 0.0;
+      nn.Ka = (t + 1) * m;
+      nn.Mo = (int)std::min<int64_t>(m, ms - (int64_t)g * m);
+      nn.N = d;
+      nn.active = -1;
+      nns.push_back(nn);
+    }
+    Staging stg;
+    const size_t o1 = stg.add(tds);
+    const size_t o2 = stg.add(wds);
+    const size_t o3 = stg.add(tms);
+    const size_t o4 = stg.add(nns);
+    rc = upload(ctx, stg, dscr);
+    if (rc) return rc;
+    HIP_TRY(hipMemsetAsync(failN, 0, (size_t)ngroups * nq * 4, st));
+    HIP_TRY(launch_tri_forward(dptr<TriDesc>(dscr, o1), ngroups * nq, m, m, 0, t, nullptr, st));
+    HIP_TRY(launch_tri_backward(dptr<TriDesc>(dscr, o1), ngroups * nq, m, m, t, nullptr, st));
+    HIP_TRY(launch_wsum(dptr<WsumDesc>(dscr, o2), ngroups, (int64_t)t * m * m, nullptr, st));
+    HIP_TRY(launch_tmul(dptr<TmulDesc>(dscr, o3), ngroups, (int64_t)(t + 1) * m * m, nullptr, st));
+    HIP_TRY(launch_gemm_nn_ex(false, dptr<NnDesc>(dscr, o4), ngroups, m, d, nullptr, st));
+    std::vector<int32_t> fh((size_t)ngroups * nq);
+    HIP_TRY(hipMemcpyAsync(fh.data(), failN, fh.size() * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    int ret = RBCG_OK;
+    for (int64_t i = 0; i < ms; ++i) {
+      const int g = (int)(i / m);
+      bool f = false;
+      for (int q = 0; q < nq; ++q) f |= fh[(size_t)g * nq + q] != 0;
+      info[i].status = f ? RBCG_ERR_NOT_SPD : RBCG_OK;
+      info[i].iters = steps;
+      info[i].matrix_loads = steps;
+      info[i].refine_sweeps = 1;
+      info[i].deflated = 0;
+      info[i].precision_used = opts->matvec;
+      info[i].relres = -1.0;
+      if (f && ret == RBCG_OK) ret = RBCG_ERR_NOT_SPD;
+    }
+    return ret;
+  }
+}
+
+// Host-only: the quadrature rule used by rbcg_sqrt_apply (exported for testing without a GPU).
+extern "C" int rbcg_sqrt_rule(double lo, double hi, int32_t n, double* shifts, double* weights) {
+  if (!shifts || !weights || n < 1) return RBCG_ERR_INVALID_ARG;
+  return sqrt_rule(lo, hi, n, shifts, weights) ? RBCG_OK : RBCG_ERR_INVALID_ARG;
+}

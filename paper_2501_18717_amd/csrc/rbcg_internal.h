@@ -1,0 +1,176 @@
+// Internal declarations shared by the device kernels (kernels.hip) and the
+// host runtime (rbcg.cpp).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace rbcg {
+
+// Largest block width a single-workgroup factorization keeps in LDS:
+// a 129 x 129 FP64 matrix is 133 KB of the 160 KB per CU.
+constexpr int kMaxBlock = 129;
+
+// A set of "rows": vectors stored contiguously, row a at
+//   p + (a / rb) * bs + (a % rb) * ld      (elements)
+// The two-level form lets several Krylov bases be interleaved block by block.
+struct RowOp {
+  const void* p;
+  int64_t ld;
+  int64_t bs;
+  int32_t rb;
+  int32_t pad_;
+};
+
+inline RowOp plain_rows(const void* p, int64_t ld) { return RowOp{p, ld, 0, 0x3fffffff, 0}; }
+
+// C[i][c] = sum_k P[i][k] * X[c][k] for i < M, c < N, k < K.
+// Partial sums of split s go to part[(s * M + i) * N + c] (FP64).
+struct NtDesc {
+  RowOp P;
+  RowOp X;
+  int32_t M, N, K, active;   // active: index into the active-flag array, -1 = always
+  double* part;              // split-K partials (when splits > 1), in output orientation
+  RowOp O;                   // direct transposed output: row c, element i (when out == null)
+  double* out;               // direct row-major output out[i * ldo + c]
+  int64_t ldo;
+  int32_t out_t, pad_;       // element type of O: DType, or 3 = BF16 hi/lo pair (rows 2c, 2c+1)
+};
+
+// Reduction of the split-K partials with an epilogue.
+enum FinMode : int32_t {
+  FIN_ROWMAJOR = 0,   // out[i * ldo + c] = alpha * sum
+  FIN_TRANS = 1,      // row c of `O` (a RowOp), element i:  = alpha * sum
+  FIN_RESID = 2,      // row c of O, element i: rhs[c][i] - sum - mu[c] * xin[c][i]
+};
+struct FinDesc {
+  const double* part;
+  int32_t M, N, splits, mode;
+  double* out;            // FIN_ROWMAJOR target
+  int64_t ldo;
+  RowOp O;                // FIN_TRANS / FIN_RESID target rows (p is writable)
+  RowOp rhs;              // FIN_RESID: right-hand sides
+  RowOp xin;              // FIN_RESID: current iterates
+  const double* mu;       // FIN_RESID: shift of each row c
+  double alpha;
+  int32_t active, pad_;
+};
+
+// O[b][i] = beta * Y[b][i] + alpha * sum_a C[a][b] * P[a][i]
+// for b < Mo, i < N, a < Ka.  O may alias Y.
+struct NnDesc {
+  RowOp P;
+  const double* C;
+  int64_t ldc;
+  RowOp Y;
+  RowOp O;
+  double alpha, beta;
+  int32_t Ka, Mo, N, active;
+};
+
+// Factorization of a small Gram matrix G = W^T W (m x m) for Cholesky QR
+// with rank-revealing pivoting and deflation.
+//   Mout[a][s]  : Q = W * Mout  (m x m, zero columns for deflated s)
+//   Bout[s][c]  : W = Q * Bout  (m x m, zero rows for deflated s)
+//   mask[s]     : 1 if basis column s is deflated
+// With prevB != null the reported coefficient is Bout * prevB.
+struct QrDesc {
+  const double* G;
+  int64_t ldg;
+  const double* pre;       // pre-projection squared norms (stride pre_stride) or null
+  int64_t pre_stride;
+  double* Mout;
+  double* Bout;
+  const double* prevB;
+  int32_t* mask;
+  int32_t* rank_out;
+  int32_t m, pivot, force_first, active;
+  double eta2;             // deflation threshold (relative, squared) vs pre-projection norm
+  double tau;              // deflation threshold (relative, squared) vs the block's own norm
+};
+
+// Symmetrised diagonal block of T from the two projection passes.
+struct DiagDesc {
+  const double* C1; const double* C2;  // rows of Q_j^T W from each pass (m x m, ld = ldc)
+  int64_t ldc;
+  double* D;                           // T diagonal block j (m x m)
+  const int32_t* mask;                 // deflated columns of Q_j
+  int32_t m, has_c2, active, pad_;
+};
+
+// Shifted block-tridiagonal solve (T_t + sigma I) Y = RHS with RHS nonzero
+// only in the first block row.  Blocks: D[j] (diagonal, m x m), Bsub[j]
+// (T[j+1][j], m x m), masks per block.  Workspace holds L_jj, X_j =
+// L_{j+1,j} and the forward iterates per block.
+struct TriDesc {
+  const double* D;         // t blocks of m*m
+  const double* Bsub;      // t blocks of m*m (block j couples j+1 to j)
+  const int32_t* mask;     // t*m deflation flags
+  const double* rhs;       // m x r (first block of the right-hand side), row stride ld_rhs
+  int64_t ld_rhs;
+  double* Lw;              // workspace: t blocks of m*m (Cholesky factors)
+  double* Xw;              // workspace: t blocks of m*m (sub-diagonal factors)
+  double* Zw;              // workspace: t blocks of m*r (forward iterates)
+  double* Y;               // output rows (block j row i at Y[(j*m + i) * ldy + c])
+  int64_t ldy;
+  double* est;             // residual estimate output (monitor) or null
+  int32_t* fail;           // set to 1 on a non-positive pivot
+  double sigma;
+  int32_t m, r, active, pad_;
+};
+
+// Conversion of rows between precisions (RNE).
+enum DType : int32_t { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
+struct CvtDesc {
+  RowOp src;  // FP64 or FP32 rows
+  RowOp dst;
+  int32_t rows, cols, src_t, dst_t;
+  int32_t active, split_lo, pad0, pad1;   // split_lo: write hi/lo BF16 pairs (dst rows 2r, 2r+1)
+};
+
+// ---------------------------------------------------------------- launchers
+// Each launcher enqueues on `st` for `nz` problems whose descriptors already
+// live in device memory.  They return hipSuccess or the launch error.
+// dtype: DType or 3 = FP32 P values with FP64 arithmetic; out_t: 0 = row-major (i, c),
+// 1 = transposed (row c); xsplit: X rows hold BF16 hi/lo pairs.
+hipError_t launch_gemm_nt_ex(int dtype, int out_t, bool xsplit, const NtDesc* d_desc, int nz, int maxM,
+                             int maxN, int splits, const int32_t* active, hipStream_t st);
+hipError_t launch_finish(const FinDesc* d_desc, int nz, int maxM, int maxN, const int32_t* active,
+                         hipStream_t st);
+hipError_t launch_gemm_nn_ex(bool p_f32, const NnDesc* d_desc, int nz, int maxMo, int maxN,
+                             const int32_t* active, hipStream_t st);
+hipError_t launch_qr_factor(const QrDesc* d_desc, int nz, int maxm, const int32_t* active,
+                            hipStream_t st);
+hipError_t launch_diag(const DiagDesc* d_desc, int nz, int maxm, const int32_t* active, hipStream_t st);
+hipError_t launch_tri_forward(const TriDesc* d_desc, int nz, int maxm, int maxr, int j0, int j1,
+                              const int32_t* active, hipStream_t st);
+hipError_t launch_tri_backward(const TriDesc* d_desc, int nz, int maxm, int maxr, int t,
+                               const int32_t* active, hipStream_t st);
+// LDS bytes the two sweeps need for block width m and r right-hand sides.
+inline size_t tri_forward_lds(int m, int r) { return ((size_t)m * m + 16 * (size_t)m + (size_t)m * r) * 8; }
+inline size_t tri_backward_lds(int m, int r) { return ((size_t)m * m + 2 * (size_t)m * r) * 8; }
+constexpr size_t kLdsCap = 160 * 1024 - 4096;
+hipError_t launch_convert(const CvtDesc* d_desc, int nz, int maxRows, int maxCols,
+                          const int32_t* active, hipStream_t st);
+// Column sums of squares: out[z * ldout + r] = sum_i rows[r][i]^2 for r < rows_z.
+struct NormDesc { RowOp x; double* out; int32_t rows, n, active, pad_; };
+hipError_t launch_sqnorms(const NormDesc* d_desc, int nz, int maxRows, const int32_t* active,
+                          hipStream_t st);
+// Copy rows (FP64): dst[r][i] = alpha * src[r][i]; zero-fills rows [rows, rows_total).
+struct CopyDesc { RowOp src; RowOp dst; double alpha; int32_t rows, rows_total, n, active; };
+hipError_t launch_copy(const CopyDesc* d_desc, int nz, int maxRows, int maxN, const int32_t* active,
+                       hipStream_t st);
+
+hipError_t launch_transpose_bf16(const float* src, int64_t ld, int rows, int cols, unsigned short* dst,
+                                 int64_t ldt, hipStream_t st);
+
+// Quadrature-node sum and block-tridiagonal product for the square root.
+struct WsumDesc { const double* Y; int64_t node_stride; const double* w; int32_t nq, n, r, active; double* out; };
+struct TmulDesc { const double* D; const double* Bsub; const double* Y; double* out; int32_t t, m, r, active; };
+hipError_t launch_wsum(const WsumDesc* d_desc, int nz, int64_t maxTotal, const int32_t* active, hipStream_t st);
+hipError_t launch_tmul(const TmulDesc* d_desc, int nz, int64_t maxTotal, const int32_t* active, hipStream_t st);
+
+// Device-side convergence: clears *active_flag once *est <= tol * *scale, recording the step.
+struct ConvDesc { const double* est; const double* scale; double tol; int32_t* active_flag; int32_t* done_at; int32_t step, pad_; };
+hipError_t launch_converge(const ConvDesc* d_desc, int nz, hipStream_t st);
+
+}  // namespace rbcg

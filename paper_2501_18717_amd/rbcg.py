@@ -1,0 +1,274 @@
+"""Thin ctypes binding of librbcg.so (C ABI in include/rbcg.h).
+
+Only argument marshalling happens here: every step of the solvers runs in the
+library's HIP kernels.  PyTorch provides device memory and the stream.  If the
+compiled library is missing, importing this module raises ImportError: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librbcg.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"librbcg.so not built ({LIB_PATH}); run `python -m paper_2501_18717_amd.build`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+F64, F32, BF16 = 0, 1, 2
+DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
+STATUS = {0: "OK", -1: "INVALID_ARG", -2: "NOT_SPD", -3: "BREAKDOWN", -4: "NO_CONVERGENCE",
+          -5: "HIP", -6: "OOM", -7: "UNSUPPORTED"}
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("t_max", ctypes.c_int32), ("rtol", ctypes.c_double), ("matvec", ctypes.c_int32),
+                ("refine_max", ctypes.c_int32), ("nquad", ctypes.c_int32), ("group", ctypes.c_int32),
+                ("eta", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("matrix_loads", ctypes.c_int32),
+                ("refine_sweeps", ctypes.c_int32), ("deflated", ctypes.c_int32),
+                ("precision_used", ctypes.c_int32), ("relres", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_status_string = _sig("rbcg_status_string", ctypes.c_char_p, [ctypes.c_int])
+_version = _sig("rbcg_version", ctypes.c_int, [])
+_create = _sig("rbcg_create", ctypes.c_int, [ctypes.POINTER(_vp), _vp])
+_destroy = _sig("rbcg_destroy", ctypes.c_int, [_vp])
+_op_dense = _sig("rbcg_op_create_dense", ctypes.c_int, [_vp, ctypes.POINTER(_vp), _i64, _vp, _i64, ctypes.c_int])
+_op_gram = _sig("rbcg_op_create_gram", ctypes.c_int, [_vp, ctypes.POINTER(_vp), _i64, _i64, _vp, _i64, ctypes.c_int])
+_op_destroy = _sig("rbcg_op_destroy", ctypes.c_int, [_vp])
+_solve = _sig("rbcg_solve", ctypes.c_int, [_vp, _i64, ctypes.POINTER(_vp), _dp, ctypes.POINTER(_vp),
+                                            ctypes.POINTER(_vp), ctypes.POINTER(_i32), ctypes.POINTER(_vp),
+                                            ctypes.POINTER(Opts), ctypes.POINTER(Info)])
+_path = _sig("rbcg_path", ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i64, _dp, _vp, ctypes.POINTER(Opts),
+                                          ctypes.POINTER(Info)])
+_sqrt = _sig("rbcg_sqrt_apply", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)])
+_ws_bytes = _sig("rbcg_workspace_bytes", _i64, [_vp])
+_sqrt_rule = _sig("rbcg_sqrt_rule", ctypes.c_int, [ctypes.c_double, ctypes.c_double, _i32, _dp, _dp])
+
+
+class RbcgError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {STATUS.get(code, code)} ({_status_string(code).decode()})")
+        self.code = code
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise RbcgError(code, where)
+
+
+def status_string(code: int) -> str:
+    return _status_string(code).decode()
+
+
+def version() -> int:
+    return _version()
+
+
+def sqrt_rule(lo: float, hi: float, n: int):
+    """Host-only quadrature rule of the square-root integral (shifts, weights)."""
+    s = (ctypes.c_double * n)()
+    w = (ctypes.c_double * n)()
+    _check(_sqrt_rule(lo, hi, n, s, w), "rbcg_sqrt_rule")
+    return list(s), list(w)
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def _need(t, dtype, shape=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+def opts(t_max: int, rtol: float = 0.0, matvec: str = "f64", refine_max: int = 1, nquad: int = 0, group: int = 0,
+         eta: float = 0.0) -> Opts:
+    return Opts(int(t_max), float(rtol), DTYPES[matvec], int(refine_max), int(nquad), int(group), float(eta))
+
+
+class Context:
+    """Binds a HIP stream (torch's current stream by default) and owns the workspace."""
+
+    def __init__(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = _vp()
+        _check(_create(ctypes.byref(h), _vp(stream.cuda_stream)), "rbcg_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace_bytes(self) -> int:
+        return int(_ws_bytes(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DenseOperator:
+    """A (d x d, FP64, symmetric) with an optional FP32 copy for mixed-precision products."""
+
+    def __init__(self, ctx: Context, A, lo: str = "f64"):
+        import torch
+        _need(A, torch.float64, name="A")
+        d = A.shape[0]
+        if A.dim() != 2 or A.shape[1] != d:
+            raise ValueError("A must be square")
+        h = _vp()
+        _check(_op_dense(ctx.handle, ctypes.byref(h), d, _ptr(A), d, DTYPES[lo]), "rbcg_op_create_dense")
+        self._h, self.A, self.d, self.ctx = h, A, d, ctx
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _op_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class GramOperator:
+    """A = Z^T Z with Z (n x d, FP32) and optional BF16 copies of Z and Z^T."""
+
+    def __init__(self, ctx: Context, Z, lo: str = "f64"):
+        import torch
+        _need(Z, torch.float32, name="Z")
+        n, d = Z.shape
+        h = _vp()
+        _check(_op_gram(ctx.handle, ctypes.byref(h), n, d, _ptr(Z), d, DTYPES[lo]), "rbcg_op_create_gram")
+        self._h, self.Z, self.n, self.d, self.ctx = h, Z, n, d, ctx
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _op_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(ctx: Context, ops: Sequence, mus: Sequence[float], bs: Sequence, omegas: Sequence, xs: Sequence,
+          options: Sequence[Opts], check: bool = True):
+    """rbcg_solve over len(ops) independent systems; x tensors are written in place."""
+    import torch
+    n = len(ops)
+    assert len(mus) == n and len(bs) == n and len(omegas) == n and len(xs) == n and len(options) == n
+    ks = []
+    for i in range(n):
+        d = ops[i].d
+        _need(bs[i], torch.float64, (d,), "b")
+        _need(xs[i], torch.float64, (d,), "x")
+        om = omegas[i]
+        if om is not None and om.numel():
+            _need(om, torch.float64, name="omega")
+            if om.dim() != 2 or om.shape[1] != d:
+                raise ValueError("omega must have shape (k, d)")
+            ks.append(om.shape[0])
+        else:
+            ks.append(0)
+    op_arr = (_vp * n)(*[o.handle for o in ops])
+    mu_arr = (ctypes.c_double * n)(*[float(m) for m in mus])
+    b_arr = (_vp * n)(*[_ptr(b) for b in bs])
+    om_arr = (_vp * n)(*[(_ptr(o) if (o is not None and o.numel()) else None) for o in omegas])
+    k_arr = (_i32 * n)(*ks)
+    x_arr = (_vp * n)(*[_ptr(x) for x in xs])
+    o_arr = (Opts * n)(*options)
+    info = (Info * n)()
+    rc = _solve(ctx.handle, n, op_arr, mu_arr, b_arr, om_arr, k_arr, x_arr, o_arr, info)
+    infos = [i.as_dict() for i in info]
+    if check and rc not in (0, -4):
+        raise RbcgError(rc, "rbcg_solve")
+    return rc, infos
+
+
+def path(ctx: Context, op, b, omega, mus: Sequence[float], X, options: Opts, check: bool = True):
+    """rbcg_path: X (L x d) written in place."""
+    import torch
+    d = op.d
+    L = len(mus)
+    _need(b, torch.float64, (d,), "b")
+    _need(X, torch.float64, (L, d), "X")
+    k = 0
+    if omega is not None and omega.numel():
+        _need(omega, torch.float64, name="omega")
+        k = omega.shape[0]
+    mu_arr = (ctypes.c_double * L)(*[float(m) for m in mus])
+    info = (Info * L)()
+    rc = _path(ctx.handle, op.handle, _ptr(b), _ptr(omega) if k else None, k, L, mu_arr, _ptr(X),
+               ctypes.byref(options), info)
+    infos = [i.as_dict() for i in info]
+    if check and rc not in (0, -4):
+        raise RbcgError(rc, "rbcg_path")
+    return rc, infos
+
+
+def sqrt_apply(ctx: Context, op, B, Y, options: Opts, check: bool = True):
+    """rbcg_sqrt_apply: Y (m_s x d) ~ rows of A^(1/2) B^T, written in place."""
+    import torch
+    ms, d = B.shape
+    _need(B, torch.float64, (ms, op.d), "B")
+    _need(Y, torch.float64, (ms, op.d), "Y")
+    info = (Info * ms)()
+    rc = _sqrt(ctx.handle, op.handle, ms, _ptr(B), _ptr(Y), ctypes.byref(options), info)
+    infos = [i.as_dict() for i in info]
+    if check and rc != 0:
+        raise RbcgError(rc, "rbcg_sqrt_apply")
+    return rc, infos
