@@ -173,6 +173,17 @@ int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t m_s, const double*
 /* Bytes of device memory currently held by the context's workspace. */
 int64_t rbcg_workspace_bytes(const rbcg_ctx* ctx);
 
+/* Measurement hook.  rbcg_profile(ctx, 1) clears the counters and starts
+ * timing every block-product GEMM launch (the A X or Z^T (Z X) products that
+ * the paper counts as matrix-loads, Sec. 1.2) with HIP events on the context's
+ * stream; rbcg_profile(ctx, 0) stops.  rbcg_profile_read reports the number of
+ * timed launches, their summed GPU time in milliseconds, and their summed
+ * algorithmic flops (2 * rows * cols * block width per GEMM) and HBM bytes
+ * (one read of the operator per GEMM).  All pointers are host pointers. */
+int rbcg_profile(rbcg_ctx* ctx, int enable);
+int rbcg_profile_read(const rbcg_ctx* ctx, int64_t* launches, double* ms_total, double* flops_total,
+                      double* bytes_total);
+
 /* Host-only, no device needed: the n-node quadrature rule rbcg_sqrt_apply
  * uses for the integral sqrt(l) = (2/pi) int_0^inf l / (l + z^2) dz on
  * spectra inside [lo, hi] (eq. sqrt_rational): the conformal-map rule of

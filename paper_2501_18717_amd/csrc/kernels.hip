@@ -186,77 +186,87 @@ hipError_t launch_gemm_nn_ex(bool p_f32, const NnDesc* dd, int nz, int maxMo, in
 // a column is deflated when that ratio falls below tau, or its remaining norm falls below
 // sqrt(eta2) of its norm before the projections against the basis.
 // ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_qr_factor(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) {
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+  // maximum value, smallest index on ties, across the 64 lanes of a wave
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off, 64);
+    const int oi = __shfl_xor(i, off, 64);
+    if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
+  }
+}
+
+// Register-resident pivoted Cholesky QR factor.  Thread t owns column c = t % m and rows
+// a = stripe + stripes*q (stripe = t / m, stripes = 1024 / m) of the Gram matrix, slot q.
+// Per pivot step: wave argmax over the published diagonal, publish the pivot row (zeros on
+// retired columns), one FMA per owned element.  Three barriers per step.
+template <int NS>
+__global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) {
   const QrDesc d = descs[blockIdx.z];
   if (!is_active(act, d.active)) return;
   const int m = d.m;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int stripes = 1024 / m;
+  const int c = tid % m, stripe = tid / m;
+  const bool owner = stripe < stripes;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* S = (double*)smem_raw;             // m*m: Schur complement; row perm[s] becomes R row s
-  double* row = S + m * m;                   // m
-  double* dref = row + m;                    // m
+  double* Rl = (double*)smem_raw;            // m*m: R rows by pivot position
+  double* rowb = Rl + m * m;                 // m: published row
+  double* diag = rowb + m;                   // m: current Schur diagonal
+  double* dref = diag + m;                   // m
   double* pre = dref + m;                    // m
-  double* redv = pre + m;                    // 256
-  int* redi = (int*)(redv + 256);            // 256
-  int* perm = redi + 256;                    // m: pivot position s -> column of W
-  int* chosen = perm + m;                    // m: per column of W
-  int* kept = chosen + m;                    // m: per pivot position, 1 = basis vector kept
-  __shared__ int s_p, s_rank;
+  double* pan = pre + m;                     // 16*m: prevB panel
+  double* wv = pan + 16 * m;                 // 16
+  int* wi = (int*)(wv + 16);                 // 16
+  int* perm = wi + 16;                       // m: pivot position -> column of W
+  int* chosen = perm + m;                    // m: per column of W (later: inverse permutation)
+  int* kept = chosen + m;                    // m: per pivot position
+  __shared__ int s_rank;
 
-  for (int e = tid; e < m * m; e += 256) S[e] = d.G[(int64_t)(e / m) * d.ldg + (e % m)];
-  __syncthreads();
-  for (int e = tid; e < m; e += 256) {
-    dref[e] = S[e * m + e];
-    pre[e] = d.pre ? d.pre[(int64_t)e * d.pre_stride] : -1.0;
-    chosen[e] = 0;
-    kept[e] = 0;
-    perm[e] = e;
+  double v[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    const int a = stripe + stripes * q;
+    v[q] = (owner && a < m) ? d.G[(int64_t)a * d.ldg + c] : 0.0;
+  }
+  for (int e = tid; e < m * m; e += 1024) Rl[e] = 0.0;
+  for (int i = tid; i < m; i += 1024) {
+    const double g = d.G[(int64_t)i * d.ldg + i];
+    dref[i] = g;
+    diag[i] = g;
+    pre[i] = d.pre ? d.pre[(int64_t)i * d.pre_stride] : -1.0;
+    chosen[i] = 0;
+    kept[i] = 0;
+    perm[i] = i;
   }
   if (tid == 0) s_rank = 0;
   __syncthreads();
 
-  for (int s = 0; s < m; ++s) {
-    // ---- choose the pivot column
+  int s = 0;
+  for (; s < m; ++s) {
+    int p = s;
     if (d.pivot && !(d.force_first && s == 0)) {
       double best = -2.0;
-      int bi = m;
-      for (int c = tid; c < m; c += 256) {
-        if (chosen[c]) continue;
-        const double rel = dref[c] > 0.0 ? S[c * m + c] / dref[c] : -1.0;
-        if (rel > best || (rel == best && c < bi)) { best = rel; bi = c; }
+      int bi = 0x7fffffff;
+      if (tid < m && !chosen[tid]) {
+        best = dref[tid] > 0.0 ? diag[tid] / dref[tid] : -1.0;
+        bi = tid;
       }
-      redv[tid] = best;
-      redi[tid] = bi;
+      wave_argmax(best, bi);
+      if (lane == 0) { wv[wave] = best; wi[wave] = bi; }
       __syncthreads();
-      for (int off = 128; off > 0; off >>= 1) {
-        if (tid < off) {
-          const double ov = redv[tid + off];
-          const int oi = redi[tid + off];
-          if (ov > redv[tid] || (ov == redv[tid] && oi < redi[tid])) { redv[tid] = ov; redi[tid] = oi; }
-        }
-        __syncthreads();
-      }
-      if (tid == 0) s_p = redi[0];
-    } else if (tid == 0) {
-      s_p = s;
+      best = wv[0];
+      bi = wi[0];
+#pragma unroll
+      for (int w = 1; w < 16; ++w)
+        if (wv[w] > best || (wv[w] == best && wi[w] < bi)) { best = wv[w]; bi = wi[w]; }
+      p = bi;
     }
-    __syncthreads();
-    const int p = s_p;
-    const double piv2 = S[p * m + p];
+    const double piv2 = diag[p];
     bool defl;
     if (d.force_first && s == 0) defl = !(piv2 > 0.0);
     else defl = !(dref[p] > 0.0) || !(piv2 > d.tau * dref[p]) || (pre[p] >= 0.0 && !(piv2 > d.eta2 * pre[p]));
-    if (defl && d.pivot) {
-      // every remaining column is at least as deficient: list them in index order and stop
-      __syncthreads();
-      if (tid == 0) {
-        int pos = s;
-        for (int c = 0; c < m; ++c)
-          if (!chosen[c]) { perm[pos++] = c; chosen[c] = 1; }
-      }
-      __syncthreads();
-      break;
-    }
+    if (defl && d.pivot) break;   // every remaining column is at least as deficient
     if (defl) {
       __syncthreads();
       if (tid == 0) { perm[s] = p; chosen[p] = 1; }
@@ -264,88 +274,132 @@ __global__ __launch_bounds__(256) void k_qr_factor(const QrDesc* __restrict__ de
       continue;
     }
     const double rp = sqrt(piv2);
-    for (int c = tid; c < m; c += 256) {
-      double v = 0.0;
-      if (c == p) v = rp;
-      else if (!chosen[c]) v = S[p * m + c] / rp;
-      row[c] = v;
+    const double irp = 1.0 / rp;
+    // publish row p of R: the owner of (p, c) for every column c
+    if (owner && stripe == p % stripes) {
+      const int qp = p / stripes;
+      double x = 0.0;
+#pragma unroll
+      for (int q = 0; q < NS; ++q)
+        if (q == qp) x = v[q];
+      rowb[c] = (c == p) ? rp : (chosen[c] ? 0.0 : x * irp);
     }
     __syncthreads();
-    // row p of S is retired: it now stores R row s
-    for (int c = tid; c < m; c += 256) S[p * m + c] = row[c];
+    // Schur update of owned elements; retired and chosen rows/columns see a zero factor
+    if (owner) {
+      const double rc = rowb[c];
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        const int a = stripe + stripes * q;
+        if (a < m) {
+          v[q] -= rowb[a] * rc;
+          if (a == c) diag[a] = v[q];
+        }
+      }
+    }
+    for (int i = tid; i < m; i += 1024) Rl[s * m + i] = rowb[i];
     if (tid == 0) { perm[s] = p; chosen[p] = 1; kept[s] = 1; s_rank = s_rank + 1; }
     __syncthreads();
-    // Schur complement update of the remaining columns
-    for (int e = tid; e < m * m; e += 256) {
-      const int a = e / m, c = e % m;
-      if (chosen[a] || chosen[c]) continue;
-      S[e] -= row[a] * row[c];
-    }
-    __syncthreads();
+  }
+  if (tid == 0) {
+    int pos = s;
+    for (int i = 0; i < m && pos < m; ++i)
+      if (!chosen[i]) { perm[pos++] = i; chosen[i] = 1; }
   }
   __syncthreads();
-  // ---- reported coefficient block: Bout[s][c] = R[s][c] (times prevB when given)
-  for (int e = tid; e < m * m; e += 256) {
-    const int s = e / m, c = e % m;
-    double v = 0.0;
-    if (kept[s]) {
-      const double* Rs = S + perm[s] * m;
-      if (d.prevB) {
-        for (int u = 0; u < m; ++u) v += Rs[u] * d.prevB[u * m + c];
-      } else {
-        v = Rs[c];
+  // ---- reported coefficient block Bout = R (times prevB, staged 16 columns at a time)
+  if (d.prevB) {
+    for (int c0 = 0; c0 < m; c0 += 16) {
+      const int nc = min(16, m - c0);
+      for (int e = tid; e < m * 16; e += 1024) {
+        const int u = e >> 4, cc = e & 15;
+        pan[e] = cc < nc ? d.prevB[u * m + c0 + cc] : 0.0;
       }
+      __syncthreads();
+      for (int e = tid; e < m * 16; e += 1024) {
+        const int s0 = e >> 4, cc = e & 15;
+        if (cc >= nc) continue;
+        double acc = 0.0;
+        if (kept[s0]) {
+          const double* Rs = Rl + s0 * m;
+          for (int u = 0; u < m; ++u) acc += Rs[u] * pan[u * 16 + cc];
+        }
+        d.Bout[s0 * m + c0 + cc] = acc;
+      }
+      __syncthreads();
     }
-    d.Bout[e] = v;
+  } else {
+    for (int e = tid; e < m * m; e += 1024) d.Bout[e] = kept[e / m] ? Rl[e] : 0.0;
   }
-  for (int e = tid; e < m; e += 256) d.mask[e] = kept[e] ? 0 : 1;
+  for (int e = tid; e < m; e += 1024) d.mask[e] = kept[e] ? 0 : 1;
   if (tid == 0 && d.rank_out) *d.rank_out = s_rank;
+  // ---- X = Rhat^{-1} in registers (pivot positions), Rhat[i][u] = R[i][perm[u]]:
+  //      X = I; for q descending: X[q][:] /= Rhat[q][q]; X[i][:] -= Rhat[i][q] X[q][:], i < q.
   __syncthreads();
-  int* iperm = chosen;   // no longer needed: reuse as the inverse permutation
-  for (int s = tid; s < m; s += 256) iperm[perm[s]] = s;
-  __syncthreads();
-  // ---- X = Rhat^{-1}, Rhat[s][u] = R[s][perm[u]] upper triangular over kept positions.
-  //      Row s of X overwrites row perm[s] of S (rows u > s already hold X, rows < s hold R):
-  //      X[s][c] stored at S[perm[s]][perm[c]].
-  for (int s = m - 1; s >= 0; --s) {
-    if (!kept[s]) continue;   // uniform (LDS)
-    const int ps = perm[s];
-    for (int u = tid; u < m; u += 256) row[u] = kept[u] ? S[ps * m + perm[u]] : 0.0;
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    const int a = stripe + stripes * q;
+    v[q] = (owner && a < m && a == c && kept[a]) ? 1.0 : 0.0;
+  }
+  const int qtop = d.pivot ? s_rank - 1 : m - 1;
+  for (int qq = qtop; qq >= 0; --qq) {
+    if (!kept[qq]) continue;                        // uniform (LDS)
+    const double rqq = Rl[qq * m + perm[qq]];
+    if (owner && stripe == qq % stripes) {
+      const int qs = qq / stripes;
+#pragma unroll
+      for (int q = 0; q < NS; ++q)
+        if (q == qs) {
+          v[q] /= rqq;
+          rowb[c] = v[q];
+        }
+    }
     __syncthreads();
-    const double rss = row[s];
-    for (int c = tid; c < m; c += 256) {
-      double v = 0.0;
-      if (c >= s && kept[c]) {
-        double acc = (c == s) ? 1.0 : 0.0;
-        for (int u = s + 1; u <= c; ++u)
-          if (kept[u]) acc -= row[u] * S[perm[u] * m + perm[c]];
-        v = acc / rss;
+    if (owner) {
+      const double xc = rowb[c];
+      const int pq = perm[qq];
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        const int a = stripe + stripes * q;
+        if (a < qq && kept[a]) v[q] -= Rl[a * m + pq] * xc;
       }
-      S[ps * m + perm[c]] = v;
     }
     __syncthreads();
   }
-  // ---- Mout[perm[s']][s] = X[s'][s]: Q column s = sum_s' W column perm[s'] * X[s'][s]
-  for (int e = tid; e < m * m; e += 256) {
-    const int a = e / m, s = e % m;   // a = column of W
-    const int sp = iperm[a];
-    double v = 0.0;
-    if (kept[sp] && kept[s] && sp <= s) v = S[a * m + perm[s]];
-    d.Mout[e] = v;
+  // ---- Mout[perm[i]][c] = X[i][c] for kept i <= c (Q column c = sum_a W column a * Mout[a][c])
+  if (owner) {
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      const int a = stripe + stripes * q;
+      if (a >= m) continue;
+      const double x = (kept[a] && kept[c] && a <= c) ? v[q] : 0.0;
+      d.Mout[perm[a] * m + c] = x;
+    }
   }
 }
 
 hipError_t launch_qr_factor(const QrDesc* dd, int nz, int maxm, const int32_t* act, hipStream_t st) {
-  const size_t lds = (size_t)maxm * maxm * 8 + (size_t)maxm * 3 * 8 + 256 * 8 + 256 * 4 + (size_t)maxm * 3 * 4 + 64;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = set_big_lds((const void*)k_qr_factor);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  const size_t lds = ((size_t)maxm * maxm + 4 * (size_t)maxm + 16 * (size_t)maxm + 16) * 8 + 16 * 4 +
+                     (size_t)maxm * 3 * 4 + 64;
   if (lds > kLdsCap) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_qr_factor, dim3(1, 1, nz), dim3(256), lds, st, dd, act);
-  return hipGetLastError();
+  const int ns = (maxm + (1024 / maxm) - 1) / (1024 / maxm);   // rows per thread
+  const void* kern;
+  int slot;
+  if (ns <= 1) { kern = (const void*)k_qr_factor<1>; slot = 0; }
+  else if (ns <= 2) { kern = (const void*)k_qr_factor<2>; slot = 1; }
+  else if (ns <= 5) { kern = (const void*)k_qr_factor<5>; slot = 2; }
+  else if (ns <= 9) { kern = (const void*)k_qr_factor<9>; slot = 3; }
+  else if (ns <= 14) { kern = (const void*)k_qr_factor<14>; slot = 4; }
+  else if (ns <= 19) { kern = (const void*)k_qr_factor<19>; slot = 5; }
+  else return hipErrorInvalidValue;
+  static bool attr[6] = {false, false, false, false, false, false};
+  if (!attr[slot]) {
+    hipError_t e = set_big_lds(kern);
+    if (e != hipSuccess) return e;
+    attr[slot] = true;
+  }
+  void* args[] = {(void*)&dd, (void*)&act};
+  return hipLaunchKernel(kern, dim3(1, 1, nz), dim3(1024), args, lds, st);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -372,214 +426,299 @@ hipError_t launch_diag(const DiagDesc* dd, int nz, int maxm, const int32_t* act,
 }
 
 // ---------------------------------------------------------------------------------------------
-// Shifted block-tridiagonal solve, one workgroup per (shift, system).
+// Shifted block-tridiagonal solve, one workgroup per (shift, system): block Thomas elimination
+// with explicit inverses of the SPD Schur complements (Gauss-Jordan in LDS, no pivoting).
 // Forward sweep over blocks j in [j0, j1):
-//   S_j = D_j + sigma I - V_{j-1}^T V_{j-1},  L_j L_j^T = S_j,
-//   z_j = L_j^{-1} (rhs_j - V_{j-1}^T z_{j-1}),  V_j = L_j^{-1} B_j^T
-// (B_j = T[j+1][j]; V_j^T = L_{j+1,j}), and optionally the residual estimate
-// || B_j y_j || = || V_j^T z_j || of the truncated solve (y_j = last block of the solution).
-// Backward sweep: y_j = L_j^{-T} (z_j - V_j y_{j+1}).
-// LDS: S (m*m) + panel (16*m) + z (m*r).
+//   S_j = D_j + sigma I - U_{j-1} B_{j-1}^T,   Sinv_j = S_j^{-1},   U_j = B_j Sinv_j,
+//   rhs'_0 = rhs,  rhs'_{j+1} = -U_j rhs'_j
+// with B_j = T[j+1][j].  The truncated solve over blocks 0..j has last block y_j = Sinv_j rhs'_j
+// and residual norm || B_j y_j || = || rhs'_{j+1} || (Lanczos relation), reported in est[j].
+// Backward sweep: y_{t-1} = Sinv_{t-1} rhs'_{t-1},  y_j = Sinv_j (rhs'_j - B_j^T y_{j+1}).
+// Storage: Lw[j] = Sinv_j, Xw[j] = U_j, Zw[j] = rhs'_j (block j+1 also written by block j).
+// LDS: S (m*m) always; B_j and U_j too when 3 m^2 + 2 m r doubles fit ("resident" mode).
 // ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_tri_forward(const TriDesc* __restrict__ descs, int j0, int j1,
-                                                     const int32_t* __restrict__ act) {
+// S[a][b] -= sum_u U[a][u] B[b][u] with U, B in global memory, through 8-row LDS panels.
+__device__ __forceinline__ void schur_update_paneled(double* S, int m, const double* U, const double* B, double* pa,
+                                                     double* pb, int tid) {
+  for (int a0 = 0; a0 < m; a0 += 8) {
+    const int na = min(8, m - a0);
+    for (int e = tid; e < 8 * m; e += 1024) pa[e] = (e / m) < na ? U[(int64_t)a0 * m + e] : 0.0;
+    for (int b0 = 0; b0 < m; b0 += 8) {
+      const int nb = min(8, m - b0);
+      for (int e = tid; e < 8 * m; e += 1024) pb[e] = (e / m) < nb ? B[(int64_t)b0 * m + e] : 0.0;
+      __syncthreads();
+      // 64 outputs, 16 lanes each over a sixteenth of u, reduced with shuffles
+      const int o = tid >> 4, part = tid & 15;
+      const int a = o >> 3, b = o & 7;
+      double acc = 0.0;
+#pragma unroll 2
+      for (int u = part; u < m; u += 16) acc += pa[a * m + u] * pb[b * m + u];
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) acc += __shfl_xor(acc, off, 64);
+      if (part == 0 && a < na && b < nb) S[(a0 + a) * m + b0 + b] -= acc;
+      __syncthreads();
+    }
+  }
+}
+
+// U[a][c] = sum_u B[a][u] Sinv[u][c] with B in global memory (8-row panels), Sinv in LDS.
+__device__ __forceinline__ void left_mul_paneled(double* Uout, int m, const double* B, const double* Sinv,
+                                                 double* pa, int tid) {
+  for (int a0 = 0; a0 < m; a0 += 8) {
+    const int na = min(8, m - a0);
+    for (int e = tid; e < 8 * m; e += 1024) pa[e] = (e / m) < na ? B[(int64_t)a0 * m + e] : 0.0;
+    __syncthreads();
+    for (int e = tid; e < na * m; e += 1024) {
+      const int a = e / m, c = e - a * m;
+      double acc = 0.0;
+#pragma unroll 2
+      for (int u = 0; u < m; ++u) acc += pa[a * m + u] * Sinv[u * m + c];
+      Uout[(int64_t)(a0 + a) * m + c] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// Block-Thomas forward sweep (see the comment above).  1024 threads; the Schur complement is
+// inverted register-resident by Gauss-Jordan: thread t owns column c = t % m and rows
+// stripe + stripes*q (stripe = t / m, stripes = 1024 / m); two barriers per pivot.  Products
+// run from LDS.
+template <int NS>
+__global__ __launch_bounds__(1024) void k_tri_forward(const TriDesc* __restrict__ descs, int j0, int j1, int lds_bytes,
+                                                      const int32_t* __restrict__ act) {
   const TriDesc d = descs[blockIdx.z];
   if (!is_active(act, d.active)) return;
   const int m = d.m, r = d.r, tid = threadIdx.x;
   const int64_t mm = (int64_t)m * m;
+  const int stripes = 1024 / m;
+  const int c = tid % m, stripe = tid / m;
+  const bool owner = stripe < stripes;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* S = (double*)smem_raw;      // m*m
-  double* pan = S + mm;               // 16*m
-  double* zb = pan + 16 * m;          // m*r
+  const bool resident = (int64_t)(3 * mm + 2 * m * r + 3 * m) * 8 <= lds_bytes;
+  double* S = (double*)smem_raw;                 // m*m: LDS image of S / S^-1
+  double* col = S + mm;                          // m
+  double* prow = col + m;                        // m
+  double* diag = prow + m;                       // m
+  double* zb = diag + m;                         // m*r: rhs'_j
+  double* zn = zb + m * r;                       // m*r: rhs'_{j+1}
+  double* Bl = zn + m * r;                       // resident: m*m (B_j); else 8*m panel
+  double* Ul = Bl + (resident ? mm : 8 * m);     // resident: m*m (U_j);  else 8*m panel
   __shared__ int s_fail;
-  __shared__ double s_red[256];
+  __shared__ double s_red[16];
+  double v[NS];
   if (tid == 0) s_fail = 0;
   for (int j = j0; j < j1; ++j) {
     const double* Dj = d.D + j * mm;
     const int32_t* mk = d.mask + (int64_t)j * m;
-    for (int e = tid; e < mm; e += 256) {
-      const int a = (int)(e / m), b = (int)(e % m);
-      double v = Dj[e];
-      if (mk[a] || mk[b]) v = (a == b) ? 1.0 : 0.0;
-      else if (a == b) v += d.sigma;
-      S[e] = v;
+    if (j > 0 && resident && j == j0) {
+      for (int e = tid; e < mm; e += 1024) {
+        Ul[e] = d.Xw[(j - 1) * mm + e];
+        Bl[e] = d.Bsub[(j - 1) * mm + e];
+      }
+    }
+    for (int e = tid; e < mm; e += 1024) S[e] = Dj[e];
+    if (j == j0) {
+      if (j == 0) {
+        for (int e = tid; e < m * r; e += 1024) zb[e] = d.rhs[(int64_t)(e / r) * d.ld_rhs + (e % r)];
+      } else {
+        for (int e = tid; e < m * r; e += 1024) zb[e] = d.Zw[(int64_t)j * m * r + e];
+      }
     }
     __syncthreads();
+    // S = D_j - U_{j-1} B_{j-1}^T
     if (j > 0) {
-      // S -= V_{j-1}^T V_{j-1}, V rows staged 16 at a time
-      const double* V = d.Xw + (j - 1) * mm;
-      for (int p0 = 0; p0 < m; p0 += 16) {
-        const int np = min(16, m - p0);
-        for (int e = tid; e < np * m; e += 256) pan[e] = V[(int64_t)p0 * m + e];
-        __syncthreads();
-        for (int e = tid; e < mm; e += 256) {
+      if (resident) {
+        for (int e = tid; e < mm; e += 1024) {
           const int a = (int)(e / m), b = (int)(e % m);
-          if (b > a) continue;
           double acc = 0.0;
-          for (int u = 0; u < np; ++u) acc += pan[u * m + a] * pan[u * m + b];
+#pragma unroll 2
+          for (int u = 0; u < m; ++u) acc += Ul[a * m + u] * Bl[b * m + u];
           S[e] -= acc;
         }
-        __syncthreads();
+      } else {
+        schur_update_paneled(S, m, d.Xw + (j - 1) * mm, d.Bsub + (j - 1) * mm, Bl, Ul, tid);
       }
-      for (int e = tid; e < mm; e += 256) {
-        const int a = (int)(e / m), b = (int)(e % m);
-        if (b > a) S[e] = S[(int64_t)b * m + a];
-      }
-      __syncthreads();
     }
-    // Cholesky (lower) in place
-    for (int s = 0; s < m; ++s) {
-      const double piv = S[s * m + s];
-      if (!(piv > 0.0)) {
-        if (tid == 0) s_fail = 1;
+    __syncthreads();
+    // registers: + sigma I, symmetrised, deflated indices decoupled with a unit diagonal
+    const bool mc = owner ? (mk[c] != 0) : false;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      const int a = stripe + stripes * q;
+      double x = 0.0;
+      if (owner && a < m) {
+        x = (a == c) ? S[a * m + c] + d.sigma : 0.5 * (S[a * m + c] + S[c * m + a]);
+        if (mc || mk[a]) x = (a == c) ? 1.0 : 0.0;
+        if (a == c) diag[a] = x;
       }
-      const double ls = sqrt(piv > 0.0 ? piv : 1.0);
+      v[q] = x;
+    }
+    __syncthreads();
+    // Gauss-Jordan inverse in registers
+    for (int p = 0; p < m; ++p) {
+      const double piv = diag[p];
+      const bool bad = !(piv > 0.0);
+      const double ipv = bad ? 0.0 : 1.0 / piv;
+      if (bad && tid == 0) s_fail = 1;
+      if (owner) {
+        const int ps = p % stripes, pq = p / stripes;
+        if (c == p) {
+#pragma unroll
+          for (int q = 0; q < NS; ++q) {
+            const int a = stripe + stripes * q;
+            if (a < m) col[a] = v[q];
+          }
+        }
+        if (stripe == ps) {
+#pragma unroll
+          for (int q = 0; q < NS; ++q)
+            if (q == pq) {
+              v[q] = (c == p) ? ipv : v[q] * ipv;
+              prow[c] = v[q];
+            }
+        }
+      }
       __syncthreads();
-      for (int i = s + 1 + tid; i < m; i += 256) S[i * m + s] /= ls;
-      if (tid == 0) S[s * m + s] = ls;
-      __syncthreads();
-      const int rem = m - s - 1;
-      for (int e = tid; e < rem * rem; e += 256) {
-        const int i = s + 1 + e / rem, c = s + 1 + e % rem;
-        if (c <= i) S[i * m + c] -= S[i * m + s] * S[c * m + s];
+      if (owner) {
+        const double pc = prow[c];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          const int a = stripe + stripes * q;
+          if (a >= m || a == p) continue;
+          v[q] = ((c == p) ? 0.0 : v[q]) - col[a] * pc;
+          if (a == c) diag[a] = v[q];
+        }
       }
       __syncthreads();
     }
     double* Lj = d.Lw + j * mm;
-    for (int e = tid; e < mm; e += 256) Lj[e] = S[e];
-    // right-hand side of block j
-    if (j == 0) {
-      for (int e = tid; e < m * r; e += 256) zb[e] = d.rhs[(int64_t)(e / r) * d.ld_rhs + (e % r)];
-    } else {
-      const double* V = d.Xw + (j - 1) * mm;
-      const double* zp = d.Zw + (int64_t)(j - 1) * m * r;
-      for (int e = tid; e < m * r; e += 256) {
-        const int a = e / r, c = e % r;
-        double acc = 0.0;
-        for (int u = 0; u < m; ++u) acc += V[(int64_t)u * m + a] * zp[u * r + c];
-        zb[e] = -acc;
+    if (owner) {
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        const int a = stripe + stripes * q;
+        if (a < m) {
+          S[a * m + c] = v[q];
+          Lj[a * m + c] = v[q];
+        }
       }
+    }
+    for (int e = tid; e < m * r; e += 1024) d.Zw[(int64_t)j * m * r + e] = zb[e];
+    const double* Bj = d.Bsub + j * mm;
+    double* Uj = d.Xw + j * mm;
+    if (resident) {
+      for (int e = tid; e < mm; e += 1024) Bl[e] = Bj[e];
     }
     __syncthreads();
-    // z_j = L^{-1} zb (column-oriented forward substitution)
-    for (int s = 0; s < m; ++s) {
-      for (int c = tid; c < r; c += 256) zb[s * r + c] /= S[s * m + s];
-      __syncthreads();
-      const int rem = m - s - 1;
-      for (int e = tid; e < rem * r; e += 256) {
-        const int i = s + 1 + e / r, c = e % r;
-        zb[i * r + c] -= S[i * m + s] * zb[s * r + c];
+    // U_j = B_j Sinv_j
+    if (resident) {
+      for (int e = tid; e < mm; e += 1024) {
+        const int a = (int)(e / m), cc = (int)(e % m);
+        double acc = 0.0;
+#pragma unroll 2
+        for (int u = 0; u < m; ++u) acc += Bl[a * m + u] * S[u * m + cc];
+        Ul[e] = acc;
+        Uj[e] = acc;
       }
       __syncthreads();
-    }
-    double* zj = d.Zw + (int64_t)j * m * r;
-    for (int e = tid; e < m * r; e += 256) zj[e] = zb[e];
-    // V_j = L^{-1} B_j^T, 16 columns of B_j^T (= rows of B_j) at a time
-    const double* Bj = d.Bsub + j * mm;
-    double* Vj = d.Xw + j * mm;
-    double est2 = 0.0;
-    for (int p0 = 0; p0 < m; p0 += 16) {
-      const int np = min(16, m - p0);
-      // pan[i][c] = B_j[p0 + c][i]
-      for (int e = tid; e < m * 16; e += 256) {
-        const int i = e / 16, c = e % 16;
-        pan[e] = c < np ? Bj[(int64_t)(p0 + c) * m + i] : 0.0;
-      }
-      __syncthreads();
-      for (int s = 0; s < m; ++s) {
-        for (int c = tid; c < 16; c += 256) pan[s * 16 + c] /= S[s * m + s];
-        __syncthreads();
-        const int rem = m - s - 1;
-        for (int e = tid; e < rem * 16; e += 256) {
-          const int i = s + 1 + e / 16, c = e % 16;
-          pan[i * 16 + c] -= S[i * m + s] * pan[s * 16 + c];
-        }
-        __syncthreads();
-      }
-      for (int e = tid; e < m * 16; e += 256) {
-        const int i = e / 16, c = e % 16;
-        if (c < np) Vj[(int64_t)i * m + p0 + c] = pan[e];
-      }
-      if (d.est) {
-        // (V_j^T z_j)[p0 + c][col] = sum_i pan[i][c] z[i][col]
-        for (int e = tid; e < np * r; e += 256) {
-          const int c = e / r, col = e % r;
-          double acc = 0.0;
-          for (int i = 0; i < m; ++i) acc += pan[i * 16 + c] * zb[i * r + col];
-          est2 += acc * acc;
-        }
-      }
+    } else {
+      left_mul_paneled(Uj, m, Bj, S, Bl, tid);
+      __threadfence();   // U_j is read back from global memory below and by the next block
       __syncthreads();
     }
-    if (d.est) {
-      s_red[tid] = est2;
-      __syncthreads();
-      for (int off = 128; off > 0; off >>= 1) {
-        if (tid < off) s_red[tid] += s_red[tid + off];
-        __syncthreads();
-      }
-      if (tid == 0) d.est[j] = sqrt(s_red[0]);
+    // rhs'_{j+1} = -U_j rhs'_j and its norm (the residual estimate of the truncated solve)
+    double sq = 0.0;
+    const double* Us = resident ? Ul : Uj;
+    for (int e = tid; e < m * r; e += 1024) {
+      const int a = e / r, cc = e % r;
+      double acc = 0.0;
+#pragma unroll 2
+      for (int u = 0; u < m; ++u) acc += Us[(int64_t)a * m + u] * zb[u * r + cc];
+      zn[e] = -acc;
+      sq += acc * acc;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off, 64);
+    if ((tid & 63) == 0) s_red[tid >> 6] = sq;
+    __syncthreads();
+    if (d.est && tid == 0) {
+      double t2 = 0.0;
+      for (int w = 0; w < 16; ++w) t2 += s_red[w];
+      d.est[j] = sqrt(t2);
+    }
+    for (int e = tid; e < m * r; e += 1024) {
+      zb[e] = zn[e];
+      d.Zw[(int64_t)(j + 1) * m * r + e] = zn[e];
     }
     __syncthreads();
   }
   if (tid == 0 && s_fail && d.fail) *d.fail = 1;
 }
 
-__global__ __launch_bounds__(256) void k_tri_backward(const TriDesc* __restrict__ descs, int t,
-                                                      const int32_t* __restrict__ act) {
+__global__ __launch_bounds__(1024) void k_tri_backward(const TriDesc* __restrict__ descs, int t,
+                                                       const int32_t* __restrict__ act) {
   const TriDesc d = descs[blockIdx.z];
   if (!is_active(act, d.active)) return;
   const int m = d.m, r = d.r, tid = threadIdx.x;
   const int64_t mm = (int64_t)m * m;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* S = (double*)smem_raw;   // L_j
-  double* yb = S + mm;             // current block (m*r)
-  double* yn = yb + m * r;         // next block y_{j+1} (m*r)
+  double* S = (double*)smem_raw;   // B_j, then Sinv_j
+  double* yb = S + mm;             // rhs'_j - B_j^T y_{j+1}
+  double* yn = yb + m * r;         // y_{j+1}
   for (int j = t - 1; j >= 0; --j) {
-    const double* Lj = d.Lw + j * mm;
-    for (int e = tid; e < mm; e += 256) S[e] = Lj[e];
     const double* zj = d.Zw + (int64_t)j * m * r;
     if (j == t - 1) {
-      for (int e = tid; e < m * r; e += 256) yb[e] = zj[e];
+      for (int e = tid; e < m * r; e += 1024) yb[e] = zj[e];
     } else {
-      const double* V = d.Xw + j * mm;
-      for (int e = tid; e < m * r; e += 256) {
+      const double* Bj = d.Bsub + j * mm;
+      for (int e = tid; e < mm; e += 1024) S[e] = Bj[e];
+      __syncthreads();
+      for (int e = tid; e < m * r; e += 1024) {
         const int a = e / r, c = e % r;
         double acc = 0.0;
-        for (int u = 0; u < m; ++u) acc += V[(int64_t)a * m + u] * yn[u * r + c];
+        for (int u = 0; u < m; ++u) acc += S[u * m + a] * yn[u * r + c];
         yb[e] = zj[e] - acc;
       }
     }
     __syncthreads();
-    // solve L^T y = yb (backward, column oriented)
-    for (int s = m - 1; s >= 0; --s) {
-      for (int c = tid; c < r; c += 256) yb[s * r + c] /= S[s * m + s];
-      __syncthreads();
-      for (int e = tid; e < s * r; e += 256) {
-        const int i = e / r, c = e % r;
-        yb[i * r + c] -= S[s * m + i] * yb[s * r + c];
-      }
-      __syncthreads();
-    }
-    for (int e = tid; e < m * r; e += 256) {
-      const int i = e / r, c = e % r;
-      d.Y[(int64_t)(j * m + i) * d.ldy + c] = yb[e];
-      yn[e] = yb[e];
+    const double* Lj = d.Lw + j * mm;
+    for (int e = tid; e < mm; e += 1024) S[e] = Lj[e];
+    __syncthreads();
+    for (int e = tid; e < m * r; e += 1024) {
+      const int a = e / r, c = e % r;
+      double acc = 0.0;
+      for (int u = 0; u < m; ++u) acc += S[a * m + u] * yb[u * r + c];
+      d.Y[(int64_t)(j * m + a) * d.ldy + c] = acc;
+      yn[e] = acc;
     }
     __syncthreads();
   }
 }
 
-
-
 hipError_t launch_tri_forward(const TriDesc* dd, int nz, int maxm, int maxr, int j0, int j1, const int32_t* act,
                               hipStream_t st) {
-  static bool attr = false;
-  if (!attr) { hipError_t e = set_big_lds((const void*)k_tri_forward); if (e != hipSuccess) return e; attr = true; }
-  const size_t lds = tri_forward_lds(maxm, maxr);
+  size_t lds = tri_forward_lds(maxm, maxr);
   if (lds > kLdsCap) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_tri_forward, dim3(1, 1, nz), dim3(256), lds, st, dd, j0, j1, act);
-  return hipGetLastError();
+  const size_t resident = ((size_t)3 * maxm * maxm + 2 * (size_t)maxm * maxr + 3 * (size_t)maxm) * 8;
+  if (resident <= kLdsCap) lds = std::max(lds, resident);
+  const int ns = (maxm + (1024 / maxm) - 1) / (1024 / maxm);   // rows per thread
+  const void* kern;
+  int slot;
+  if (ns <= 1) { kern = (const void*)k_tri_forward<1>; slot = 0; }
+  else if (ns <= 2) { kern = (const void*)k_tri_forward<2>; slot = 1; }
+  else if (ns <= 5) { kern = (const void*)k_tri_forward<5>; slot = 2; }
+  else if (ns <= 9) { kern = (const void*)k_tri_forward<9>; slot = 3; }
+  else if (ns <= 14) { kern = (const void*)k_tri_forward<14>; slot = 4; }
+  else if (ns <= 19) { kern = (const void*)k_tri_forward<19>; slot = 5; }
+  else return hipErrorInvalidValue;
+  static bool attr[6] = {false, false, false, false, false, false};
+  if (!attr[slot]) {
+    hipError_t e = set_big_lds(kern);
+    if (e != hipSuccess) return e;
+    attr[slot] = true;
+  }
+  int lb = (int)lds;
+  void* args[] = {(void*)&dd, (void*)&j0, (void*)&j1, (void*)&lb, (void*)&act};
+  return hipLaunchKernel(kern, dim3(1, 1, nz), dim3(1024), args, lds, st);
 }
 
 hipError_t launch_tri_backward(const TriDesc* dd, int nz, int maxm, int maxr, int t, const int32_t* act,
@@ -588,7 +727,7 @@ hipError_t launch_tri_backward(const TriDesc* dd, int nz, int maxm, int maxr, in
   if (!attr) { hipError_t e = set_big_lds((const void*)k_tri_backward); if (e != hipSuccess) return e; attr = true; }
   const size_t lds = tri_backward_lds(maxm, maxr);
   if (lds > kLdsCap) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_tri_backward, dim3(1, 1, nz), dim3(256), lds, st, dd, t, act);
+  hipLaunchKernelGGL(k_tri_backward, dim3(1, 1, nz), dim3(1024), lds, st, dd, t, act);
   return hipGetLastError();
 }
 

@@ -27,6 +27,8 @@
 
 namespace rbcg {
 bool sqrt_rule(double lo, double hi, int N, double* shifts, double* weights);
+hipError_t mv_f32(int tn, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act, hipStream_t st);
+hipError_t mv_f64(int tn, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act, hipStream_t st);
 }
 
 using namespace rbcg;
@@ -40,6 +42,15 @@ struct rbcg_ctx {
   void* pinned = nullptr;   // host staging (descriptors, flags)
   size_t pinned_cap = 0;
   hipEvent_t ev[2] = {nullptr, nullptr};
+  hipStream_t side = nullptr;        // convergence monitor, overlapped with the next step
+  hipEvent_t ev_mon = nullptr;
+  // block-product timing (rbcg_profile): event pairs around each block-product GEMM launch
+  bool prof = false;
+  std::vector<hipEvent_t> prof_pool;
+  size_t prof_used = 0;
+  std::vector<double> prof_flops, prof_bytes;
+  int64_t prof_launches = 0;
+  double prof_ms = 0.0, prof_flops_total = 0.0, prof_bytes_total = 0.0;
 };
 
 struct rbcg_op {
@@ -97,7 +108,9 @@ extern "C" int rbcg_create(rbcg_ctx** out, void* stream) {
   c->device = dev;
   c->stream = (hipStream_t)stream;
   if (hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_mon, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
     delete c;
     return RBCG_ERR_HIP;
   }
@@ -111,11 +124,37 @@ extern "C" int rbcg_destroy(rbcg_ctx* c) {
   if (c->pinned) (void)hipHostFree(c->pinned);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& e : c->prof_pool) (void)hipEventDestroy(e);
+  if (c->ev_mon) (void)hipEventDestroy(c->ev_mon);
+  if (c->side) (void)hipStreamDestroy(c->side);
   delete c;
   return RBCG_OK;
 }
 
 extern "C" int64_t rbcg_workspace_bytes(const rbcg_ctx* c) { return c ? (int64_t)c->ws_cap : 0; }
+
+extern "C" int rbcg_profile(rbcg_ctx* c, int enable) {
+  if (!c) return RBCG_ERR_INVALID_ARG;
+  c->prof = enable != 0;
+  c->prof_used = 0;
+  c->prof_flops.clear();
+  c->prof_bytes.clear();
+  if (enable) {
+    c->prof_launches = 0;
+    c->prof_ms = c->prof_flops_total = c->prof_bytes_total = 0.0;
+  }
+  return RBCG_OK;
+}
+
+extern "C" int rbcg_profile_read(const rbcg_ctx* c, int64_t* launches, double* ms_total, double* flops_total,
+                                 double* bytes_total) {
+  if (!c || !launches || !ms_total || !flops_total || !bytes_total) return RBCG_ERR_INVALID_ARG;
+  *launches = c->prof_launches;
+  *ms_total = c->prof_ms;
+  *flops_total = c->prof_flops_total;
+  *bytes_total = c->prof_bytes_total;
+  return RBCG_OK;
+}
 
 // ---------------------------------------------------------------------------- operators
 extern "C" int rbcg_op_create_dense(rbcg_ctx* ctx, rbcg_op** out, int64_t d, const double* A, int64_t lda, int lo) {
@@ -308,11 +347,56 @@ struct Launch {
   int nz = 0;
   int a0 = 0, a1 = 0, a2 = 0, a3 = 0;   // kind-specific sizes
   bool flag = false;
+  bool prof = false;                    // a block-product GEMM (timed by rbcg_profile)
+  double flops = 0.0, bytes = 0.0;      // its algorithmic flops and HBM bytes
 };
+
+// Event pair around a profiled launch; elapsed times are collected after the call's final sync.
+static hipError_t prof_begin(rbcg_ctx* c, const Launch& L, hipStream_t st) {
+  if (!c->prof || !L.prof) return hipSuccess;
+  if (c->prof_used + 2 > c->prof_pool.size()) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      hipError_t er = hipEventCreate(&e);
+      if (er != hipSuccess) return er;
+      c->prof_pool.push_back(e);
+    }
+  }
+  c->prof_flops.push_back(L.flops);
+  c->prof_bytes.push_back(L.bytes);
+  return hipEventRecord(c->prof_pool[c->prof_used], st);
+}
+static hipError_t prof_end(rbcg_ctx* c, const Launch& L, hipStream_t st) {
+  if (!c->prof || !L.prof) return hipSuccess;
+  hipError_t e = hipEventRecord(c->prof_pool[c->prof_used + 1], st);
+  c->prof_used += 2;
+  return e;
+}
+static void prof_collect(rbcg_ctx* c) {
+  if (!c->prof) return;
+  for (size_t i = 0; i + 1 < c->prof_used; i += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->prof_pool[i], c->prof_pool[i + 1]) == hipSuccess) {
+      c->prof_ms += ms;
+      c->prof_launches += 1;
+      c->prof_flops_total += c->prof_flops[i / 2];
+      c->prof_bytes_total += c->prof_bytes[i / 2];
+    }
+  }
+  c->prof_used = 0;
+  c->prof_flops.clear();
+  c->prof_bytes.clear();
+}
 
 static hipError_t enqueue(const Launch& L, unsigned char* dbase, const int32_t* act, hipStream_t st) {
   switch (L.kind) {
     case Launch::NT:
+      if (L.a0 & (1 << 9)) {   // tall block product (64-row tiles, X staged in LDS)
+        const int tn = (L.a2 + 15) / 16;
+        const bool pvec = (L.a0 >> 10) & 1;
+        return (L.a0 & 0xff) == DT_F32 ? mv_f32(tn, pvec, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a3, act, st)
+                                       : mv_f64(tn, pvec, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a3, act, st);
+      }
       return launch_gemm_nt_ex(L.a0 & 0xff, (L.a0 >> 8) & 1, L.flag, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a2,
                                L.a3, act, st);
     case Launch::FIN: return launch_finish(dptr<FinDesc>(dbase, L.off), L.nz, L.a1, L.a2, act, st);
@@ -332,7 +416,7 @@ static hipError_t enqueue(const Launch& L, unsigned char* dbase, const int32_t* 
 struct Program {
   Staging stg;
   std::vector<std::vector<Launch>> steps;   // steps[0] = start block, steps[j+1] = Lanczos step j
-  std::vector<Launch> mon;                  // per step j: monitor launches (appended in steps)
+  std::vector<std::vector<Launch>> mon;     // mon[j]: monitor of step j (runs on the side stream)
 };
 
 // Build NT descriptors "rows [0, M) of basis p against block rows X" for all problems.
@@ -506,14 +590,15 @@ static void add_rmul(Program& pg, std::vector<Launch>& out, Engine& E, int slot,
 // Two rounds of pivoted Cholesky QR of block slot `slot`; the second writes the basis mask of
 // that slot and the coefficient block (R0 for the start block, B_j afterwards).
 static void add_cholqr(Program& pg, std::vector<Launch>& out, Engine& E, int slot, const double* const* pre,
-                       double** coef, bool start) {
-  add_gram(pg, out, E, slot);
+                       double** coef, bool start, const double* const* g1 = nullptr) {
+  // first pass: the Gram matrix comes with the second projection (g1) or is formed here
+  if (!g1) add_gram(pg, out, E, slot);
   {
     std::vector<QrDesc> qr;
     for (size_t p = 0; p < E.P.size(); ++p) {
       const Prob& pr = E.P[p];
       QrDesc d{};
-      d.G = pr.G;
+      d.G = g1 ? g1[p] : pr.G;
       d.ldg = pr.m;
       d.pre = pre ? pre[p] : nullptr;
       d.pre_stride = pr.m + 1;
@@ -615,10 +700,14 @@ static void add_matvec(Program& pg, std::vector<Launch>& out, Engine& E, int j) 
       Launch L{Launch::NT};
       L.off = pg.stg.add(std::vector<NtDesc>{nd});
       L.nz = 1;
-      L.a0 = dtype | (1 << 8);
+      const bool pvec = dtype == DT_F32 || (op->ld % 2 == 0 && ((uintptr_t)op->data % 16) == 0);
+      L.a0 = dtype | (1 << 8) | (G.N <= 144 ? (1 << 9) : 0) | (pvec ? (1 << 10) : 0);
       L.a1 = d;
       L.a2 = G.N;
       L.a3 = splits;
+      L.prof = true;
+      L.flops = 2.0 * d * (double)d * G.N;
+      L.bytes = (double)d * d * (dtype == DT_F32 ? 4.0 : 8.0);
       out.push_back(L);
       if (splits > 1) {
         FinDesc f{};
@@ -673,6 +762,9 @@ static void add_matvec(Program& pg, std::vector<Launch>& out, Engine& E, int j) 
         L1.a1 = n;
         L1.a2 = G.N;
         L1.a3 = 1;
+        L1.prof = true;
+        L1.flops = 2.0 * n * (double)d * G.N;
+        L1.bytes = 2.0 * n * (double)d;
         out.push_back(L1);
         NtDesc n2{};
         n2.P = plain_rows(op->lot, op->ld_lot);
@@ -693,6 +785,9 @@ static void add_matvec(Program& pg, std::vector<Launch>& out, Engine& E, int j) 
         L2.a1 = d;
         L2.a2 = G.N;
         L2.a3 = splits;
+        L2.prof = true;
+        L2.flops = 2.0 * n * (double)d * G.N;
+        L2.bytes = 2.0 * n * (double)d;
         out.push_back(L2);
         if (splits > 1) {
           FinDesc f{};
@@ -804,6 +899,7 @@ static void add_monitor(Program& pg, std::vector<Launch>& out, Engine& E, int j,
 static void build_program(Program& pg, Engine& E, const std::vector<double>& tol, bool monitor,
                           std::vector<CopyDesc>& start_copies, int max_start_rows) {
   pg.steps.assign(E.t_max + 1, {});
+  pg.mon.assign(E.t_max, {});
   // start block: caller-provided copies into block 0, then Cholesky QR (R0 = coefficients)
   {
     auto& out = pg.steps[0];
@@ -832,7 +928,9 @@ static void build_program(Program& pg, Engine& E, const std::vector<double>& tol
     }
     add_proj(pg, out, E, j, true, c1.data());
     add_update(pg, out, E, j, c1.data());
-    add_proj(pg, out, E, j, false, c2.data());
+    // second pass also returns W^T W of the once-projected block: the Gram of the first
+    // Cholesky QR pass (the second update changes W only at rounding level)
+    add_proj(pg, out, E, j, true, c2.data());
     add_update(pg, out, E, j, c2.data());
     {
       std::vector<DiagDesc> dd;
@@ -855,8 +953,10 @@ static void build_program(Program& pg, Engine& E, const std::vector<double>& tol
       L.a1 = E.maxm;
       out.push_back(L);
     }
-    add_cholqr(pg, out, E, j + 1, pre.data(), coef.data(), false);
-    if (monitor) add_monitor(pg, out, E, j, tol);
+    std::vector<const double*> g1(E.P.size());
+    for (size_t p = 0; p < E.P.size(); ++p) g1[p] = E.P[p].C2 + (int64_t)(j + 1) * E.P[p].m * E.P[p].m;
+    add_cholqr(pg, out, E, j + 1, pre.data(), coef.data(), false, g1.data());
+    if (monitor) add_monitor(pg, pg.mon[j], E, j, tol);
   }
 }
 
@@ -881,6 +981,9 @@ static void size_partials(Engine& E) {
     int Kp = (G.op->kind == RBCG_OP_GRAM && G.mv_t == RBCG_BF16) ? (int)G.op->n : d;
     if (G.op->kind == RBCG_OP_GRAM && G.mv_t != RBCG_BF16) {
       G.splits2 = 1;
+    } else if (G.op->kind == RBCG_OP_DENSE && G.N <= 144) {
+      const int t64 = (d + 63) / 64;
+      G.splits2 = std::max(1, std::min(std::max(1, 512 / t64), std::max(1, d / 512)));
     } else {
       G.splits2 = pick_splits(tiles, 1, Kp);
     }
@@ -927,7 +1030,7 @@ static void carve(Arena& ar, Engine& E) {
     pr.part = pr.part_elems ? ar.take<double>(pr.part_elems) : nullptr;
     pr.Lw = ar.take<double>(T * mm);
     pr.Xw = ar.take<double>(T * mm);
-    pr.Zw = ar.take<double>(T * pr.m);
+    pr.Zw = ar.take<double>((T + 1) * pr.m);
     pr.est = ar.take<double>(T);
     pr.scale = ar.take<double>(1);
     pr.ybuf = ar.take<double>(T * pr.m);
@@ -974,10 +1077,21 @@ static int run_steps(rbcg_ctx* ctx, Engine& E, Program& pg, unsigned char* dbase
   hipStream_t st = ctx->stream;
   const int np = (int)E.P.size();
   for (const auto& L : pg.steps[0]) HIP_TRY(enqueue(L, dbase, E.active, st));
+  auto run = [&](const Launch& L) -> hipError_t {
+    hipError_t e = prof_begin(ctx, L, st);
+    if (e == hipSuccess) e = enqueue(L, dbase, E.active, st);
+    if (e == hipSuccess) e = prof_end(ctx, L, st);
+    return e;
+  };
   int32_t* flags_h = E.active_h;
   int j = 0;
   for (; j < E.t_max; ++j) {
-    for (const auto& L : pg.steps[j + 1]) HIP_TRY(enqueue(L, dbase, E.active, st));
+    for (const auto& L : pg.steps[j + 1]) HIP_TRY(run(L));
+    if (!pg.mon[j].empty()) {
+      HIP_TRY(hipEventRecord(ctx->ev_mon, st));
+      HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->ev_mon, 0));
+      for (const auto& L : pg.mon[j]) HIP_TRY(enqueue(L, dbase, E.active, ctx->side));
+    }
     // read the flags of this step asynchronously; decide on the previous step's copy
     int32_t* dst = flags_h + (j & 1) * np;
     HIP_TRY(hipMemcpyAsync(dst, E.active, np * sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -991,6 +1105,8 @@ static int run_steps(rbcg_ctx* ctx, Engine& E, Program& pg, unsigned char* dbase
     }
   }
   HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipStreamSynchronize(ctx->side));
+  prof_collect(ctx);
   *steps_run = j;
   return RBCG_OK;
 }
@@ -1461,7 +1577,7 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
     sq_dev = a.take<double>(L);
     Lws = a.take<double>(L * T * mm);
     Xws = a.take<double>(L * T * mm);
-    Zws = a.take<double>(L * T * m);
+    Zws = a.take<double>(L * (T + 1) * m);
     Yall = a.take<double>(T * m * L);
     Bhat = a.take<double>((size_t)L * m);
     failL = a.take<int32_t>(L);
@@ -1585,7 +1701,7 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
       td.ld_rhs = m;
       td.Lw = Lws + l * T * mm;
       td.Xw = Xws + l * T * mm;
-      td.Zw = Zws + l * T * m;
+      td.Zw = Zws + l * (T + 1) * m;
       td.Y = Yall + l;
       td.ldy = L;
       td.est = nullptr;
@@ -1700,7 +1816,7 @@ extern "C" int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, con
     const size_t nz = std::max((size_t)ngroups * nq, (size_t)ngroups * ntr);
     Lws = a.take<double>(nz * T * mm);
     Xws = a.take<double>(nz * T * mm);
-    Zws = a.take<double>(nz * T * mm);
+    Zws = a.take<double>(nz * (T + 1) * mm);
     Ynodes = a.take<double>((size_t)ngroups * nq * T * mm);
     Ybar = a.take<double>((size_t)ngroups * T * mm);
     Cq = a.take<double>((size_t)ngroups * (T + 1) * mm);
@@ -1806,7 +1922,7 @@ extern "C" int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, con
           td.rhs = nullptr;
           td.Lw = Lws + ((size_t)g * ntr + i) * T * mm;
           td.Xw = Xws + ((size_t)g * ntr + i) * T * mm;
-          td.Zw = Zws + ((size_t)g * ntr + i) * T * mm;
+          td.Zw = Zws + ((size_t)g * ntr + i) * (T + 1) * mm;
           td.fail = failT + g * ntr + i;
           td.sigma = -tau;
           td.m = m;
@@ -1853,7 +1969,7 @@ extern "C" int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, con
         td.ld_rhs = m;
         td.Lw = Lws + z * T * mm;
         td.Xw = Xws + z * T * mm;
-        td.Zw = Zws + z * T * mm;
+        td.Zw = Zws + z * (T + 1) * mm;
         td.Y = Ynodes + z * T * mm;
         td.ldy = m;
         td.fail = failN + z;

@@ -99,17 +99,18 @@ struct DiagDesc {
 
 // Shifted block-tridiagonal solve (T_t + sigma I) Y = RHS with RHS nonzero
 // only in the first block row.  Blocks: D[j] (diagonal, m x m), Bsub[j]
-// (T[j+1][j], m x m), masks per block.  Workspace holds L_jj, X_j =
-// L_{j+1,j} and the forward iterates per block.
+// (T[j+1][j], m x m), masks per block.  Workspace per block: Lw = S_j^{-1}
+// (inverse Schur complement), Xw = U_j = B_j S_j^{-1}, Zw = eliminated
+// right-hand side (t + 1 blocks of m x r).
 struct TriDesc {
   const double* D;         // t blocks of m*m
   const double* Bsub;      // t blocks of m*m (block j couples j+1 to j)
   const int32_t* mask;     // t*m deflation flags
   const double* rhs;       // m x r (first block of the right-hand side), row stride ld_rhs
   int64_t ld_rhs;
-  double* Lw;              // workspace: t blocks of m*m (Cholesky factors)
-  double* Xw;              // workspace: t blocks of m*m (sub-diagonal factors)
-  double* Zw;              // workspace: t blocks of m*r (forward iterates)
+  double* Lw;              // workspace: t blocks of m*m (inverse Schur complements)
+  double* Xw;              // workspace: t blocks of m*m (B_j S_j^{-1})
+  double* Zw;              // workspace: t+1 blocks of m*r (eliminated right-hand sides)
   double* Y;               // output rows (block j row i at Y[(j*m + i) * ldy + c])
   int64_t ldy;
   double* est;             // residual estimate output (monitor) or null
@@ -146,7 +147,7 @@ hipError_t launch_tri_forward(const TriDesc* d_desc, int nz, int maxm, int maxr,
 hipError_t launch_tri_backward(const TriDesc* d_desc, int nz, int maxm, int maxr, int t,
                                const int32_t* active, hipStream_t st);
 // LDS bytes the two sweeps need for block width m and r right-hand sides.
-inline size_t tri_forward_lds(int m, int r) { return ((size_t)m * m + 16 * (size_t)m + (size_t)m * r) * 8; }
+inline size_t tri_forward_lds(int m, int r) { return ((size_t)m * m + 19 * (size_t)m + 2 * (size_t)m * r) * 8; }
 inline size_t tri_backward_lds(int m, int r) { return ((size_t)m * m + 2 * (size_t)m * r) * 8; }
 constexpr size_t kLdsCap = 160 * 1024 - 4096;
 hipError_t launch_convert(const CvtDesc* d_desc, int nz, int maxRows, int maxCols,

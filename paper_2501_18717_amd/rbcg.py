@@ -68,6 +68,8 @@ _path = _sig("rbcg_path", ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i64, _dp, _v
 _sqrt = _sig("rbcg_sqrt_apply", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)])
 _ws_bytes = _sig("rbcg_workspace_bytes", _i64, [_vp])
 _sqrt_rule = _sig("rbcg_sqrt_rule", ctypes.c_int, [ctypes.c_double, ctypes.c_double, _i32, _dp, _dp])
+_profile = _sig("rbcg_profile", ctypes.c_int, [_vp, ctypes.c_int])
+_profile_read = _sig("rbcg_profile_read", ctypes.c_int, [_vp, ctypes.POINTER(_i64), _dp, _dp, _dp])
 
 
 class RbcgError(RuntimeError):
@@ -136,6 +138,17 @@ class Context:
 
     def workspace_bytes(self) -> int:
         return int(_ws_bytes(self._h))
+
+    def profile(self, enable: bool):
+        """Start (clearing counters) or stop event timing of the block-product GEMMs."""
+        _check(_profile(self._h, 1 if enable else 0), "rbcg_profile")
+
+    def profile_read(self) -> dict:
+        n = _i64()
+        ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(_profile_read(self._h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by)),
+               "rbcg_profile_read")
+        return {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
 
     def close(self):
         if getattr(self, "_h", None):

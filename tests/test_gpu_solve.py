@@ -1,9 +1,11 @@
 """GPU parity of rbcg_solve (through the C ABI) against the FP64 CPU oracle.
 
 Tolerances: plain FP64 block-CG iterates must match the oracle's iterate at
-the same t to a relative A_mu-norm difference of 1e-12 (1e-11 where the
-oracle's own error floor is higher); mixed precision with FP64 refinement
-must match the converged oracle solution to 1e-8.
+the same t to a relative A_mu-norm difference of max(1e-12, 1e-15 kappa),
+kappa = cond(A + mu I): two correct FP64 implementations that round
+differently agree only to about kappa times the unit roundoff on
+ill-conditioned systems.  Mixed precision with FP64 refinement must match
+the converged oracle solution to 1e-8.
 """
 import numpy as np
 import pytest
@@ -82,7 +84,8 @@ def test_ragged_shapes(R, d, k, t, p, mu):
     rc, info, x = _solve_one(R, A, mu, b, Om, t)
     assert rc == 0, info
     X, _ = ob.bcg(A, [mu], b, Om if k else None, t)
-    assert a_err(A, mu, x, X[0]) < 1e-11
+    kappa = (lam[0] + mu) / (lam[-1] + mu)
+    assert a_err(A, mu, x, X[0]) < max(1e-12, 1e-15 * kappa)
 
 
 def test_batched_uneven_systems_match_one_at_a_time(R):
