@@ -223,6 +223,75 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
   int* kept = chosen + m;                    // m: per pivot position
   __shared__ int s_rank;
 
+  // ---- second pass on a near-identity Gram: G = I + E over the non-zero columns with
+  //      max |E| <= 1e-8 gives R = I + F (F = upper part of E, halved diagonal) and
+  //      R^{-1} = I - F, both exact to O(|E|^2) = rounding level; no sequential factorization.
+  if (!d.pivot && d.prevB) {
+    __shared__ int s_small;
+    __shared__ double s_wmax[16];
+    double emax = 0.0;
+    for (int e = tid; e < m * m; e += 1024) {
+      const int a = e / m, cc = e - a * m;
+      const double ga = d.G[(int64_t)a * d.ldg + a], gc = d.G[(int64_t)cc * d.ldg + cc];
+      if (ga == 0.0 || gc == 0.0) continue;   // deflated (zero) columns
+      const double g = d.G[(int64_t)a * d.ldg + cc];
+      emax = fmax(emax, fabs(g - (a == cc ? 1.0 : 0.0)));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) emax = fmax(emax, __shfl_xor(emax, off, 64));
+    if (lane == 0) s_wmax[wave] = emax;
+    __syncthreads();
+    if (tid == 0) {
+      double mx = 0.0;
+      for (int w = 0; w < 16; ++w) mx = fmax(mx, s_wmax[w]);
+      s_small = mx <= 1e-8;
+    }
+    __syncthreads();
+    if (s_small) {
+      // kept[i] = column i non-zero; F in Rl (upper), Bout = (I + F) prevB, Mout = I - F
+      for (int i = tid; i < m; i += 1024) kept[i] = d.G[(int64_t)i * d.ldg + i] != 0.0;
+      __syncthreads();
+      for (int e = tid; e < m * m; e += 1024) {
+        const int a = e / m, cc = e - a * m;
+        double f = 0.0;
+        if (kept[a] && kept[cc] && cc >= a) {
+          const double g = d.G[(int64_t)a * d.ldg + cc];
+          f = (a == cc) ? 0.5 * (g - 1.0) : g;
+        }
+        Rl[e] = f;
+        d.Mout[e] = (kept[a] && kept[cc]) ? ((a == cc ? 1.0 : 0.0) - f) : 0.0;
+      }
+      for (int i = tid; i < m; i += 1024) d.mask[i] = kept[i] ? 0 : 1;
+      if (tid == 0 && d.rank_out) {
+        int rk = 0;
+        for (int i = 0; i < m; ++i) rk += kept[i];
+        *d.rank_out = rk;
+      }
+      __syncthreads();
+      for (int c0 = 0; c0 < m; c0 += 16) {
+        const int nc = min(16, m - c0);
+        for (int e = tid; e < m * 16; e += 1024) {
+          const int u = e >> 4, cc = e & 15;
+          pan[e] = cc < nc ? d.prevB[u * m + c0 + cc] : 0.0;
+        }
+        __syncthreads();
+        for (int e = tid; e < m * 16; e += 1024) {
+          const int s0 = e >> 4, cc = e & 15;
+          if (cc >= nc) continue;
+          double acc = 0.0;
+          if (kept[s0]) {
+            acc = pan[s0 * 16 + cc];
+            const double* Fs = Rl + s0 * m;
+            for (int u = s0; u < m; ++u) acc += Fs[u] * pan[u * 16 + cc];
+          }
+          d.Bout[s0 * m + c0 + cc] = acc;
+        }
+        __syncthreads();
+      }
+      return;
+    }
+  }
+
   double v[NS];
 #pragma unroll
   for (int q = 0; q < NS; ++q) {
@@ -246,21 +315,19 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
   for (; s < m; ++s) {
     int p = s;
     if (d.pivot && !(d.force_first && s == 0)) {
-      double best = -2.0;
-      int bi = 0x7fffffff;
-      if (tid < m && !chosen[tid]) {
-        best = dref[tid] > 0.0 ? diag[tid] / dref[tid] : -1.0;
-        bi = tid;
+      if (wave == 0) {
+        double best = -2.0;
+        int bi = 0x7fffffff;
+        for (int cc = lane; cc < m; cc += 64) {
+          if (chosen[cc]) continue;
+          const double rel = dref[cc] > 0.0 ? diag[cc] / dref[cc] : -1.0;
+          if (rel > best || (rel == best && cc < bi)) { best = rel; bi = cc; }
+        }
+        wave_argmax(best, bi);
+        if (lane == 0) wi[0] = bi;
       }
-      wave_argmax(best, bi);
-      if (lane == 0) { wv[wave] = best; wi[wave] = bi; }
       __syncthreads();
-      best = wv[0];
-      bi = wi[0];
-#pragma unroll
-      for (int w = 1; w < 16; ++w)
-        if (wv[w] > best || (wv[w] == best && wi[w] < bi)) { best = wv[w]; bi = wi[w]; }
-      p = bi;
+      p = wi[0];
     }
     const double piv2 = diag[p];
     bool defl;
@@ -750,11 +817,14 @@ __global__ __launch_bounds__(256) void k_convert(const CvtDesc* __restrict__ des
     } else if (!d.split_lo) {
       ((unsigned short*)d.dst.p)[row_off(d.dst, rr) + c] = f32_to_bf16((float)v);
     } else {
-      const float f = (float)v;
-      const unsigned short hi = f32_to_bf16(f);
-      const unsigned short lo = f32_to_bf16((float)(v - (double)bf16_to_f32(hi)));
-      ((unsigned short*)d.dst.p)[row_off(d.dst, 2 * rr) + c] = hi;
-      ((unsigned short*)d.dst.p)[row_off(d.dst, 2 * rr + 1) + c] = lo;
+      // three BF16 parts of the FP64 value (about 24 significant bits)
+      const unsigned short hi = f32_to_bf16((float)v);
+      const double r1 = v - (double)bf16_to_f32(hi);
+      const unsigned short mid = f32_to_bf16((float)r1);
+      const unsigned short lo = f32_to_bf16((float)(r1 - (double)bf16_to_f32(mid)));
+      ((unsigned short*)d.dst.p)[row_off(d.dst, 3 * rr) + c] = hi;
+      ((unsigned short*)d.dst.p)[row_off(d.dst, 3 * rr + 1) + c] = mid;
+      ((unsigned short*)d.dst.p)[row_off(d.dst, 3 * rr + 2) + c] = lo;
     }
   }
 }

@@ -298,7 +298,7 @@ struct MvGroup {
   int mv_t = RBCG_F64;       // block-product precision
   void* xlo = nullptr;       // low-precision copy of the current block
   int64_t ld_xlo = 0;
-  void* ylo = nullptr;       // gram: BF16 pair copy of Z X (2N x ld_ylo)
+  void* ylo = nullptr;       // gram: three-part BF16 copy of Z X (3N x ld_ylo)
   int64_t ld_ylo = 0;
   double* ys = nullptr;      // gram FP64: Z X (n x N)
   double* part = nullptr;
@@ -1002,9 +1002,9 @@ static void carve(Arena& ar, Engine& E) {
       G.xlo = ar.take<float>((size_t)G.N * ldv);
     } else if (G.mv_t == RBCG_BF16) {
       G.ld_xlo = ldv;
-      G.xlo = ar.take<unsigned short>((size_t)2 * G.N * ldv);
+      G.xlo = ar.take<unsigned short>((size_t)3 * G.N * ldv);
       G.ld_ylo = round_up(G.op->n, 64);
-      G.ylo = ar.take<unsigned short>((size_t)2 * G.N * G.ld_ylo);
+      G.ylo = ar.take<unsigned short>((size_t)3 * G.N * G.ld_ylo);
     } else if (G.op->kind == RBCG_OP_GRAM) {
       G.ys = ar.take<double>((size_t)G.op->n * G.N);
     }

@@ -33,7 +33,7 @@ struct NtDesc {
   RowOp O;                   // direct transposed output: row c, element i (when out == null)
   double* out;               // direct row-major output out[i * ldo + c]
   int64_t ldo;
-  int32_t out_t, pad_;       // element type of O: DType, or 3 = BF16 hi/lo pair (rows 2c, 2c+1)
+  int32_t out_t, pad_;       // element type of O: DType, or 3 = three BF16 parts (rows 3c, 3c+1, 3c+2)
 };
 
 // Reduction of the split-K partials with an epilogue.
@@ -125,7 +125,7 @@ struct CvtDesc {
   RowOp src;  // FP64 or FP32 rows
   RowOp dst;
   int32_t rows, cols, src_t, dst_t;
-  int32_t active, split_lo, pad0, pad1;   // split_lo: write hi/lo BF16 pairs (dst rows 2r, 2r+1)
+  int32_t active, split_lo, pad0, pad1;   // split_lo: write three BF16 parts (dst rows 3r, 3r+1, 3r+2)
 };
 
 // ---------------------------------------------------------------- launchers

@@ -1,0 +1,189 @@
+"""GPU parity of rbcg_path (regularization path, dense and Gram operators) and
+rbcg_sqrt_apply (block-Lanczos square root) against the FP64 CPU oracle, all
+through the C ABI.
+
+Tolerances: path iterates vs the oracle's bcg_t at every shift to
+max(1e-12, 1e-15 kappa(A_mu)) in the A_mu-norm (plain FP64); mixed BF16 Gram
+products with FP64 refinement vs the dense ridge solution to 1e-8.  The
+square root is compared with the oracle's closed form A Q T^{-1/2} Q^T B; the
+GPU integrates with a 32-node conformal-map rule on its own Ritz interval,
+whose error is below 1e-10 for these spectra, so the bound is 1e-9 relative
+per sample.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import block_cg as ob
+from oracle import truth as ot
+
+from gpu_util import a_err, note, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_18717_amd import rbcg
+    return rbcg, rbcg.Context()
+
+
+def _path(R, op, b, Om, mus, t, **kw):
+    import torch
+    rbcg, ctx = R
+    bd = to_dev(b)
+    om = to_dev(Om) if Om is not None and len(Om) else None
+    X = torch.zeros((len(mus), b.shape[0]), dtype=torch.float64, device="cuda")
+    rc, info = rbcg.path(ctx, op, bd, om, list(mus), X, rbcg.opts(t, **kw), check=False)
+    torch.cuda.synchronize()
+    return rc, info, X.cpu().numpy()
+
+
+@pytest.mark.parametrize("d,k,t,L", [(400, 15, 6, 8), (333, 20, 4, 5), (256, 31, 9, 16)])
+def test_dense_path_matches_oracle_every_shift(R, d, k, t, L):
+    """One Krylov space, L shifts (eq. bcg_alg): every shift equals the
+    oracle's iterate from the same space."""
+    rbcg, ctx = R
+    note(f"dense path d={d} k={k} t={t} L={L}")
+    g = np.random.default_rng(d)
+    lam = np.arange(1, d + 1, dtype=float) ** (-1.5)
+    A = synth.spd_from_spectrum(lam, g)
+    b = g.standard_normal(d)
+    Om = g.standard_normal((k, d))
+    mus = np.logspace(-5, 0, L)
+    op = rbcg.DenseOperator(ctx, to_dev(A))
+    rc, info, X = _path(R, op, b, Om, mus, t)
+    assert rc == 0, info
+    Xo, _ = ob.bcg(A, mus, b, Om, t)
+    for i, mu in enumerate(mus):
+        kappa = (lam[0] + mu) / (lam[-1] + mu)
+        assert a_err(A, mu, X[i], Xo[i]) < max(1e-12, 1e-15 * kappa), (i, mu)
+
+
+@pytest.fixture(scope="module")
+def ridge_small():
+    """A scaled-down ridge problem with the same construction as the
+    200000 x 4096 workload: Z = G diag(exp(-j/decay)), FP32."""
+    return synth.ridge_problem(3, 6000, 384, 63, decay=40.0, L=12)
+
+
+def test_gram_path_fp64_exact_termination(R, ridge_small):
+    """Gram operator Z^T (Z X) with FP64 arithmetic on the FP32 values of Z;
+    64 * 6 >= 384 so every shift is exact: compare with the SVD ridge path."""
+    rbcg, ctx = R
+    P = ridge_small
+    note("gram path fp64 exact")
+    Zd = to_dev(P["Z"])
+    op = rbcg.GramOperator(ctx, Zd, lo="f64")
+    rc, info, X = _path(R, op, P["b"], P["omega"], P["mus"], 6)
+    assert rc == 0, info
+    Z64 = P["Z"].astype(np.float64)
+    A = Z64.T @ Z64
+    Xt = ot.ridge_path_svd(P["Z"], P["f"], P["mus"])
+    for i, mu in enumerate(P["mus"]):
+        lam = np.linalg.eigvalsh(A)
+        kappa = (lam[-1] + mu) / (lam[0] + mu)
+        assert a_err(A, mu, X[i], Xt[i]) < max(1e-11, 1e-15 * kappa), (i, mu)
+
+
+def test_gram_path_fp64_iterates_match_oracle(R, ridge_small):
+    rbcg, ctx = R
+    P = ridge_small
+    note("gram path fp64 t=3")
+    op = rbcg.GramOperator(ctx, to_dev(P["Z"]), lo="f64")
+    rc, info, X = _path(R, op, P["b"], P["omega"], P["mus"], 3)
+    assert rc == 0, info
+    Xo, _ = ob.bcg(ob.gram_operator(P["Z"]), P["mus"], P["b"], P["omega"], 3)
+    Z64 = P["Z"].astype(np.float64)
+    A = Z64.T @ Z64
+    for i, mu in enumerate(P["mus"]):
+        assert a_err(A, mu, X[i], Xo[i]) < 1e-10, (i, mu)
+
+
+def test_gram_path_bf16_refined_reaches_fp64_answer(R, ridge_small):
+    """BF16 Z and Z^T copies on MFMA (hi/lo split vectors) with FP64
+    refinement: every shift within 1e-8 of the dense ridge solution."""
+    rbcg, ctx = R
+    P = ridge_small
+    note("gram path bf16 refine")
+    op = rbcg.GramOperator(ctx, to_dev(P["Z"]), lo="bf16")
+    rc, info, X = _path(R, op, P["b"], P["omega"], P["mus"], 8, rtol=1e-11, matvec="bf16", refine_max=8)
+    assert rc == 0, info
+    Z64 = P["Z"].astype(np.float64)
+    A = Z64.T @ Z64
+    Xt = ot.ridge_path_svd(P["Z"], P["f"], P["mus"])
+    for i, mu in enumerate(P["mus"]):
+        assert a_err(A, mu, X[i], Xt[i]) < 1e-8, (i, mu, info[i])
+    assert all(inf["precision_used"] == 2 for inf in info)
+
+
+def _sqrt(R, op, B, t, nquad=32, group=32, matvec="f64"):
+    import torch
+    rbcg, ctx = R
+    Bd = to_dev(B)
+    Y = torch.zeros_like(Bd)
+    rc, info = rbcg.sqrt_apply(ctx, op, Bd, Y, rbcg.opts(t, nquad=nquad, group=group, matvec=matvec), check=False)
+    torch.cuda.synchronize()
+    return rc, info, Y.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def rbf_small():
+    return synth.rbf_problem(4, 1024, 64, ell=0.2)
+
+
+def test_sqrt_matches_oracle_closed_form(R, rbf_small):
+    """Two groups of 32 samples, one shared pass over A per step; each group
+    equals the oracle's block-Lanczos square root of its own block."""
+    rbcg, ctx = R
+    P = rbf_small
+    note("sqrt rbf d=1024 t=8")
+    A, B = P["A"], P["B"]
+    op = rbcg.DenseOperator(ctx, to_dev(A))
+    t = 8
+    rc, info, Y = _sqrt(R, op, B, t)
+    assert rc == 0, info
+    for g in range(2):
+        Yo, _ = ob.sqrt_apply_exact(A, B[32 * g:32 * (g + 1)], t)
+        Yg = Y[32 * g:32 * (g + 1)]
+        rel = np.linalg.norm(Yg - Yo, axis=1) / np.linalg.norm(Yo, axis=1)
+        assert rel.max() < 1e-9, rel.max()
+
+
+def test_sqrt_ragged_last_group(R):
+    """40 samples in groups of 16: the last group has 8 samples (its block is
+    zero padded and the padding deflates); every group equals the oracle's
+    square root over its own block."""
+    rbcg, ctx = R
+    note("sqrt ragged groups")
+    g = np.random.default_rng(77)
+    d = 200
+    A = synth.spd_from_spectrum(np.linspace(1.0, 50.0, d) ** 2, g)
+    B = g.standard_normal((40, d))
+    op = rbcg.DenseOperator(ctx, to_dev(A))
+    t = 5
+    rc, info, Y = _sqrt(R, op, B, t, group=16)
+    assert rc == 0, info
+    for g0, g1 in [(0, 16), (16, 32), (32, 40)]:
+        Yo, _ = ob.sqrt_apply_exact(A, B[g0:g1], t)
+        rel = np.linalg.norm(Y[g0:g1] - Yo, axis=1) / np.linalg.norm(Yo, axis=1)
+        assert rel.max() < 1e-9, (g0, rel.max())
+
+
+def test_sqrt_full_space_equals_eigh(R):
+    """m t >= d: the block-Lanczos square root is A^{1/2} B exactly."""
+    rbcg, ctx = R
+    note("sqrt full space")
+    g = np.random.default_rng(78)
+    d = 96
+    A = synth.spd_from_spectrum(np.linspace(1.0, 50.0, d), g)
+    B = g.standard_normal((48, d))
+    op = rbcg.DenseOperator(ctx, to_dev(A))
+    rc, info, Y = _sqrt(R, op, B, 7, group=16)
+    assert rc == 0, info
+    Yt = ot.sqrt_eig(A, B)
+    rel = np.linalg.norm(Y - Yt, axis=1) / np.linalg.norm(Yt, axis=1)
+    assert rel.max() < 1e-9, rel.max()

@@ -110,8 +110,9 @@ def test_batched_uneven_systems_match_one_at_a_time(R):
     for (A, mu, b, Om), xd in zip(probs, xs):
         X, _ = ob.bcg(A, [mu], b, Om, t)
         assert a_err(A, mu, xd.cpu().numpy(), X[0]) < 1e-11
+        # alone, the system gets a different split-K partition: equal up to rounding
         rc1, _, x1 = _solve_one(R, A, mu, b, Om, t)
-        assert np.array_equal(x1, xd.cpu().numpy()) or a_err(A, mu, x1, xd.cpu().numpy()) < 1e-14
+        assert a_err(A, mu, x1, xd.cpu().numpy()) < 1e-12
 
 
 def test_rtol_stops_and_reports_relres(R):
