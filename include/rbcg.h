@@ -170,6 +170,14 @@ int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, const double* o
 int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t m_s, const double* B, double* Y,
                     const rbcg_opts* opts, rbcg_info* info);
 
+/* The block product the solvers use (one matrix-load, Sec. 1.2):
+ * W = A X for N vectors (rows of X, N x d row-major FP64, device), written to W
+ * (N x d row-major FP64, device).  matvec selects the arithmetic exactly as in
+ * rbcg_opts.matvec (F64; F32 for a dense operator with an FP32 copy; BF16 for
+ * a Gram operator with BF16 copies, where X and Z X are carried as three BF16
+ * parts).  1 <= N <= 256.  Returns after W is complete. */
+int rbcg_op_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t N, const double* X, double* W, int matvec);
+
 /* Bytes of device memory currently held by the context's workspace. */
 int64_t rbcg_workspace_bytes(const rbcg_ctx* ctx);
 

@@ -49,6 +49,38 @@ def ridge_path_svd(Z, f, mus):
     return np.stack([Vt.T @ (s / (s * s + mu) * Uf) for mu in mus])
 
 
+def ridge_path_qr_svd(Z, f, mus, rows_per_block=None, progress=None):
+    """Same path through a thin QR of Z (Householder, FP64) and the SVD of the
+    triangular factor: Z = Q R, R = U S V^T, x_mu = V diag(s/(s^2+mu)) U^T Q^T f.
+
+    The QR is taken block-row by block-row (tall-skinny QR): Z_i = Q_i R_i,
+    then [R_1; ...; R_p] = Q' R, so Q = diag(Q_i) Q' and
+    Q^T f = Q'^T [Q_1^T f_1; ...; Q_p^T f_p].  ``progress(i, p)`` is called
+    after each block."""
+    Z = np.asarray(Z)
+    f = np.asarray(f, dtype=np.float64)
+    n, d = Z.shape
+    rb = rows_per_block or max(d, n)
+    Rs, cs = [], []
+    nblk = (n + rb - 1) // rb
+    for i, r0 in enumerate(range(0, n, rb)):
+        Zi = np.asarray(Z[r0:r0 + rb], dtype=np.float64)
+        Qi, Ri = np.linalg.qr(Zi, mode="reduced")
+        Rs.append(Ri)
+        cs.append(Qi.T @ f[r0:r0 + rb])
+        del Qi, Zi
+        if progress:
+            progress(i + 1, nblk)
+    if len(Rs) == 1:
+        Rf, Qf = Rs[0], cs[0]
+    else:
+        Q2, Rf = np.linalg.qr(np.vstack(Rs), mode="reduced")
+        Qf = Q2.T @ np.concatenate(cs)
+    U, s, Vt = np.linalg.svd(Rf)
+    Uf = U.T @ Qf
+    return np.stack([Vt.T @ (s / (s * s + mu) * Uf) for mu in mus])
+
+
 def ridge_path_eig_gram(Z, b, mus):
     """Same path from b = Z^T f through the eigendecomposition of Z^T Z
     (right singular vectors / squared singular values of Z)."""

@@ -332,7 +332,8 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
     const double piv2 = diag[p];
     bool defl;
     if (d.force_first && s == 0) defl = !(piv2 > 0.0);
-    else defl = !(dref[p] > 0.0) || !(piv2 > d.tau * dref[p]) || (pre[p] >= 0.0 && !(piv2 > d.eta2 * pre[p]));
+    else defl = !(dref[p] > 0.0) || !(piv2 > d.tau * dref[p]) || (pre[p] >= 0.0 && !(piv2 > d.eta2 * pre[p])) ||
+                !(piv2 > d.floor2);
     if (defl && d.pivot) break;   // every remaining column is at least as deficient
     if (defl) {
       __syncthreads();

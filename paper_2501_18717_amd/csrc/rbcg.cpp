@@ -643,6 +643,10 @@ static void add_cholqr(Program& pg, std::vector<Launch>& out, Engine& E, int slo
       d.active = (int)p;
       d.eta2 = 0.0;
       d.tau = 1e-2;   // second pass: columns are near orthonormal; a large loss means dependence
+      // A Gram-based Cholesky resolves a Schur complement only to about eps * ||G||, so a
+      // first-pass column whose true new part is at rounding level can be kept; its scaled
+      // column then has a norm far from one.  Such columns are dropped here.
+      d.floor2 = 0.25;
       qr.push_back(d);
     }
     Launch L{Launch::QR};
@@ -1270,6 +1274,97 @@ static bool op_supports(const rbcg_op* op, int mv) {
   if (mv == RBCG_F64) return true;
   if (op->kind == RBCG_OP_DENSE) return mv == RBCG_F32 && op->lo_t == RBCG_F32 && op->lo;
   return mv == RBCG_BF16 && op->lo_t == RBCG_BF16 && op->lo && op->lot;
+}
+
+// ---------------------------------------------------------------------- block product
+extern "C" int rbcg_op_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t N, const double* X, double* W, int matvec) {
+  if (!ctx || !op || !X || !W || N < 1 || N > 256) return RBCG_ERR_INVALID_ARG;
+  if (matvec != RBCG_F64 && matvec != RBCG_F32 && matvec != RBCG_BF16) return RBCG_ERR_INVALID_ARG;
+  if (!op_supports(op, matvec)) return RBCG_ERR_UNSUPPORTED;
+  if (op->device != ctx->device) return RBCG_ERR_INVALID_ARG;
+  const int d = (int)op->d;
+  Engine E;
+  E.t_max = 1;
+  E.Gs.resize(1);
+  MvGroup& G = E.Gs[0];
+  G.op = op;
+  G.first = 0;
+  G.count = 1;
+  G.N = (int)N;
+  G.ldv = round_up(d, 64);
+  G.mv_t = matvec;
+  size_partials(E);
+  auto carve_g = [&](Arena& a) {
+    G.q = a.take<double>((size_t)2 * G.N * G.ldv);
+    G.bs = (int64_t)G.N * G.ldv;
+    if (G.mv_t == RBCG_F32) {
+      G.ld_xlo = G.ldv;
+      G.xlo = a.take<float>((size_t)G.N * G.ldv);
+    } else if (G.mv_t == RBCG_BF16) {
+      G.ld_xlo = G.ldv;
+      G.xlo = a.take<unsigned short>((size_t)3 * G.N * G.ldv);
+      G.ld_ylo = round_up(op->n, 64);
+      G.ylo = a.take<unsigned short>((size_t)3 * G.N * G.ld_ylo);
+    } else if (op->kind == RBCG_OP_GRAM) {
+      G.ys = a.take<double>((size_t)op->n * G.N);
+    }
+    G.part = G.part_elems ? a.take<double>(G.part_elems) : nullptr;
+  };
+  Arena a0;
+  carve_g(a0);
+  const size_t desc_off = (size_t)round_up((int64_t)a0.off, 256);
+  int rc = ensure_ws(ctx, desc_off + (1 << 16));
+  if (rc) return rc;
+  Arena a1;
+  a1.base = ctx->ws;
+  carve_g(a1);
+  unsigned char* ddesc = (unsigned char*)ctx->ws + desc_off;
+  Program pg;
+  std::vector<Launch> out;
+  {
+    CopyDesc c{};
+    c.src = plain_rows(X, d);
+    c.dst = plain_rows(G.q, G.ldv);
+    c.alpha = 1.0;
+    c.rows = G.N;
+    c.rows_total = G.N;
+    c.n = d;
+    c.active = -1;
+    Launch L{Launch::COPY};
+    L.off = pg.stg.add(std::vector<CopyDesc>{c});
+    L.nz = 1;
+    L.a1 = G.N;
+    L.a2 = d;
+    out.push_back(L);
+  }
+  add_matvec(pg, out, E, 0);
+  {
+    CopyDesc c{};
+    c.src = plain_rows(G.q + G.bs, G.ldv);
+    c.dst = plain_rows(W, d);
+    c.alpha = 1.0;
+    c.rows = G.N;
+    c.rows_total = G.N;
+    c.n = d;
+    c.active = -1;
+    Launch L{Launch::COPY};
+    L.off = pg.stg.add(std::vector<CopyDesc>{c});
+    L.nz = 1;
+    L.a1 = G.N;
+    L.a2 = d;
+    out.push_back(L);
+  }
+  if (desc_off + pg.stg.host.size() > ctx->ws_cap) return RBCG_ERR_OOM;
+  rc = upload(ctx, pg.stg, ddesc);
+  if (rc) return rc;
+  for (const auto& L : out) {
+    HIP_TRY(prof_begin(ctx, L, ctx->stream));
+    HIP_TRY(enqueue(L, ddesc, nullptr, ctx->stream));
+    HIP_TRY(prof_end(ctx, L, ctx->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  prof_collect(ctx);
+  return RBCG_OK;
 }
 
 // ------------------------------------------------------------------------------ solve

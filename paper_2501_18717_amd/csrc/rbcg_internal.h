@@ -86,6 +86,9 @@ struct QrDesc {
   int32_t m, pivot, force_first, active;
   double eta2;             // deflation threshold (relative, squared) vs pre-projection norm
   double tau;              // deflation threshold (relative, squared) vs the block's own norm
+  double floor2;           // absolute floor on the squared Schur pivot (second pass: columns are
+                           // nominally unit, so a pivot below it came from a rounding-dominated
+                           // first-pass Schur complement); 0 = none
 };
 
 // Symmetrised diagonal block of T from the two projection passes.
@@ -141,6 +144,9 @@ hipError_t launch_gemm_nn_ex(bool p_f32, const NnDesc* d_desc, int nz, int maxMo
                              const int32_t* active, hipStream_t st);
 hipError_t launch_qr_factor(const QrDesc* d_desc, int nz, int maxm, const int32_t* active,
                             hipStream_t st);
+// One lane per column variant (m <= kQrColsMax); launch_qr_factor dispatches to it.
+constexpr int kQrColsMax = 96;
+hipError_t launch_qr_cols(const QrDesc* d_desc, int nz, int maxm, const int32_t* active, hipStream_t st);
 hipError_t launch_diag(const DiagDesc* d_desc, int nz, int maxm, const int32_t* active, hipStream_t st);
 hipError_t launch_tri_forward(const TriDesc* d_desc, int nz, int maxm, int maxr, int j0, int j1,
                               const int32_t* active, hipStream_t st);

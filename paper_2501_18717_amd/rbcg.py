@@ -67,6 +67,7 @@ _path = _sig("rbcg_path", ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i64, _dp, _v
                                           ctypes.POINTER(Info)])
 _sqrt = _sig("rbcg_sqrt_apply", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)])
 _ws_bytes = _sig("rbcg_workspace_bytes", _i64, [_vp])
+_op_apply = _sig("rbcg_op_apply", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, ctypes.c_int])
 _sqrt_rule = _sig("rbcg_sqrt_rule", ctypes.c_int, [ctypes.c_double, ctypes.c_double, _i32, _dp, _dp])
 _profile = _sig("rbcg_profile", ctypes.c_int, [_vp, ctypes.c_int])
 _profile_read = _sig("rbcg_profile_read", ctypes.c_int, [_vp, ctypes.POINTER(_i64), _dp, _dp, _dp])
@@ -216,6 +217,15 @@ class GramOperator:
             self.close()
         except Exception:
             pass
+
+
+def op_apply(ctx: Context, op, X, W, matvec: str = "f64"):
+    """W = A X (rows of X) with the solvers' block product in the given precision."""
+    import torch
+    N, d = X.shape
+    _need(X, torch.float64, (N, op.d), "X")
+    _need(W, torch.float64, (N, op.d), "W")
+    _check(_op_apply(ctx.handle, op.handle, N, _ptr(X), _ptr(W), DTYPES[matvec]), "rbcg_op_apply")
 
 
 def solve(ctx: Context, ops: Sequence, mus: Sequence[float], bs: Sequence, omegas: Sequence, xs: Sequence,

@@ -1,0 +1,121 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark uses (same library calls, same sizes).
+
+* dense d = 8192, k = 64, mu = 1e-4, rtol 1e-10: plain FP64 and FP32-MFMA +
+  FP64 refinement, both against the oracle's block-CG solution.
+* ridge path n = 200000, d = 4096, k = 128, 64 shifts: BF16 block products
+  with FP64 refinement against an FP64 ridge truth (thin QR of Z plus the SVD
+  of its triangular factor).
+* RBF sampling on 16384 points, 256 samples in 8 groups of 32, 32 nodes,
+  FP32 block products: the first group against the oracle's closed form.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import block_cg as ob
+from oracle import truth as ot
+
+from gpu_util import a_err, note, to_dev
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_18717_amd import rbcg
+    return rbcg, rbcg.Context()
+
+
+def test_dense_d8192_fp64_and_mixed(R):
+    import torch
+    rbcg, ctx = R
+    note("full dense d=8192 k=64")
+    P = synth.dense_problem(2, 8192, 1.5, 64, 1e-4)
+    A, b, Om, mu = P["A"], P["b"], P["omega"], P["mu"]
+    Ad = to_dev(A)
+    op = rbcg.DenseOperator(ctx, Ad, lo="f32")
+    bd, omd = to_dev(b), to_dev(Om)
+    x64 = torch.zeros_like(bd)
+    xmx = torch.zeros_like(bd)
+    rc, info64 = rbcg.solve(ctx, [op], [mu], [bd], [omd], [x64], [rbcg.opts(48, rtol=1e-10, refine_max=3)])
+    assert rc == 0, info64
+    rc, infomx = rbcg.solve(ctx, [op], [mu], [bd], [omd], [xmx], [rbcg.opts(48, rtol=1e-10, matvec="f32",
+                                                                          refine_max=6)])
+    assert rc == 0, infomx
+    t = info64[0]["iters"]
+    Xo, _ = ob.bcg(A, [mu], b, Om, t)
+    e64 = a_err(A, mu, x64.cpu().numpy(), Xo[0])
+    emx = a_err(A, mu, xmx.cpu().numpy(), Xo[0])
+    note(f"fp64 iters {t} err {e64:.2e}; mixed {infomx[0]} err {emx:.2e}")
+    kappa = (1.0 + mu) / (8192 ** -1.5 + mu)
+    assert e64 < max(1e-12, 1e-15 * kappa)
+    assert emx < 1e-8
+
+
+def test_ridge_path_full_bf16_refined(R):
+    import torch
+    rbcg, ctx = R
+    note("full ridge n=200000 d=4096 k=128 L=64: generating")
+    P = synth.ridge_problem(3, 200000, 4096, 128)
+    Zd = to_dev(P["Z"])
+    op = rbcg.GramOperator(ctx, Zd, lo="bf16")
+    bd, omd = to_dev(P["b"]), to_dev(P["omega"])
+    mus = P["mus"]
+    X = torch.zeros((len(mus), 4096), dtype=torch.float64, device="cuda")
+    note("ridge: GPU path")
+    rc, info = rbcg.path(ctx, op, bd, omd, list(mus), X, rbcg.opts(32, rtol=1e-10, matvec="bf16", refine_max=4),
+                         check=False)
+    note(f"ridge: rc={rc} sweeps={info[0]['refine_sweeps']} loads={info[0]['matrix_loads']} "
+         f"relres max={max(i['relres'] for i in info):.2e}")
+    Xg = X.cpu().numpy()
+    del X, Zd, op
+    note("ridge: FP64 truth (QR + SVD)")
+    Xt = ot.ridge_path_qr_svd(P["Z"], P["f"], mus, rows_per_block=20000,
+                              progress=lambda i, p: note(f"ridge truth: QR block {i}/{p}"))
+    # the A_mu-norm through Z: ||e||^2_{A_mu} = ||Z e||^2 + mu ||e||^2
+    Z64 = P["Z"].astype(np.float64)
+    worst = 0.0
+    for i, mu in enumerate(mus):
+        if i % 8:
+            continue
+        e = Xg[i] - Xt[i]
+        Ze = Z64 @ e
+        Zx = Z64 @ Xt[i]
+        err = np.sqrt((Ze @ Ze + mu * (e @ e)) / (Zx @ Zx + mu * (Xt[i] @ Xt[i])))
+        worst = max(worst, err)
+    note(f"ridge: worst sampled A_mu-norm error {worst:.2e}")
+    assert worst < 1e-8
+    assert rc == 0
+
+
+def test_rbf_sampling_full_first_group(R):
+    import torch
+    rbcg, ctx = R
+    note("full RBF sampling d=16384: generating")
+    P = synth.rbf_problem(4, 16384, 256)
+    A, B = P["A"], P["B"]
+    Ad = to_dev(A)
+    op = rbcg.DenseOperator(ctx, Ad, lo="f32")
+    Bd = to_dev(B)
+    Y = torch.zeros_like(Bd)
+    t = 64
+    note("RBF: GPU sqrt (FP32 products)")
+    rc, info = rbcg.sqrt_apply(ctx, op, Bd, Y, rbcg.opts(t, nquad=32, group=32, matvec="f32"))
+    assert rc == 0
+    Yg = Y[:32].cpu().numpy()
+    # the same with FP64 products
+    Y64 = torch.zeros_like(Bd)
+    rc, _ = rbcg.sqrt_apply(ctx, op, Bd, Y64, rbcg.opts(t, nquad=32, group=32))
+    assert rc == 0
+    Y6 = Y64[:32].cpu().numpy()
+    note("RBF: oracle closed form, group 0")
+    Yo, _ = ob.sqrt_apply_exact(A, B[:32], t)
+    r64 = (np.linalg.norm(Y6 - Yo, axis=1) / np.linalg.norm(Yo, axis=1)).max()
+    r32 = (np.linalg.norm(Yg - Yo, axis=1) / np.linalg.norm(Yo, axis=1)).max()
+    note(f"RBF: FP64 products vs oracle {r64:.2e}; FP32 products vs oracle {r32:.2e}")
+    assert r64 < 1e-8
+    assert r32 < 1e-4

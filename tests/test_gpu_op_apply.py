@@ -1,0 +1,99 @@
+"""The block product alone (the paper's matrix-load, Sec. 1.2) through
+rbcg_op_apply: W = A X for dense A and W = Z^T (Z X) for the Gram operator,
+in every precision the solvers use.
+
+Each low-precision variant is compared with the exact FP64 product of the same
+rounded operands (A or Z rounded to FP32 / BF16 by round-to-nearest-even, as
+the library stores them), so what remains is accumulation rounding and, for
+BF16, the three-part splitting of X and Z X (24 bits):
+  FP64                      rel. error <= 1e-13
+  FP32 (A and X in FP32)    rel. error <= 2e-5  against fl32(A) fl32(X)
+  BF16 Gram (Z in BF16)     rel. error <= 2e-5  against bf16(Z)^T bf16(Z) X
+Shapes span several 64-row tiles with ragged tails; X carries zero rows (the
+deflated columns of a basis block).
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import note, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_18717_amd import rbcg
+    return rbcg, rbcg.Context()
+
+
+def _rel(W, ref):
+    return np.abs(W - ref).max() / np.abs(ref).max()
+
+
+def _x(seed, N, d):
+    X = synth.rng(seed, 0).standard_normal((N, d))
+    X[N // 3: N // 3 + N // 4] = 0.0
+    return X
+
+
+@pytest.mark.parametrize("d,N", [(777, 1), (777, 17), (1000, 65), (513, 130)])
+def test_dense_block_product(R, d, N):
+    import torch
+    rbcg, ctx = R
+    note(f"op_apply dense d={d} N={N}")
+    P = synth.dense_problem(1, d, 1.0, 4, 1e-3)
+    A = P["A"]
+    X = _x(11, N, d)
+    op = rbcg.DenseOperator(ctx, to_dev(A), lo="f32")
+    Xd = to_dev(X)
+    W = torch.full((N, d), float("nan"), dtype=torch.float64, device="cuda")
+    rbcg.op_apply(ctx, op, Xd, W, "f64")
+    assert _rel(W.cpu().numpy(), X @ A.T) <= 1e-13
+    W.fill_(float("nan"))
+    rbcg.op_apply(ctx, op, Xd, W, "f32")
+    A32 = A.astype(np.float32).astype(np.float64)
+    X32 = X.astype(np.float32).astype(np.float64)
+    e = _rel(W.cpu().numpy(), X32 @ A32.T)
+    note(f"  f32 rel err {e:.2e}")
+    assert e <= 2e-5
+
+
+@pytest.mark.parametrize("n,d,N", [(3001, 513, 1), (4097, 256, 65), (20000, 1024, 130)])
+def test_gram_block_product(R, n, d, N):
+    import torch
+    rbcg, ctx = R
+    note(f"op_apply gram n={n} d={d} N={N}")
+    Z = synth.rng(5, 0).standard_normal((n, d)).astype(np.float32)
+    X = _x(12, N, d)
+    Z64 = Z.astype(np.float64)
+    Zd = to_dev(Z)
+    Xd = to_dev(X)
+    W = torch.full((N, d), float("nan"), dtype=torch.float64, device="cuda")
+    op = rbcg.GramOperator(ctx, Zd, lo="f64")
+    rbcg.op_apply(ctx, op, Xd, W, "f64")
+    assert _rel(W.cpu().numpy(), (Z64.T @ (Z64 @ X.T)).T) <= 1e-13
+    del op
+    op = rbcg.GramOperator(ctx, Zd, lo="bf16")
+    W.fill_(float("nan"))
+    rbcg.op_apply(ctx, op, Xd, W, "bf16")
+    Zb = torch.from_numpy(Z).to(torch.bfloat16).to(torch.float64).numpy()
+    e = _rel(W.cpu().numpy(), (Zb.T @ (Zb @ X.T)).T)
+    note(f"  bf16 rel err {e:.2e}")
+    assert e <= 2e-5
+
+
+def test_op_apply_rejects_bad_arguments(R):
+    import torch
+    rbcg, ctx = R
+    A = np.eye(64)
+    op = rbcg.DenseOperator(ctx, to_dev(A))
+    X = torch.zeros((3, 64), dtype=torch.float64, device="cuda")
+    W = torch.zeros((3, 64), dtype=torch.float64, device="cuda")
+    with pytest.raises(rbcg.RbcgError):
+        rbcg.op_apply(ctx, op, X, W, "bf16")   # dense operator has no BF16 copy
+    with pytest.raises(ValueError):
+        rbcg.op_apply(ctx, op, X, torch.zeros((3, 63), dtype=torch.float64, device="cuda"))

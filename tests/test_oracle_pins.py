@@ -260,10 +260,14 @@ def test_ridge_truths_agree():
     mus = [1e-4, 1e-2, 1.0]
     X1 = ot.ridge_path_svd(Z, f, mus)
     X2 = ot.ridge_path_eig_gram(Z, b, mus)
+    X4 = ot.ridge_path_qr_svd(Z, f, mus)
+    X5 = ot.ridge_path_qr_svd(Z, f, mus, rows_per_block=70)
     for i, mu in enumerate(mus):
         x3 = ot.solve_dense(Z64.T @ Z64, mu, b)
         assert np.linalg.norm(X1[i] - x3) < 1e-8 * np.linalg.norm(x3)
         assert np.linalg.norm(X2[i] - x3) < 1e-8 * np.linalg.norm(x3)
+        assert np.linalg.norm(X4[i] - x3) < 1e-8 * np.linalg.norm(x3)
+        assert np.linalg.norm(X5[i] - x3) < 1e-8 * np.linalg.norm(x3)
 
 
 def test_ridge_block_cg_path_exact():
