@@ -55,6 +55,17 @@ __global__ __launch_bounds__(256) void k_finish(const FinDesc* __restrict__ desc
   const bool rowmajor = f.mode == FIN_ROWMAJOR;
   const int rows = rowmajor ? f.M : f.N;   // outer index of the partial layout
   const int cols = rowmajor ? f.N : f.M;
+  if (f.mode == FIN_T2R) {
+    const int64_t total = (int64_t)f.N * f.M;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+      const int c = (int)(e / f.M), i = (int)(e % f.M);
+      double v = 0.0;
+      for (int s = 0; s < f.splits; ++s) v += f.part[(int64_t)s * total + e];
+      f.out[(int64_t)i * f.ldo + c] = f.alpha * v;
+    }
+    return;
+  }
   const int64_t total = (int64_t)rows * cols;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
@@ -446,7 +457,9 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
   }
 }
 
-hipError_t launch_qr_factor(const QrDesc* dd, int nz, int maxm, const int32_t* act, hipStream_t st) {
+hipError_t launch_qr_factor(const QrDesc* dd, int nz, int maxm, bool uniform, const int32_t* act,
+                            hipStream_t st) {
+  if (uniform && qr_m_supported(maxm)) return launch_qr_m(dd, nz, maxm, act, st);
   const size_t lds = ((size_t)maxm * maxm + 4 * (size_t)maxm + 16 * (size_t)maxm + 16) * 8 + 16 * 4 +
                      (size_t)maxm * 3 * 4 + 64;
   if (lds > kLdsCap) return hipErrorInvalidValue;

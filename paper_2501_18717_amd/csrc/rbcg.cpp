@@ -323,6 +323,15 @@ static int pick_splits(int tiles, int nz, int K) {
   return std::max(1, std::min(want, std::min(cap, 256)));
 }
 
+// Splits of the projection products [Q_0..Q_j W]^T W on the tall kernel (64-row tiles):
+// about 768 workgroups, at least 256 values of k per split.
+static int proj_splits(int M, int nz, int K) {
+  const int tiles = (M + 63) / 64;
+  const int want = std::max(1, 768 / std::max(1, tiles * nz));
+  const int cap = std::max(1, K / 256);
+  return std::max(1, std::min(want, std::min(cap, 64)));
+}
+
 // Descriptor staging: host copies, later uploaded in one transfer.
 struct Staging {
   std::vector<unsigned char> host;
@@ -401,7 +410,7 @@ static hipError_t enqueue(const Launch& L, unsigned char* dbase, const int32_t* 
                                L.a3, act, st);
     case Launch::FIN: return launch_finish(dptr<FinDesc>(dbase, L.off), L.nz, L.a1, L.a2, act, st);
     case Launch::NN: return launch_gemm_nn_ex(L.flag, dptr<NnDesc>(dbase, L.off), L.nz, L.a1, L.a2, act, st);
-    case Launch::QR: return launch_qr_factor(dptr<QrDesc>(dbase, L.off), L.nz, L.a1, act, st);
+    case Launch::QR: return launch_qr_factor(dptr<QrDesc>(dbase, L.off), L.nz, L.a1, L.flag, act, st);
     case Launch::DIAG: return launch_diag(dptr<DiagDesc>(dbase, L.off), L.nz, L.a1, act, st);
     case Launch::TRIF:
       return launch_tri_forward(dptr<TriDesc>(dbase, L.off), L.nz, L.a1, L.a2, L.a3, L.a3 + 1, act, st);
@@ -430,10 +439,10 @@ static void add_proj(Program& pg, std::vector<Launch>& out, Engine& E, int j, bo
     maxM = std::max(maxM, M);
     maxN = std::max(maxN, pr.m);
   }
-  tiles = (maxM + 15) / 16;
+  (void)tiles;
   int K = 0;
   for (auto& pr : E.P) K = std::max(K, pr.d);
-  const int splits = pick_splits(tiles, (int)E.P.size(), K);
+  const int splits = proj_splits(maxM, (int)E.P.size(), K);
   for (size_t p = 0; p < E.P.size(); ++p) {
     const Prob& pr = E.P[p];
     NtDesc d{};
@@ -452,7 +461,7 @@ static void add_proj(Program& pg, std::vector<Launch>& out, Engine& E, int j, bo
     f.M = d.M;
     f.N = d.N;
     f.splits = splits;
-    f.mode = FIN_ROWMAJOR;
+    f.mode = FIN_T2R;
     f.out = Cdst[p];
     f.ldo = pr.m;
     f.alpha = 1.0;
@@ -462,7 +471,7 @@ static void add_proj(Program& pg, std::vector<Launch>& out, Engine& E, int j, bo
   Launch L{Launch::NT};
   L.off = pg.stg.add(nt);
   L.nz = (int)nt.size();
-  L.a0 = DT_F64;
+  L.a0 = DT_F64 | (1 << 9) | (1 << 10);   // tall kernel; basis rows are 16-byte aligned
   L.a1 = maxM;
   L.a2 = maxN;
   L.a3 = splits;
@@ -513,7 +522,7 @@ static void add_gram(Program& pg, std::vector<Launch>& out, Engine& E, int slot)
   std::vector<FinDesc> fin;
   int maxm = 0, K = 0;
   for (auto& pr : E.P) { maxm = std::max(maxm, pr.m); K = std::max(K, pr.d); }
-  const int splits = pick_splits((maxm + 15) / 16, (int)E.P.size(), K);
+  const int splits = proj_splits(maxm, (int)E.P.size(), K);
   for (size_t p = 0; p < E.P.size(); ++p) {
     const Prob& pr = E.P[p];
     NtDesc d{};
@@ -532,7 +541,7 @@ static void add_gram(Program& pg, std::vector<Launch>& out, Engine& E, int slot)
     f.M = pr.m;
     f.N = pr.m;
     f.splits = splits;
-    f.mode = FIN_ROWMAJOR;
+    f.mode = FIN_T2R;
     f.out = pr.G;
     f.ldo = pr.m;
     f.alpha = 1.0;
@@ -542,7 +551,7 @@ static void add_gram(Program& pg, std::vector<Launch>& out, Engine& E, int slot)
   Launch L{Launch::NT};
   L.off = pg.stg.add(nt);
   L.nz = (int)nt.size();
-  L.a0 = DT_F64;
+  L.a0 = DT_F64 | (1 << 9) | (1 << 10);   // tall kernel; basis rows are 16-byte aligned
   L.a1 = maxm;
   L.a2 = maxm;
   L.a3 = splits;
@@ -589,6 +598,12 @@ static void add_rmul(Program& pg, std::vector<Launch>& out, Engine& E, int slot,
 
 // Two rounds of pivoted Cholesky QR of block slot `slot`; the second writes the basis mask of
 // that slot and the coefficient block (R0 for the start block, B_j afterwards).
+static bool uniform_width(const Engine& E) {
+  for (const auto& pr : E.P)
+    if (pr.m != E.maxm) return false;
+  return true;
+}
+
 static void add_cholqr(Program& pg, std::vector<Launch>& out, Engine& E, int slot, const double* const* pre,
                        double** coef, bool start, const double* const* g1 = nullptr) {
   // first pass: the Gram matrix comes with the second projection (g1) or is formed here
@@ -619,6 +634,7 @@ static void add_cholqr(Program& pg, std::vector<Launch>& out, Engine& E, int slo
     L.off = pg.stg.add(qr);
     L.nz = (int)qr.size();
     L.a1 = E.maxm;
+    L.flag = uniform_width(E);
     out.push_back(L);
   }
   add_rmul(pg, out, E, slot, false);
@@ -653,6 +669,7 @@ static void add_cholqr(Program& pg, std::vector<Launch>& out, Engine& E, int slo
     L.off = pg.stg.add(qr);
     L.nz = (int)qr.size();
     L.a1 = E.maxm;
+    L.flag = false;   // near-identity Gram: the 1024-thread kernel's first-order path is faster
     out.push_back(L);
   }
   add_rmul(pg, out, E, slot, true);
@@ -973,10 +990,10 @@ static void size_partials(Engine& E) {
   for (int j = 0; j < E.t_max; ++j) {
     int maxM = 0;
     for (auto& pr : E.P) maxM = std::max(maxM, (j + 2) * pr.m);
-    const int s = pick_splits((maxM + 15) / 16, nz, K);
+    const int s = proj_splits(maxM, nz, K);
     if (s > 1) need = std::max(need, (size_t)s * maxM * E.maxm);
   }
-  const int sg = pick_splits((E.maxm + 15) / 16, nz, K);
+  const int sg = proj_splits(E.maxm, nz, K);
   if (sg > 1) need = std::max(need, (size_t)sg * E.maxm * E.maxm);
   for (auto& pr : E.P) pr.part_elems = need;
   for (auto& G : E.Gs) {

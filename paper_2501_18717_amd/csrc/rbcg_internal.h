@@ -41,6 +41,7 @@ enum FinMode : int32_t {
   FIN_ROWMAJOR = 0,   // out[i * ldo + c] = alpha * sum
   FIN_TRANS = 1,      // row c of `O` (a RowOp), element i:  = alpha * sum
   FIN_RESID = 2,      // row c of O, element i: rhs[c][i] - sum - mu[c] * xin[c][i]
+  FIN_T2R = 3,        // partials in (c, i) order, out[i * ldo + c] = alpha * sum
 };
 struct FinDesc {
   const double* part;
@@ -142,11 +143,12 @@ hipError_t launch_finish(const FinDesc* d_desc, int nz, int maxM, int maxN, cons
                          hipStream_t st);
 hipError_t launch_gemm_nn_ex(bool p_f32, const NnDesc* d_desc, int nz, int maxMo, int maxN,
                              const int32_t* active, hipStream_t st);
-hipError_t launch_qr_factor(const QrDesc* d_desc, int nz, int maxm, const int32_t* active,
+// uniform: every problem of the launch has block width maxm (enables the exact-width kernels).
+hipError_t launch_qr_factor(const QrDesc* d_desc, int nz, int maxm, bool uniform, const int32_t* active,
                             hipStream_t st);
-// One lane per column variant (m <= kQrColsMax); launch_qr_factor dispatches to it.
-constexpr int kQrColsMax = 96;
-hipError_t launch_qr_cols(const QrDesc* d_desc, int nz, int maxm, const int32_t* active, hipStream_t st);
+// One lane per column, compiled for an exact block width (m = 9, 17, 33, 65, 129).
+bool qr_m_supported(int m);
+hipError_t launch_qr_m(const QrDesc* d_desc, int nz, int m, const int32_t* active, hipStream_t st);
 hipError_t launch_diag(const DiagDesc* d_desc, int nz, int maxm, const int32_t* active, hipStream_t st);
 hipError_t launch_tri_forward(const TriDesc* d_desc, int nz, int maxm, int maxr, int j0, int j1,
                               const int32_t* active, hipStream_t st);

@@ -97,22 +97,25 @@ def test_batched_uneven_systems_match_one_at_a_time(R):
     probs = []
     for i, (d, k, p, mu) in enumerate([(400, 8, 1.2, 1e-3), (1100, 16, 2.0, 1e-5), (257, 31, 1.0, 1e-2)]):
         g = np.random.default_rng(100 + i)
-        A = synth.spd_from_spectrum(np.arange(1, d + 1, dtype=float) ** (-p), g)
-        probs.append((A, mu, g.standard_normal(d), g.standard_normal((k, d))))
+        lam = np.arange(1, d + 1, dtype=float) ** (-p)
+        A = synth.spd_from_spectrum(lam, g)
+        probs.append((A, mu, g.standard_normal(d), g.standard_normal((k, d)), (1.0 + mu) / (lam[-1] + mu)))
     t = 6
     ops = [rbcg.DenseOperator(ctx, to_dev(A)) for A, *_ in probs]
-    bs = [to_dev(b) for _, _, b, _ in probs]
-    oms = [to_dev(Om) for *_, Om in probs]
+    bs = [to_dev(pr[2]) for pr in probs]
+    oms = [to_dev(pr[3]) for pr in probs]
     xs = [torch.zeros_like(b) for b in bs]
     o = [rbcg.opts(t) for _ in probs]
     rc, info = rbcg.solve(ctx, ops, [pr[1] for pr in probs], bs, oms, xs, o)
     assert rc == 0
-    for (A, mu, b, Om), xd in zip(probs, xs):
+    for (A, mu, b, Om, kappa), xd in zip(probs, xs):
         X, _ = ob.bcg(A, [mu], b, Om, t)
         assert a_err(A, mu, xd.cpu().numpy(), X[0]) < 1e-11
-        # alone, the system gets a different split-K partition: equal up to rounding
+        # alone, the system gets a different split-K partition and, when its block width is
+        # one the exact-width factorization kernel serves, a different kernel (pivot ties may
+        # break differently): equal up to rounding, at the oracle-parity bound
         rc1, _, x1 = _solve_one(R, A, mu, b, Om, t)
-        assert a_err(A, mu, x1, xd.cpu().numpy()) < 1e-12
+        assert a_err(A, mu, x1, xd.cpu().numpy()) < max(1e-12, 1e-15 * kappa)
 
 
 def test_rtol_stops_and_reports_relres(R):
