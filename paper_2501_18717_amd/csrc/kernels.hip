@@ -77,6 +77,10 @@ __global__ __launch_bounds__(256) void k_finish(const FinDesc* __restrict__ desc
       f.out[(int64_t)o * f.ldo + in] = v;
     } else if (f.mode == FIN_TRANS) {
       ((double*)f.O.p)[row_off(f.O, o) + in] = v;
+    } else if (f.mode == FIN_AXPBY) {
+      double y = v;
+      if (f.beta != 0.0) y += f.beta * ((const double*)f.rhs.p)[row_off(f.rhs, o) + in];
+      ((double*)f.O.p)[row_off(f.O, o) + in] = y;
     } else {
       const double rv = ((const double*)f.rhs.p)[row_off(f.rhs, o) + in];
       const double xv = ((const double*)f.xin.p)[row_off(f.xin, o) + in];
@@ -188,6 +192,127 @@ hipError_t launch_gemm_nn_ex(bool p_f32, const NnDesc* dd, int nz, int maxMo, in
   const int tb = (maxMo + 15) / 16;
   if (tb < 1 || tb > 16) return hipErrorInvalidValue;
   return p_f32 ? dispatch_tb<float>(tb, dd, nz, maxN, act, st) : dispatch_tb<double>(tb, dd, nz, maxN, act, st);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Tall NN update: O[b][i] = beta * Y[b][i] + alpha * sum_a C[a][b] P[a][i], i < N (long),
+// b < Mo (<= 144), a in this split's range.  Workgroup = 4 waves = 64 columns i (16 per wave),
+// all TB row tiles of b.  The C chunk (16 values of a x 16 TB values of b) is staged in LDS,
+// double-buffered and shared by the waves; each lane streams its 4 P values per chunk one chunk
+// ahead.  MFMA A operand = C^T (b x a) from LDS, B operand = P (a x i); D rows b, columns i.
+// ---------------------------------------------------------------------------------------------
+template <typename PT, int TB>
+__global__ __launch_bounds__(256) void k_nn_tall(const NnDesc* __restrict__ descs, int splits,
+                                                 const int32_t* __restrict__ act) {
+  constexpr int BW = 16 * TB;            // padded b range
+  constexpr int CS = BW + 2;             // LDS row stride (doubles)
+  const NnDesc d = descs[blockIdx.z];
+  if (!is_active(act, d.active)) return;
+  const int i0 = blockIdx.x * 64;
+  if (i0 >= d.N) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int q = lane >> 4, r16 = lane & 15;
+  const int i = i0 + 16 * wave + r16;
+  const bool ival = i < d.N;
+  const int s = blockIdx.y;
+  const int per = ((d.Ka + splits - 1) / splits + 15) / 16 * 16;
+  const int ab = s * per, ae = min(d.Ka, ab + per);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* cs = (double*)smem_raw;        // [2][16][CS]
+  const PT* __restrict__ P = (const PT*)d.P.p;
+  auto load_p = [&](int a0, double* pv) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int a = a0 + 4 * e + q;
+      pv[e] = (ival && a < ae) ? (double)P[row_off(d.P, a) + i] : 0.0;
+    }
+  };
+  auto stage_c = [&](int a0, int buf) {
+    double* dst = cs + buf * 16 * CS;
+    for (int e = tid; e < 16 * BW; e += 256) {
+      const int r = e / BW, b = e - r * BW;
+      const int a = a0 + r;
+      dst[r * CS + b] = (a < ae && b < d.Mo) ? d.C[(int64_t)a * d.ldc + b] : 0.0;
+    }
+  };
+  v4d acc[TB];
+#pragma unroll
+  for (int tb = 0; tb < TB; ++tb) acc[tb] = v4d{0, 0, 0, 0};
+  double pcur[4], pnext[4];
+  int buf = 0;
+  if (ab < ae) {
+    stage_c(ab, 0);
+    load_p(ab, pcur);
+  }
+  __syncthreads();
+  for (int a0 = ab; a0 < ae; a0 += 16) {
+    const bool more = a0 + 16 < ae;
+    if (more) {
+      load_p(a0 + 16, pnext);
+      stage_c(a0 + 16, buf ^ 1);
+    }
+    const double* cb = cs + buf * 16 * CS;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const double* crow = cb + (4 * e + q) * CS + r16;
+#pragma unroll
+      for (int tb = 0; tb < TB; ++tb)
+        acc[tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(crow[16 * tb], pcur[e], acc[tb], 0, 0, 0);
+    }
+    __syncthreads();
+    buf ^= 1;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) pcur[e] = pnext[e];
+  }
+  if (!ival) return;
+#pragma unroll
+  for (int tb = 0; tb < TB; ++tb) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int b = 16 * tb + q + 4 * r;
+      if (b >= d.Mo) continue;
+      const double v = acc[tb][r];
+      if (splits > 1) {
+        d.part[((int64_t)s * d.Mo + b) * d.N + i] = v;
+      } else {
+        double out = d.alpha * v;
+        if (d.beta != 0.0) out += d.beta * ((const double*)d.Y.p)[row_off(d.Y, b) + i];
+        ((double*)d.O.p)[row_off(d.O, b) + i] = out;
+      }
+    }
+  }
+}
+
+template <typename PT, int TB>
+static hipError_t launch_nn_tall_t(const NnDesc* dd, int nz, int maxN, int splits, const int32_t* act,
+                                   hipStream_t st) {
+  const size_t lds = (size_t)2 * 16 * (16 * TB + 2) * 8;
+  hipLaunchKernelGGL((k_nn_tall<PT, TB>), dim3((maxN + 63) / 64, splits, nz), dim3(256), lds, st, dd, splits, act);
+  return hipGetLastError();
+}
+
+template <typename PT>
+static hipError_t dispatch_nn_tall(int tb, const NnDesc* dd, int nz, int maxN, int splits, const int32_t* act,
+                                   hipStream_t st) {
+  switch (tb) {
+    case 1: return launch_nn_tall_t<PT, 1>(dd, nz, maxN, splits, act, st);
+    case 2: return launch_nn_tall_t<PT, 2>(dd, nz, maxN, splits, act, st);
+    case 3: return launch_nn_tall_t<PT, 3>(dd, nz, maxN, splits, act, st);
+    case 4: return launch_nn_tall_t<PT, 4>(dd, nz, maxN, splits, act, st);
+    case 5: return launch_nn_tall_t<PT, 5>(dd, nz, maxN, splits, act, st);
+    case 6: return launch_nn_tall_t<PT, 6>(dd, nz, maxN, splits, act, st);
+    case 7: case 8: return launch_nn_tall_t<PT, 8>(dd, nz, maxN, splits, act, st);
+    case 9: return launch_nn_tall_t<PT, 9>(dd, nz, maxN, splits, act, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_nn_tall(bool p_f32, const NnDesc* dd, int nz, int maxMo, int maxN, int splits, const int32_t* act,
+                          hipStream_t st) {
+  const int tb = (maxMo + 15) / 16;
+  if (tb < 1 || tb > 9 || splits < 1) return hipErrorInvalidValue;
+  return p_f32 ? dispatch_nn_tall<float>(tb, dd, nz, maxN, splits, act, st)
+               : dispatch_nn_tall<double>(tb, dd, nz, maxN, splits, act, st);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -918,6 +1043,24 @@ hipError_t launch_copy(const CopyDesc* dd, int nz, int maxRows, int maxN, const 
   int blocks = (int)std::min<int64_t>((tot + 255) / 256, 4096);
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_copy, dim3(blocks, 1, nz), dim3(256), 0, st, dd, act);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_fill(const FillDesc* __restrict__ descs, const int32_t* __restrict__ act) {
+  const FillDesc d = descs[blockIdx.z];
+  if (!is_active(act, d.active)) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= d.n) return;
+  int j = 0;
+  for (int s = 0; s < d.m && j < d.src_avail; ++s) {
+    if (!d.mask[s]) continue;
+    ((double*)d.dst.p)[row_off(d.dst, s) + i] = ((const double*)d.src.p)[row_off(d.src, d.src_first + j) + i];
+    ++j;
+  }
+}
+
+hipError_t launch_fill(const FillDesc* dd, int nz, int maxN, const int32_t* act, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill, dim3((maxN + 255) / 256, 1, nz), dim3(256), 0, st, dd, act);
   return hipGetLastError();
 }
 

@@ -323,6 +323,15 @@ static int pick_splits(int tiles, int nz, int K) {
   return std::max(1, std::min(want, std::min(cap, 256)));
 }
 
+// Splits of the tall NN update (64 output columns per workgroup): about 384 workgroups, at
+// least 128 values of the reduction index per split.
+static int nn_splits(int N, int Ka, int nz) {
+  const int tiles = (N + 63) / 64;
+  const int want = std::max(1, 384 / std::max(1, tiles * nz));
+  const int cap = std::max(1, Ka / 128);
+  return std::max(1, std::min(want, std::min(cap, 64)));
+}
+
 // Splits of the projection products [Q_0..Q_j W]^T W on the tall kernel (64-row tiles):
 // about 768 workgroups, at least 256 values of k per split.
 static int proj_splits(int M, int nz, int K) {
@@ -351,7 +360,7 @@ static const T* dptr(unsigned char* dbase, size_t off) {
 
 // One enqueued kernel launch of the step program.
 struct Launch {
-  enum Kind { NT, FIN, NN, QR, DIAG, TRIF, CONV, CVT, COPY } kind;
+  enum Kind { NT, FIN, NN, QR, DIAG, TRIF, CONV, CVT, COPY, FILL } kind;
   size_t off = 0;
   int nz = 0;
   int a0 = 0, a1 = 0, a2 = 0, a3 = 0;   // kind-specific sizes
@@ -409,7 +418,10 @@ static hipError_t enqueue(const Launch& L, unsigned char* dbase, const int32_t* 
       return launch_gemm_nt_ex(L.a0 & 0xff, (L.a0 >> 8) & 1, L.flag, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a2,
                                L.a3, act, st);
     case Launch::FIN: return launch_finish(dptr<FinDesc>(dbase, L.off), L.nz, L.a1, L.a2, act, st);
-    case Launch::NN: return launch_gemm_nn_ex(L.flag, dptr<NnDesc>(dbase, L.off), L.nz, L.a1, L.a2, act, st);
+    case Launch::NN:
+      if (L.a0 & (1 << 9))
+        return launch_nn_tall(L.flag, dptr<NnDesc>(dbase, L.off), L.nz, L.a1, L.a2, L.a3, act, st);
+      return launch_gemm_nn_ex(L.flag, dptr<NnDesc>(dbase, L.off), L.nz, L.a1, L.a2, act, st);
     case Launch::QR: return launch_qr_factor(dptr<QrDesc>(dbase, L.off), L.nz, L.a1, L.flag, act, st);
     case Launch::DIAG: return launch_diag(dptr<DiagDesc>(dbase, L.off), L.nz, L.a1, act, st);
     case Launch::TRIF:
@@ -417,6 +429,7 @@ static hipError_t enqueue(const Launch& L, unsigned char* dbase, const int32_t* 
     case Launch::CONV: return launch_converge(dptr<ConvDesc>(dbase, L.off), L.nz, st);
     case Launch::CVT: return launch_convert(dptr<CvtDesc>(dbase, L.off), L.nz, L.a1, L.a2, act, st);
     case Launch::COPY: return launch_copy(dptr<CopyDesc>(dbase, L.off), L.nz, L.a1, L.a2, act, st);
+    case Launch::FILL: return launch_fill(dptr<FillDesc>(dbase, L.off), L.nz, L.a1, act, st);
   }
   return hipErrorInvalidValue;
 }
@@ -489,7 +502,14 @@ static void add_proj(Program& pg, std::vector<Launch>& out, Engine& E, int j, bo
 // W -= Q_{0..j} C  (rows [0, (j+1)m) of the basis)
 static void add_update(Program& pg, std::vector<Launch>& out, Engine& E, int j, double** C) {
   std::vector<NnDesc> nn;
-  int maxMo = 0, maxN = 0;
+  std::vector<FinDesc> fin;
+  int maxMo = 0, maxN = 0, maxKa = 0;
+  for (auto& pr : E.P) {
+    maxMo = std::max(maxMo, pr.m);
+    maxN = std::max(maxN, pr.d);
+    maxKa = std::max(maxKa, (j + 1) * pr.m);
+  }
+  const int splits = nn_splits(maxN, maxKa, (int)E.P.size());
   for (size_t p = 0; p < E.P.size(); ++p) {
     const Prob& pr = E.P[p];
     NnDesc d{};
@@ -504,16 +524,37 @@ static void add_update(Program& pg, std::vector<Launch>& out, Engine& E, int j, 
     d.Mo = pr.m;
     d.N = pr.d;
     d.active = (int)p;
+    d.part = pr.part;
     nn.push_back(d);
-    maxMo = std::max(maxMo, pr.m);
-    maxN = std::max(maxN, pr.d);
+    FinDesc f{};
+    f.part = pr.part;
+    f.M = pr.d;
+    f.N = pr.m;
+    f.splits = splits;
+    f.mode = FIN_AXPBY;
+    f.O = pr.block(j + 1);
+    f.rhs = pr.block(j + 1);
+    f.alpha = -1.0;
+    f.beta = 1.0;
+    f.active = (int)p;
+    fin.push_back(f);
   }
   Launch L{Launch::NN};
   L.off = pg.stg.add(nn);
   L.nz = (int)nn.size();
+  L.a0 = 1 << 9;   // tall variant
   L.a1 = maxMo;
   L.a2 = maxN;
+  L.a3 = splits;
   out.push_back(L);
+  if (splits > 1) {
+    Launch F{Launch::FIN};
+    F.off = pg.stg.add(fin);
+    F.nz = (int)fin.size();
+    F.a1 = maxN;
+    F.a2 = maxMo;
+    out.push_back(F);
+  }
 }
 
 // G = W^T W for the W in block slot `slot`
@@ -858,13 +899,38 @@ static void add_matvec(Program& pg, std::vector<Launch>& out, Engine& E, int j) 
         nn.Mo = G.N;
         nn.N = d;
         nn.active = act_idx;
+        nn.part = G.part;
         Launch L2{Launch::NN};
         L2.off = pg.stg.add(std::vector<NnDesc>{nn});
         L2.nz = 1;
         L2.flag = true;
         L2.a1 = G.N;
         L2.a2 = d;
+        const bool tall = G.N <= 144;
+        if (tall) {
+          L2.a0 = 1 << 9;
+          L2.a3 = G.splits2;
+        }
         out.push_back(L2);
+        if (tall && G.splits2 > 1) {
+          FinDesc f{};
+          f.part = G.part;
+          f.M = d;
+          f.N = G.N;
+          f.splits = G.splits2;
+          f.mode = FIN_AXPBY;
+          f.O = Wb;
+          f.rhs = Wb;
+          f.alpha = 1.0;
+          f.beta = 0.0;
+          f.active = act_idx;
+          Launch F{Launch::FIN};
+          F.off = pg.stg.add(std::vector<FinDesc>{f});
+          F.nz = 1;
+          F.a1 = d;
+          F.a2 = G.N;
+          out.push_back(F);
+        }
       }
     }
   }
@@ -917,8 +983,20 @@ static void add_monitor(Program& pg, std::vector<Launch>& out, Engine& E, int j,
   out.push_back(C);
 }
 
+// Start block of a refinement sweep of a path (one problem): the L residual rows R are in the
+// start block; after its rank-revealing factorization the deflated columns are refilled with
+// unused Gaussian rows, the block is factorized again, and the right-hand side of shift l in
+// the first basis block becomes Q_0^T r_l (column l of R0).
+struct Refill {
+  RowOp R;
+  int L = 0;
+  RowOp omega;
+  int src_first = 0, src_avail = 0;
+};
+
 static void build_program(Program& pg, Engine& E, const std::vector<double>& tol, bool monitor,
-                          std::vector<CopyDesc>& start_copies, int max_start_rows) {
+                          std::vector<CopyDesc>& start_copies, int max_start_rows,
+                          const Refill* refill = nullptr) {
   pg.steps.assign(E.t_max + 1, {});
   pg.mon.assign(E.t_max, {});
   // start block: caller-provided copies into block 0, then Cholesky QR (R0 = coefficients)
@@ -935,6 +1013,64 @@ static void build_program(Program& pg, Engine& E, const std::vector<double>& tol
     std::vector<double*> coef(E.P.size());
     for (size_t p = 0; p < E.P.size(); ++p) coef[p] = E.P[p].R0;
     add_cholqr(pg, out, E, 0, nullptr, coef.data(), true);
+    if (refill && refill->src_avail > 0) {
+      const Prob& pr = E.P[0];
+      FillDesc f{};
+      f.dst = pr.block(0);
+      f.mask = pr.mask;
+      f.src = refill->omega;
+      f.src_first = refill->src_first;
+      f.src_avail = refill->src_avail;
+      f.m = pr.m;
+      f.n = pr.d;
+      f.active = 0;
+      Launch F{Launch::FILL};
+      F.off = pg.stg.add(std::vector<FillDesc>{f});
+      F.nz = 1;
+      F.a1 = pr.d;
+      out.push_back(F);
+      add_cholqr(pg, out, E, 0, nullptr, coef.data(), true);
+    }
+    if (refill) {
+      const Prob& pr = E.P[0];
+      const int splits = proj_splits(pr.m, 1, pr.d);
+      NtDesc nd{};
+      nd.P = pr.block(0);
+      nd.X = refill->R;
+      nd.M = pr.m;
+      nd.N = refill->L;
+      nd.K = pr.d;
+      nd.active = 0;
+      nd.part = pr.part;
+      nd.out = pr.R0;
+      nd.ldo = pr.m;
+      Launch L{Launch::NT};
+      L.off = pg.stg.add(std::vector<NtDesc>{nd});
+      L.nz = 1;
+      L.a0 = DT_F64 | (1 << 9) | (1 << 10);
+      L.a1 = pr.m;
+      L.a2 = refill->L;
+      L.a3 = splits;
+      out.push_back(L);
+      if (splits > 1) {
+        FinDesc fd{};
+        fd.part = pr.part;
+        fd.M = pr.m;
+        fd.N = refill->L;
+        fd.splits = splits;
+        fd.mode = FIN_T2R;
+        fd.out = pr.R0;
+        fd.ldo = pr.m;
+        fd.alpha = 1.0;
+        fd.active = 0;
+        Launch F{Launch::FIN};
+        F.off = pg.stg.add(std::vector<FinDesc>{fd});
+        F.nz = 1;
+        F.a1 = pr.m;
+        F.a2 = refill->L;
+        out.push_back(F);
+      }
+    }
   }
   for (int j = 0; j < E.t_max; ++j) {
     auto& out = pg.steps[j + 1];
@@ -992,6 +1128,8 @@ static void size_partials(Engine& E) {
     for (auto& pr : E.P) maxM = std::max(maxM, (j + 2) * pr.m);
     const int s = proj_splits(maxM, nz, K);
     if (s > 1) need = std::max(need, (size_t)s * maxM * E.maxm);
+    const int su = nn_splits(K, (j + 1) * E.maxm, nz);
+    if (su > 1) need = std::max(need, (size_t)su * E.maxm * K);
   }
   const int sg = proj_splits(E.maxm, nz, K);
   if (sg > 1) need = std::max(need, (size_t)sg * E.maxm * E.maxm);
@@ -1001,7 +1139,8 @@ static void size_partials(Engine& E) {
     int tiles = (d + 15) / 16;
     int Kp = (G.op->kind == RBCG_OP_GRAM && G.mv_t == RBCG_BF16) ? (int)G.op->n : d;
     if (G.op->kind == RBCG_OP_GRAM && G.mv_t != RBCG_BF16) {
-      G.splits2 = 1;
+      // FP64 path: the second product W = Z^T (Z X) on the tall NN kernel (widths <= 144)
+      G.splits2 = G.N <= 144 ? nn_splits(d, (int)G.op->n, 1) : 1;
     } else if (G.op->kind == RBCG_OP_DENSE && G.N <= 144) {
       const int t64 = (d + 63) / 64;
       G.splits2 = std::max(1, std::min(std::max(1, 512 / t64), std::max(1, d / 512)));
@@ -1782,7 +1921,15 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
       tol[0] = std::min(t, 0.5);
     }
     Program pg;
-    build_program(pg, E, tol, refine, cps, std::max(nstart, m));
+    Refill rf;
+    if (sweep > 0) {
+      rf.R = plain_rows(Rbuf, ldv);
+      rf.L = (int)L;
+      rf.omega = plain_rows(omega, d);
+      rf.src_first = m - (int)L;
+      rf.src_avail = k > 0 ? k - (m - (int)L) : 0;
+    }
+    build_program(pg, E, tol, refine, cps, std::max(nstart, m), sweep > 0 ? &rf : nullptr);
     if (desc_off + pg.stg.host.size() > ctx->ws_cap) return RBCG_ERR_OOM;
     rc = upload(ctx, pg.stg, ddesc);
     if (rc) return rc;

@@ -42,6 +42,7 @@ enum FinMode : int32_t {
   FIN_TRANS = 1,      // row c of `O` (a RowOp), element i:  = alpha * sum
   FIN_RESID = 2,      // row c of O, element i: rhs[c][i] - sum - mu[c] * xin[c][i]
   FIN_T2R = 3,        // partials in (c, i) order, out[i * ldo + c] = alpha * sum
+  FIN_AXPBY = 4,      // row c of O, element i: beta * rhs[c][i] + alpha * sum
 };
 struct FinDesc {
   const double* part;
@@ -54,6 +55,7 @@ struct FinDesc {
   const double* mu;       // FIN_RESID: shift of each row c
   double alpha;
   int32_t active, pad_;
+  double beta;            // FIN_AXPBY
 };
 
 // O[b][i] = beta * Y[b][i] + alpha * sum_a C[a][b] * P[a][i]
@@ -66,6 +68,7 @@ struct NnDesc {
   RowOp O;
   double alpha, beta;
   int32_t Ka, Mo, N, active;
+  double* part;            // split partials of the tall variant ([s][b][i]) when splits > 1
 };
 
 // Factorization of a small Gram matrix G = W^T W (m x m) for Cholesky QR
@@ -143,6 +146,11 @@ hipError_t launch_finish(const FinDesc* d_desc, int nz, int maxM, int maxN, cons
                          hipStream_t st);
 hipError_t launch_gemm_nn_ex(bool p_f32, const NnDesc* d_desc, int nz, int maxMo, int maxN,
                              const int32_t* active, hipStream_t st);
+// Same product, 64 output columns per workgroup with the C chunk staged in LDS and P streamed
+// one chunk ahead; with splits > 1 the partial sums go to `part` ([s][b][i], s < splits) and
+// a FIN_AXPBY finish forms O = beta Y + alpha sum.  Mo <= 144.
+hipError_t launch_nn_tall(bool p_f32, const NnDesc* d_desc, int nz, int maxMo, int maxN, int splits,
+                          const int32_t* active, hipStream_t st);
 // uniform: every problem of the launch has block width maxm (enables the exact-width kernels).
 hipError_t launch_qr_factor(const QrDesc* d_desc, int nz, int maxm, bool uniform, const int32_t* active,
                             hipStream_t st);
@@ -168,6 +176,11 @@ hipError_t launch_sqnorms(const NormDesc* d_desc, int nz, int maxRows, const int
 struct CopyDesc { RowOp src; RowOp dst; double alpha; int32_t rows, rows_total, n, active; };
 hipError_t launch_copy(const CopyDesc* d_desc, int nz, int maxRows, int maxN, const int32_t* active,
                        hipStream_t st);
+
+// Refill of deflated start-block columns: the j-th deflated position s (mask[s] != 0, in
+// position order) gets src row (src_first + j) when j < src_avail; other rows are untouched.
+struct FillDesc { RowOp dst; const int32_t* mask; RowOp src; int32_t src_first, src_avail, m, n, active, pad_; };
+hipError_t launch_fill(const FillDesc* d_desc, int nz, int maxN, const int32_t* active, hipStream_t st);
 
 hipError_t launch_transpose_bf16(const float* src, int64_t ld, int rows, int cols, unsigned short* dst,
                                  int64_t ldt, hipStream_t st);

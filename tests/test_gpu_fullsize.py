@@ -5,9 +5,15 @@ benchmark uses (same library calls, same sizes).
   FP64 refinement, both against the oracle's block-CG solution.
 * ridge path n = 200000, d = 4096, k = 128, 64 shifts: BF16 block products
   with FP64 refinement against an FP64 ridge truth (thin QR of Z plus the SVD
-  of its triangular factor).
-* RBF sampling on 16384 points, 256 samples in 8 groups of 32, 32 nodes,
-  FP32 block products: the first group against the oracle's closed form.
+  of its triangular factor); the plain FP64 path at t = 32 (exact termination,
+  32 * 129 >= 4096) against the same truth.
+* RBF sampling on 16384 points, 256 samples in 8 groups of 32, 32 nodes: FP64
+  block products against the oracle's closed form; FP32 block products
+  against the oracle's closed form for the FP32-rounded matrix.  Sampling has
+  no residual to refine, and rounding A to FP32 moves its entries by about
+  6e-8 |A_ij|, the size of the 1e-6 nugget that sets lambda_min, so the FP32
+  result differs from the FP64 one by about 6e-3; what the FP32 path must
+  reproduce is the method applied to fl32(A).
 """
 import numpy as np
 import pytest
@@ -67,29 +73,36 @@ def test_ridge_path_full_bf16_refined(R):
     mus = P["mus"]
     X = torch.zeros((len(mus), 4096), dtype=torch.float64, device="cuda")
     note("ridge: GPU path")
-    rc, info = rbcg.path(ctx, op, bd, omd, list(mus), X, rbcg.opts(32, rtol=1e-10, matvec="bf16", refine_max=4),
+    rc, info = rbcg.path(ctx, op, bd, omd, list(mus), X, rbcg.opts(32, rtol=3e-11, matvec="bf16", refine_max=10),
                          check=False)
     note(f"ridge: rc={rc} sweeps={info[0]['refine_sweeps']} loads={info[0]['matrix_loads']} "
          f"relres max={max(i['relres'] for i in info):.2e}")
     Xg = X.cpu().numpy()
-    del X, Zd, op
+    op64 = rbcg.GramOperator(ctx, Zd, lo="f64")
+    note("ridge: GPU path, FP64 products, t = 32")
+    rc64, _ = rbcg.path(ctx, op64, bd, omd, list(mus), X, rbcg.opts(32), check=False)
+    X64 = X.cpu().numpy()
+    del X, Zd, op, op64
     note("ridge: FP64 truth (QR + SVD)")
     Xt = ot.ridge_path_qr_svd(P["Z"], P["f"], mus, rows_per_block=20000,
                               progress=lambda i, p: note(f"ridge truth: QR block {i}/{p}"))
     # the A_mu-norm through Z: ||e||^2_{A_mu} = ||Z e||^2 + mu ||e||^2
     Z64 = P["Z"].astype(np.float64)
-    worst = 0.0
-    for i, mu in enumerate(mus):
-        if i % 8:
-            continue
-        e = Xg[i] - Xt[i]
+
+    def err(Xs, i, mu):
+        e = Xs[i] - Xt[i]
         Ze = Z64 @ e
         Zx = Z64 @ Xt[i]
-        err = np.sqrt((Ze @ Ze + mu * (e @ e)) / (Zx @ Zx + mu * (Xt[i] @ Xt[i])))
-        worst = max(worst, err)
-    note(f"ridge: worst sampled A_mu-norm error {worst:.2e}")
-    assert worst < 1e-8
+        return np.sqrt((Ze @ Ze + mu * (e @ e)) / (Zx @ Zx + mu * (Xt[i] @ Xt[i])))
+
+    sel = [i for i in range(len(mus)) if i % 8 == 0] + [len(mus) - 1]
+    worst = max(err(Xg, i, mus[i]) for i in sel)
+    worst64 = max(err(X64, i, mus[i]) for i in sel)
+    note(f"ridge: worst sampled A_mu-norm error, BF16 + refinement {worst:.2e}; FP64 t=32 {worst64:.2e}")
     assert rc == 0
+    assert worst < 1e-8
+    assert rc64 == 0
+    assert worst64 < 1e-10
 
 
 def test_rbf_sampling_full_first_group(R):
@@ -114,8 +127,12 @@ def test_rbf_sampling_full_first_group(R):
     Y6 = Y64[:32].cpu().numpy()
     note("RBF: oracle closed form, group 0")
     Yo, _ = ob.sqrt_apply_exact(A, B[:32], t)
+    note("RBF: oracle closed form on fl32(A), group 0")
+    Yo32, _ = ob.sqrt_apply_exact(A.astype(np.float32).astype(np.float64), B[:32], t)
     r64 = (np.linalg.norm(Y6 - Yo, axis=1) / np.linalg.norm(Yo, axis=1)).max()
-    r32 = (np.linalg.norm(Yg - Yo, axis=1) / np.linalg.norm(Yo, axis=1)).max()
-    note(f"RBF: FP64 products vs oracle {r64:.2e}; FP32 products vs oracle {r32:.2e}")
+    r32 = (np.linalg.norm(Yg - Yo32, axis=1) / np.linalg.norm(Yo32, axis=1)).max()
+    r32x = (np.linalg.norm(Yg - Yo, axis=1) / np.linalg.norm(Yo, axis=1)).max()
+    note(f"RBF: FP64 products vs oracle {r64:.2e}; FP32 products vs oracle on fl32(A) {r32:.2e} "
+         f"(vs oracle on A {r32x:.2e})")
     assert r64 < 1e-8
-    assert r32 < 1e-4
+    assert r32 < 1e-5
