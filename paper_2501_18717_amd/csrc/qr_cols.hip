@@ -7,11 +7,10 @@
 // revealing); a column is deflated when that ratio falls below tau, when its remaining norm is
 // below sqrt(eta2) of its pre-projection norm, or when its Schur pivot is below floor2.
 //
-// Lane c owns column c of the Schur complement in registers.  Per pivot step the owner of the
-// pivot column publishes it to LDS (double-buffered, so one barrier per step suffices; two when
-// several waves exchange their argmax), and every lane applies the rank-1 update to its own
-// column from 16-byte LDS broadcast reads.  With m fixed at compile time every loop over rows
-// is unrolled without guards.
+// The factorization runs in a 2D block-cyclic register layout (one wave for m <= 72, four
+// waves for m = 129), the pivot column published through double-buffered LDS; the triangular
+// inverse and the outputs run one lane per column.  With m fixed at compile time every loop
+// over rows is unrolled.
 #include "device_common.inc"
 
 namespace rbcg {
@@ -41,190 +40,206 @@ __device__ __forceinline__ unsigned pivot_key(bool chosen, double diag, double i
   return 0x80000000u | (((unsigned)__float_as_uint(rel) >> 1) & ~0xFFu) | idx;
 }
 
-__device__ __forceinline__ double max_wave(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  return v;
-}
 
 // LDS layout for block width M (row stride MP = M rounded up to even):
 //   Rl    M*MP       R rows by pivot position (columns in W's order); later the transpose of
-//                    Rhat (row u = column u of Rhat, in pivot order); fast path: F rows
+//                    Rhat (row u = column u of Rhat, in pivot order)
 //   prow  2*(MP+2)   published pivot column + its reference and pre-projection norms
-//   wv    8, wi 8    per-wave argmax (double-buffered) and reductions
+//   wi    8 (+8)     per-wave argmax keys (double-buffered); s and rank after the loop
 //   perm  M, kept M  pivot position -> column of W; kept flag per pivot position
+//   rinv  M          1 / Rhat[s][s] of kept positions
 inline size_t qr_m_lds(int M) {
   const int MP = (M + 1) & ~1;
-  return ((size_t)M * MP + 2 * ((size_t)MP + 2) + 8) * 8 + (8 + 2 * (size_t)M) * 4 + 16;
+  return ((size_t)M * MP + 2 * ((size_t)MP + 2) + (size_t)M) * 8 + (16 + 2 * (size_t)M) * 4 + 32;
 }
 
-template <int M>
-__global__ __launch_bounds__(64 * ((M + 63) / 64)) void k_qr_m(const QrDesc* __restrict__ descs,
-                                                               const int32_t* __restrict__ act) {
-  constexpr int NW = (M + 63) / 64;
-  constexpr int NT = 64 * NW;
+// Factorization in a 2D block-cyclic layout: the GR x GR lanes of the first NWF waves own
+// element (a, c) of the Schur complement in register slot (a / GR, c / GR) when a % GR and
+// c % GR are the lane's row and column index.  Per pivot step a lane needs only the S = M / GR
+// pivot-column values of its rows and of its columns, and applies S x S register FMAs.  The
+// triangular inverse and the outputs then run one lane per column.
+template <int M, int GR, int NWF>
+__global__ __launch_bounds__(64 * ((M + 63) / 64 > NWF ? (M + 63) / 64 : NWF))
+void k_qr_m(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) {
+  constexpr int NWC = (M + 63) / 64;               // waves for the one-lane-per-column phases
+  constexpr int NT = 64 * (NWC > NWF ? NWC : NWF);
+  static_assert(GR * GR == 64 * NWF, "lane grid must fill the factorization waves");
+  static_assert(NWF == 1 || NWF == NT / 64, "either one factorization wave or all waves");
+  constexpr int S = (M + GR - 1) / GR;             // register slots per dimension
   constexpr int MP = (M + 1) & ~1;
   constexpr int PB = MP + 2;
+  constexpr int NCH = (M + 63) / 64;               // 64-bit words of the chosen-column mask
   const QrDesc d = descs[blockIdx.z];
   if (!is_active(act, d.active)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int c = tid;
-  const bool own = c < M;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* Rl = (double*)smem_raw;
   double* prow = Rl + M * MP;
-  double* wv = prow + 2 * PB;
-  int* wi = (int*)(wv + 8);
-  int* perm = wi + 8;
+  int* wi = (int*)(prow + 2 * PB);
+  int* perm = wi + 16;
   int* kept = perm + M;
+  double* rinv = (double*)(((uintptr_t)(kept + M) + 15) & ~(uintptr_t)15);   // 1 / Rhat[s][s]
   const double* __restrict__ G = d.G;
   const int64_t ldg = d.ldg;
 
-  // ---- second pass on a near-identity Gram: G = I + E over the non-zero columns with
-  //      max |E| <= 1e-8 gives R = I + F (F = upper part of E, halved diagonal) and
-  //      R^{-1} = I - F, both exact to O(|E|^2) = rounding level; no sequential factorization.
-  if (!d.pivot && d.prevB) {
-    double emax = 0.0;
-    for (int e = tid; e < M * M; e += NT) {
-      const int a = e / M, cc = e - a * M;
-      const double ga = G[(int64_t)a * ldg + a], gc = G[(int64_t)cc * ldg + cc];
-      if (ga == 0.0 || gc == 0.0) continue;   // deflated (zero) columns
-      emax = fmax(emax, fabs(G[(int64_t)a * ldg + cc] - (a == cc ? 1.0 : 0.0)));
-    }
-    emax = max_wave(emax);
-    if (lane == 0) wv[wave] = emax;
-    __syncthreads();
-    double mx = wv[0];
-#pragma unroll
-    for (int w = 1; w < NW; ++w) mx = fmax(mx, wv[w]);
-    if (mx <= 1e-8) {
-      for (int i = tid; i < M; i += NT) kept[i] = G[(int64_t)i * ldg + i] != 0.0;
-      __syncthreads();
-      for (int e = tid; e < M * MP; e += NT) {
-        const int a = e / MP, cc = e - a * MP;
-        double f = 0.0;
-        if (cc < M && kept[a] && kept[cc] && cc >= a) {
-          const double g = G[(int64_t)a * ldg + cc];
-          f = (a == cc) ? 0.5 * (g - 1.0) : g;
-        }
-        Rl[e] = (a == cc) ? 1.0 + f : f;   // rows of R = I + F
-        if (cc < M) d.Mout[a * M + cc] = (kept[a] && kept[cc]) ? ((a == cc ? 1.0 : 0.0) - f) : 0.0;
-      }
-      for (int i = tid; i < M; i += NT) d.mask[i] = kept[i] ? 0 : 1;
-      if (tid == 0 && d.rank_out) {
-        int rk = 0;
-        for (int i = 0; i < M; ++i) rk += kept[i];
-        *d.rank_out = rk;
-      }
-      __syncthreads();
-      // Bout column c = (I + F) prevB column c; rows of deflated positions zero (their row of
-      // I + F is a unit row, masked here)
-      if (own) {
-        double pb[MP];
-#pragma unroll
-        for (int u = 0; u < MP; ++u) pb[u] = u < M ? d.prevB[u * M + c] : 0.0;
-        for (int s0 = 0; s0 < M; ++s0) {
-          const double* Fs = Rl + s0 * MP;
-          double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-          for (int u = 0; u < MP; u += 2) {
-            const double2 f2 = *(const double2*)(Fs + u);
-            a0 = fma(f2.x, pb[u], a0);
-            a1 = fma(f2.y, pb[u + 1], a1);
-          }
-          d.Bout[s0 * M + c] = kept[s0] ? a0 + a1 : 0.0;
-        }
-      }
-      return;
-    }
-    __syncthreads();
-  }
-
-  // ---- pivoted (or in-order) Cholesky with deflation
-  double v[MP];
-#pragma unroll
-  for (int a = 0; a < MP; ++a) v[a] = (own && a < M) ? G[(int64_t)a * ldg + c] : 0.0;
-  double diag = own ? G[(int64_t)c * ldg + c] : 0.0;
-  const double dref = diag;
-  const double idref = dref > 0.0 ? 1.0 / dref : 0.0;
-  const double pre = (own && d.pre) ? d.pre[(int64_t)c * d.pre_stride] : -1.0;
-  bool chosen = !own;
   for (int e = tid; e < M * MP; e += NT) Rl[e] = 0.0;
   for (int i = tid; i < M; i += NT) {
     perm[i] = i;
     kept[i] = 0;
   }
-  uint64_t ch[NW];   // chosen columns as a uniform bitmask (identical in every lane)
-#pragma unroll
-  for (int w = 0; w < NW; ++w) ch[w] = 0;
   __syncthreads();
 
-  int s = 0, rank = 0;
-  for (; s < M; ++s) {
-    const int buf = s & 1;
-    double* pr = prow + buf * PB;
-    int p = s;
-    if (d.pivot && !(d.force_first && s == 0)) {
-      unsigned key = wave_max_key(pivot_key(chosen, diag, idref, dref > 0.0, c));
-      if constexpr (NW > 1) {
-        if (lane == 0) wi[buf * 4 + wave] = (int)key;
-        __syncthreads();
-        key = (unsigned)wi[buf * 4];
+  if (wave < NWF) {
+    const int rl = tid % GR, cl = tid / GR;
+    const bool dl = rl == cl;                       // holds diagonal elements (slot (i, i))
+    double v[S][S];
 #pragma unroll
-        for (int w = 1; w < NW; ++w) key = max(key, (unsigned)wi[buf * 4 + w]);
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+        const int a = rl + GR * i, c = cl + GR * j;
+        v[i][j] = (a < M && c < M) ? G[(int64_t)a * ldg + c] : 0.0;
       }
-      p = (int)(255u - (key & 0xFFu));
-    }
-    // The owner of column p publishes it (the Schur row p, by symmetry); entry p is the pivot
-    // itself, so r_a = pr[a] / sqrt(pivot) for every row a.  Entries in rows chosen earlier are
-    // rounding leftovers: they only ever update other chosen rows, which nothing reads.
-    if (c == p) {
+    double dref[S], idref[S], pre[S];
 #pragma unroll
-      for (int a = 0; a < MP; a += 2) *(double2*)(pr + a) = double2{v[a], v[a + 1]};
-      pr[MP] = dref;
-      pr[MP + 1] = pre;
+    for (int i = 0; i < S; ++i) {
+      const int a = rl + GR * i;
+      dref[i] = (dl && a < M) ? v[i][i] : 0.0;
+      idref[i] = dref[i] > 0.0 ? 1.0 / dref[i] : 0.0;
+      pre[i] = (dl && a < M && d.pre) ? d.pre[(int64_t)a * d.pre_stride] : -1.0;
     }
-    __syncthreads();
-    const double piv2 = pr[p];
-    const double drp = pr[MP], prp = pr[MP + 1];
-    bool defl;
-    if (d.force_first && s == 0) defl = !(piv2 > 0.0);
-    else
-      defl = !(drp > 0.0) || !(piv2 > d.tau * drp) || (prp >= 0.0 && !(piv2 > d.eta2 * prp)) ||
-             !(piv2 > d.floor2);
-    if (defl && d.pivot) break;   // every remaining column is at least as deficient
-    const bool was_chosen = chosen;
+    uint64_t ch[NCH];
 #pragma unroll
-    for (int w = 0; w < NW; ++w)
-      if ((p >> 6) == w) ch[w] |= 1ull << (p & 63);
-    if (c == p) chosen = true;
-    if (tid == 0) perm[s] = p;
-    if (defl) continue;
-    if (tid == 0) kept[s] = 1;
-    ++rank;
-    const double irp = 1.0 / sqrt(piv2);
-    // my factor R[s][c] (zero for columns chosen before this step; rp for the pivot column)
-    const double rc = (own && !was_chosen) ? pr[c] * irp : 0.0;
-    if (own) Rl[s * MP + c] = rc;
-    const double f = rc * irp;
+    for (int w = 0; w < NCH; ++w) ch[w] = 0;
+    // chosen flags of this lane's diagonal slots (slot i <-> column rl + GR i); slots beyond M
+    // count as chosen
+    unsigned mych = 0u;
 #pragma unroll
-    for (int a = 0; a < MP; a += 2) {
-      const double2 q = *(const double2*)(pr + a);
-      v[a] = fma(-q.x, f, v[a]);
-      v[a + 1] = fma(-q.y, f, v[a + 1]);
+    for (int i = 0; i < S; ++i)
+      if (rl + GR * i >= M) mych |= 1u << i;
+    auto chosen = [&](int a) -> bool {
+      uint64_t w = ch[0];
+#pragma unroll
+      for (int k = 1; k < NCH; ++k)
+        if ((a >> 6) == k) w = ch[k];
+      return (w >> (a & 63)) & 1;
+    };
+    auto sync = [&]() {
+      if constexpr (NWF > 1) __syncthreads();
+      else __builtin_amdgcn_wave_barrier();
+    };
+    int s = 0, rank = 0;
+    for (; s < M; ++s) {
+      const int buf = s & 1;
+      double* pr = prow + buf * PB;
+      int p = s;
+      if (d.pivot && !(d.force_first && s == 0)) {
+        unsigned key = 0u;
+        if (dl) {
+#pragma unroll
+          for (int i = 0; i < S; ++i)
+            if (!((mych >> i) & 1u)) key = max(key, pivot_key(false, v[i][i], idref[i], dref[i] > 0.0, rl + GR * i));
+        }
+        if constexpr (NWF == 1) {
+          // only the GR diagonal lanes (lane rl + GR rl) hold candidates
+          unsigned k2 = (unsigned)__builtin_amdgcn_readlane((int)key, 0);
+#pragma unroll
+          for (int r = 1; r < GR; ++r) k2 = max(k2, (unsigned)__builtin_amdgcn_readlane((int)key, r * (GR + 1)));
+          key = k2;
+        } else {
+          key = wave_max_key(key);
+        }
+        if constexpr (NWF > 1) {
+          if (lane == 0) wi[buf * 4 + wave] = (int)key;
+          __syncthreads();
+          key = (unsigned)wi[buf * 4];
+#pragma unroll
+          for (int w = 1; w < NWF; ++w) key = max(key, (unsigned)wi[buf * 4 + w]);
+        }
+        p = (int)(255u - (key & 0xFFu));
+      }
+      // publish column p (the Schur row p, by symmetry) from its owners; entry p is the pivot
+      // itself.  Entries in rows chosen earlier are rounding leftovers that only ever update
+      // other chosen rows, which nothing reads.
+      const int jp = __builtin_amdgcn_readfirstlane(p / GR);
+      // slot column jp is uniform: one scalar branch per candidate slot (the scheduling barrier
+      // keeps the compiler from turning the cases into per-element selects)
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+        if (j == jp) {
+          __builtin_amdgcn_sched_barrier(0);
+          if (cl == p % GR) {
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+              const int a = rl + GR * i;
+              if (a < M) pr[a] = v[i][j];
+            }
+            if (dl) {
+              pr[MP] = dref[j];
+              pr[MP + 1] = pre[j];
+            }
+          }
+        }
+      }
+      sync();
+      const double piv2 = pr[p];
+      const double drp = pr[MP], prp = pr[MP + 1];
+      bool defl;
+      if (d.force_first && s == 0) defl = !(piv2 > 0.0);
+      else
+        defl = !(drp > 0.0) || !(piv2 > d.tau * drp) || (prp >= 0.0 && !(piv2 > d.eta2 * prp)) ||
+               !(piv2 > d.floor2);
+      if (defl && d.pivot) break;   // every remaining column is at least as deficient
+      double ra[S], rc[S];
+      bool cb[S];                     // column chosen before this step
+#pragma unroll
+      for (int i = 0; i < S; ++i) {
+        const int a = rl + GR * i, c = cl + GR * i;
+        ra[i] = a < M ? pr[a] : 0.0;
+        rc[i] = c < M ? pr[c] : 0.0;
+        cb[i] = c < M ? chosen(c) : true;
+      }
+#pragma unroll
+      for (int w = 0; w < NCH; ++w)
+        if ((p >> 6) == w) ch[w] |= 1ull << (p & 63);
+      if (dl && rl == p % GR) mych |= 1u << (p / GR);
+      if (tid == 0) perm[s] = p;
+      if (defl) continue;
+      ++rank;
+      const double irp = 1.0 / sqrt(piv2);
+      if (tid == 0) {
+        kept[s] = 1;
+        rinv[s] = irp;
+      }
+      const double f = irp * irp;
+      if (rl == 0) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+          const int c = cl + GR * j;
+          if (c < M) Rl[s * MP + c] = cb[j] ? 0.0 : rc[j] * irp;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < S; ++i) {
+        const double ri = ra[i] * f;
+#pragma unroll
+        for (int j = 0; j < S; ++j) v[i][j] = fma(-ri, rc[j], v[i][j]);
+      }
+      // no barrier here: step s + 1 publishes into the other buffer, and step s + 2 reuses this
+      // one only after every wave has passed step s + 1's publication barrier
     }
-    diag -= rc * rc;
+    if (tid == 0) {
+      // positions after the break take the remaining columns, in order, as deflated
+      int pos = s;
+      for (int i = 0; i < M && pos < M; ++i)
+        if (!chosen(i)) perm[pos++] = i;
+      wi[8] = rank;
+    }
   }
   __syncthreads();
-  if (tid == 0) {
-    // positions after the break take the remaining columns, in order, as deflated
-    int pos = s;
-#pragma unroll
-    for (int w = 0; w < NW; ++w)
-      for (int i = 64 * w; i < M && i < 64 * w + 64; ++i)
-        if (!((ch[w] >> (i & 63)) & 1)) perm[pos++] = i;
-  }
-  __syncthreads();
+  const int rank = wi[8];
+  const int c = tid;
+  const bool own = c < M;
 
   // ---- reported coefficient block Bout = R (times prevB); rows of deflated positions zero
   if (own) {
@@ -274,7 +289,7 @@ __global__ __launch_bounds__(64 * ((M + 63) / 64)) void k_qr_m(const QrDesc* __r
     for (int q = M - 1; q >= 0; --q) {
       if (kept[q]) {
         const double* Rq = Rl + q * MP;   // column q of Rhat
-        const double xq = x[q] / Rq[q];
+        const double xq = x[q] * rinv[q];
         x[q] = xq;
 #pragma unroll
         for (int a = 0; a + 1 < q; a += 2) {
@@ -292,11 +307,11 @@ __global__ __launch_bounds__(64 * ((M + 63) / 64)) void k_qr_m(const QrDesc* __r
   }
 }
 
-template <int M>
+template <int M, int GR, int NWF>
 static hipError_t launch_qr_m_t(const QrDesc* dd, int nz, const int32_t* act, hipStream_t st) {
   const size_t lds = qr_m_lds(M);
   if (lds > kLdsCap) return hipErrorInvalidValue;
-  const void* kern = (const void*)k_qr_m<M>;
+  const void* kern = (const void*)k_qr_m<M, GR, NWF>;
   static bool attr = false;
   if (!attr) {
     hipFuncAttributes fa;
@@ -307,18 +322,19 @@ static hipError_t launch_qr_m_t(const QrDesc* dd, int nz, const int32_t* act, hi
     attr = true;
   }
   void* args[] = {(void*)&dd, (void*)&act};
-  return hipLaunchKernel(kern, dim3(1, 1, nz), dim3(64 * ((M + 63) / 64)), args, lds, st);
+  constexpr int NWC = (M + 63) / 64;
+  return hipLaunchKernel(kern, dim3(1, 1, nz), dim3(64 * (NWC > NWF ? NWC : NWF)), args, lds, st);
 }
 
 bool qr_m_supported(int m) { return m == 9 || m == 17 || m == 33 || m == 65 || m == 129; }
 
 hipError_t launch_qr_m(const QrDesc* dd, int nz, int m, const int32_t* act, hipStream_t st) {
   switch (m) {
-    case 9: return launch_qr_m_t<9>(dd, nz, act, st);
-    case 17: return launch_qr_m_t<17>(dd, nz, act, st);
-    case 33: return launch_qr_m_t<33>(dd, nz, act, st);
-    case 65: return launch_qr_m_t<65>(dd, nz, act, st);
-    case 129: return launch_qr_m_t<129>(dd, nz, act, st);
+    case 9: return launch_qr_m_t<9, 8, 1>(dd, nz, act, st);
+    case 17: return launch_qr_m_t<17, 8, 1>(dd, nz, act, st);
+    case 33: return launch_qr_m_t<33, 8, 1>(dd, nz, act, st);
+    case 65: return launch_qr_m_t<65, 8, 1>(dd, nz, act, st);
+    case 129: return launch_qr_m_t<129, 16, 4>(dd, nz, act, st);
     default: return hipErrorInvalidValue;
   }
 }

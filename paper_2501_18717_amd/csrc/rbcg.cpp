@@ -1143,7 +1143,9 @@ static void size_partials(Engine& E) {
       G.splits2 = G.N <= 144 ? nn_splits(d, (int)G.op->n, 1) : 1;
     } else if (G.op->kind == RBCG_OP_DENSE && G.N <= 144) {
       const int t64 = (d + 63) / 64;
-      G.splits2 = std::max(1, std::min(std::max(1, 512 / t64), std::max(1, d / 512)));
+      // about 1024 workgroups: finer granularity lets other CUs absorb a CU held by the
+      // convergence monitor on the side stream
+      G.splits2 = std::max(1, std::min(std::max(1, 1024 / t64), std::max(1, d / 512)));
     } else {
       G.splits2 = pick_splits(tiles, 1, Kp);
     }
