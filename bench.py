@@ -28,6 +28,40 @@ if ROOT not in sys.path:
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 PEAK_HBM_GBS = 8000.0
 
+# HBM traffic of the dominant kernel comes from rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarised in
+# this file; it is used only while the kernel's source is the one the counters were taken on.
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_block_product_f32_d8192.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2501_18717_amd", "csrc", f) for f in ("device_common.inc", "gemm_nt_f32.hip")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP32 block product, or None when absent or stale."""
+    try:
+        with open(TRAFFIC_SUMMARY) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    vals = {}
+    for ln in lines:
+        if ":" in ln and ln.startswith("- "):
+            key, val = ln[2:].split(":", 1)
+            vals[key.strip()] = val.strip().strip("`")
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -45,6 +79,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run three untimed 1 GiB device-to-device copies (known-size reference for "
+                         "HBM counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -67,6 +104,14 @@ def main():
     Ad = torch.from_numpy(A).to(dev)
     bd = torch.from_numpy(b).to(dev)
     omd = torch.from_numpy(Om).to(dev)
+    if args.copy_probe:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy probe: 3 x 1 GiB device copies done")
     ctx = rbcg.Context()
     op = rbcg.DenseOperator(ctx, Ad, lo="f32")
     x_mix = torch.zeros_like(bd)
@@ -158,8 +203,8 @@ def main():
         "config": {"workload": "dense SPD d=8192, lambda_i=i^-1.5, mu=1e-4, k=64, rtol=1e-10 (FP32 MFMA block "
                                "products + FP64 refinement)", "d": d, "k": k, "mu": mu, "rtol": rtol},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS["f32"], "traffic": None,
-                     "kernel": "k_gemm_nt<DT_F32, TN=5, OUT_T=1> (A X block product)",
+                     "frac": achieved / PEAK_TFLOPS["f32"], "traffic": measured_traffic(),
+                     "kernel": "k_mv_tall<DT_F32, TN=5> (A X block product)",
                      "avg_launch_ms": avg_ms, "launches": prof["launches"]},
         "fp64_gpu": {"value": args.steps / t_64, "unit": "solves/s", "ms_per_step": 1e3 * t_64 / args.steps,
                      "iters": info_64["iters"], "relres": info_64["relres"], "rel_a_err_vs_oracle": err_64,
