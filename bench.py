@@ -79,6 +79,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--workload", choices=["dense", "batch", "ridge", "sqrt"], default="dense",
+                    help="dense: the d=8192 system (default); batch: uneven independent systems; "
+                         "ridge: the 64-shift ridge path, n=200000, d=4096; sqrt: RBF sampling, 16384 points")
+    ap.add_argument("--nsys", type=int, default=200, help="batch workload: number of systems")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run three untimed 1 GiB device-to-device copies (known-size reference for "
                          "HBM counter runs)")
@@ -93,6 +97,16 @@ def main():
 
     import synth
     from paper_2501_18717_amd import rbcg
+
+    if args.workload == "batch":
+        run_batch(args)
+        return
+    if args.workload == "ridge":
+        run_ridge(args)
+        return
+    if args.workload == "sqrt":
+        run_sqrt(args)
+        return
 
     d, k, mu, rtol = 8192, 64, 1e-4, 1e-10
     log("generating the d=8192 system (seeded)")
@@ -215,6 +229,197 @@ def main():
                   "rel_a_err_vs_oracle": err_mix},
         "speedup_mixed_vs_fp64": t_64 / t_mix,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_batch(args):
+    """Independent systems of uneven size: d ~ U{1000..16000}, lambda_i = i^-p with p ~ U[1, 3],
+    mu = 10^U[-6, -2], k ~ U{8, 16, 32, 64, 128}; eigenbases from four Householder reflectors,
+    formed on the GPU.  One step = all systems solved to rtol 1e-10 (FP64 products) by one batched
+    rbcg_solve call; the same systems solved one call at a time are timed beside it."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2501_18717_amd import rbcg
+
+    rtol, t_max = 1e-10, 64
+    dev = torch.device("cuda:0")
+    params = synth.batch_params(5, args.nsys, 1000, 16000)
+    log(f"batch: forming {len(params)} systems on the GPU")
+    t0 = time.time()
+    ctx = rbcg.Context()
+    ops, mus, bs, oms, Ads = [], [], [], [], []
+    for pr in params:
+        S = synth.batch_system_fast(5, pr)
+        A = synth.spd_from_reflectors_torch(S["lam"], S["V"], dev)
+        Ads.append(A)
+        ops.append(rbcg.DenseOperator(ctx, A))
+        mus.append(S["mu"])
+        bs.append(torch.from_numpy(S["b"]).to(dev))
+        oms.append(torch.from_numpy(S["omega"]).to(dev))
+    torch.cuda.synchronize()
+    gb = sum(p["d"] ** 2 for p in params) * 8 / 1e9
+    log(f"batch: formed in {time.time() - t0:.1f}s, {gb:.1f} GB of FP64 matrices")
+    opts = [rbcg.opts(t_max, rtol=rtol, matvec="f64", refine_max=3) for _ in params]
+
+    def batched():
+        xs = [torch.zeros_like(b) for b in bs]
+        rc, info = rbcg.solve(ctx, ops, mus, bs, oms, xs, opts, check=False)
+        return rc, info
+
+    def one_at_a_time():
+        infos = []
+        rc = 0
+        for i in range(len(params)):
+            x = torch.zeros_like(bs[i])
+            r, info = rbcg.solve(ctx, [ops[i]], [mus[i]], [bs[i]], [oms[i]], [x], [opts[i]], check=False)
+            rc = rc or r
+            infos += info
+        return rc, infos
+
+    for _ in range(args.warmup):
+        batched()
+        one_at_a_time()
+    torch.cuda.synchronize()
+    t_b = 0.0
+    for _ in range(args.steps):
+        t1 = time.time()
+        rc_b, info_b = batched()
+        torch.cuda.synchronize()
+        t_b += time.time() - t1
+        log(f"batch: batched call {time.time() - t1:.2f}s rc={rc_b}")
+    t_1 = 0.0
+    for _ in range(args.steps):
+        t1 = time.time()
+        rc_1, info_1 = one_at_a_time()
+        torch.cuda.synchronize()
+        t_1 += time.time() - t1
+        log(f"batch: one at a time {time.time() - t1:.2f}s rc={rc_1}")
+    loads = [i["matrix_loads"] for i in info_b]
+    flops = sum(2.0 * p["d"] ** 2 * (p["k"] + 1) * i["matrix_loads"] for p, i in zip(params, info_b))
+    out = {
+        "metric": "solves/s at 1e-8 rel A-norm err: mixed+batched vs plain FP64; HBM/MFMA % peak",
+        "value": len(params) * args.steps / t_b,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_b / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batch of {len(params)} independent dense SPD systems, d in [1000, 16000], "
+                               "lambda_i=i^-p p in [1,3], mu in [1e-6, 1e-2], k in {8..128}, rtol 1e-10, "
+                               "FP64 products, one batched call", "nsys": len(params), "gbytes": gb},
+        "one_at_a_time": {"value": len(params) * args.steps / t_1, "unit": "solves/s",
+                          "ms_per_step": 1e3 * t_1 / args.steps},
+        "speedup_batched_vs_one_at_a_time": t_1 / t_b,
+        "status": {"batched": rc_b, "one_at_a_time": rc_1,
+                   "max_relres": max(i["relres"] for i in info_b),
+                   "loads_min_max": [min(loads), max(loads)]},
+        "block_product_tflops_avg": flops * args.steps / t_b / 1e12,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _timed(fn, steps):
+    import torch
+    torch.cuda.synchronize()
+    t = 0.0
+    out = None
+    for _ in range(steps):
+        t1 = time.time()
+        out = fn()
+        torch.cuda.synchronize()
+        t += time.time() - t1
+    return t, out
+
+
+def run_ridge(args):
+    """Ridge path: Z = G diag(exp(-j/400)) (n = 200000, d = 4096, FP32), 64 shifts log-spaced over
+    [1e-6, 1], k = 128.  One step = the whole path: plain FP64 products at t = 32 (the Krylov space
+    is the whole space, 32 * 129 >= 4096), and BF16 products with FP64 refinement to rtol 2e-12."""
+    import torch
+
+    import synth
+    from paper_2501_18717_amd import rbcg
+
+    log("ridge: generating Z (200000 x 4096, seeded)")
+    P = synth.ridge_problem(3, 200000, 4096, 128)
+    dev = torch.device("cuda:0")
+    ctx = rbcg.Context()
+    Zd = torch.from_numpy(P["Z"]).to(dev)
+    op64 = rbcg.GramOperator(ctx, Zd, lo="f64")
+    op16 = rbcg.GramOperator(ctx, Zd, lo="bf16")
+    bd = torch.from_numpy(P["b"]).to(dev)
+    omd = torch.from_numpy(P["omega"]).to(dev)
+    mus = list(P["mus"])
+    X = torch.zeros((len(mus), 4096), dtype=torch.float64, device=dev)
+    o64 = rbcg.opts(32)
+    o16 = rbcg.opts(32, rtol=2e-12, matvec="bf16", refine_max=20)
+    for _ in range(args.warmup):
+        rbcg.path(ctx, op64, bd, omd, mus, X, o64, check=False)
+        rbcg.path(ctx, op16, bd, omd, mus, X, o16, check=False)
+    t64, (rc64, i64) = _timed(lambda: rbcg.path(ctx, op64, bd, omd, mus, X, o64, check=False), args.steps)
+    log(f"ridge: fp64 {t64 / args.steps:.3f}s per path rc={rc64}")
+    t16, (rc16, i16) = _timed(lambda: rbcg.path(ctx, op16, bd, omd, mus, X, o16, check=False), args.steps)
+    log(f"ridge: bf16 {t16 / args.steps:.3f}s per path rc={rc16} sweeps {i16[0]['refine_sweeps']}")
+    out = {
+        "metric": "solves/s at 1e-8 rel A-norm err: mixed+batched vs plain FP64; HBM/MFMA % peak",
+        "value": len(mus) * args.steps / t16, "unit": "shift solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t16 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16-mfma+f64", "data": "synthetic",
+        "config": {"workload": "ridge path n=200000 d=4096 k=128, 64 shifts in [1e-6, 1], BF16 Z with FP64 "
+                               "refinement to rtol 2e-12", "n": 200000, "d": 4096, "k": 128, "shifts": len(mus)},
+        "fp64_gpu": {"value": len(mus) * args.steps / t64, "unit": "shift solves/s",
+                     "ms_per_step": 1e3 * t64 / args.steps, "status": rc64, "loads": i64[0]["matrix_loads"],
+                     "relres_max": max(i["relres"] for i in i64)},
+        "mixed": {"status": rc16, "refine_sweeps": i16[0]["refine_sweeps"], "loads": i16[0]["matrix_loads"],
+                  "relres_max": max(i["relres"] for i in i16)},
+        "speedup_mixed_vs_fp64": t64 / t16,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_sqrt(args):
+    """Gaussian sampling A^(1/2) B: RBF kernel on 16384 points in [0,1]^3 (length scale 0.1, nugget
+    1e-6), 256 samples in groups of 32, 32 quadrature nodes, t = 64 block products.  One step = all
+    256 samples, with FP64 products and with FP32 products."""
+    import torch
+
+    import synth
+    from paper_2501_18717_amd import rbcg
+
+    log("sqrt: generating the RBF kernel matrix (16384 points, seeded)")
+    P = synth.rbf_problem(4, 16384, 256)
+    dev = torch.device("cuda:0")
+    ctx = rbcg.Context()
+    Ad = torch.from_numpy(P["A"]).to(dev)
+    op = rbcg.DenseOperator(ctx, Ad, lo="f32")
+    Bd = torch.from_numpy(P["B"]).to(dev)
+    Y = torch.zeros_like(Bd)
+    o64 = rbcg.opts(64, nquad=32, group=32)
+    o32 = rbcg.opts(64, nquad=32, group=32, matvec="f32")
+    for _ in range(args.warmup):
+        rbcg.sqrt_apply(ctx, op, Bd, Y, o64, check=False)
+        rbcg.sqrt_apply(ctx, op, Bd, Y, o32, check=False)
+    t64, (rc64, _) = _timed(lambda: rbcg.sqrt_apply(ctx, op, Bd, Y, o64, check=False), args.steps)
+    t32, (rc32, _) = _timed(lambda: rbcg.sqrt_apply(ctx, op, Bd, Y, o32, check=False), args.steps)
+    log(f"sqrt: fp64 {t64 / args.steps:.3f}s, fp32 {t32 / args.steps:.3f}s per 256 samples")
+    out = {
+        "metric": "solves/s at 1e-8 rel A-norm err: mixed+batched vs plain FP64; HBM/MFMA % peak",
+        "value": 256 * args.steps / t64, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t64 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "RBF sampling 16384 points, 256 samples (8 groups of 32), 32 nodes, t=64, FP64 "
+                               "products", "d": 16384, "samples": 256, "nodes": 32, "t": 64},
+        "fp32_products": {"value": 256 * args.steps / t32, "unit": "samples/s", "ms_per_step": 1e3 * t32 / args.steps,
+                          "status": rc32, "note": "about 6e-3 from the FP64 result (no refinement for sampling)"},
+        "status": rc64,
     }
     print(json.dumps(out), flush=True)
 

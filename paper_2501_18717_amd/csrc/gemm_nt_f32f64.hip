@@ -9,3 +9,11 @@ hipError_t nt_f32f64_o0(int tn, const NtDesc* dd, int nz, int maxM, int splits, 
   return dispatch_tn<DT_F32F64, 0, false>(tn, dd, nz, maxM, splits, act, st);
 }
 }  // namespace rbcg
+
+namespace rbcg {
+hipError_t mv_f32f64(int tn, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act,
+                     hipStream_t st) {
+  return pvec ? dispatch_mv<DT_F32F64, true>(tn, dd, nz, maxM, splits, act, st)
+              : dispatch_mv<DT_F32F64, false>(tn, dd, nz, maxM, splits, act, st);
+}
+}  // namespace rbcg

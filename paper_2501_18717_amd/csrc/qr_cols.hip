@@ -13,7 +13,19 @@
 // over rows is unrolled.
 #include "device_common.inc"
 
+#include <utility>
+
 namespace rbcg {
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I = 0 .. N-1, fully expanded.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 // Maximum of a 32-bit key over the 64 lanes of a wave: four DPP stages give every lane the
 // maximum of its row of 16, then the four row maxima are read out (uniform result).
@@ -53,6 +65,81 @@ inline size_t qr_m_lds(int M) {
   return ((size_t)M * MP + 2 * ((size_t)MP + 2) + (size_t)M) * 8 + (16 + 2 * (size_t)M) * 4 + 32;
 }
 
+// Outputs of a factorization whose R rows (by pivot position, columns in W's order) are in Rl:
+// Bout, mask, rank, and Mout = the columns of Rhat^{-1} placed by perm.  One lane per column.
+template <int M>
+__device__ __forceinline__ void qr_epilogue(const QrDesc& d, double* Rl, const int* perm, const int* kept,
+                                            const double* rinv, int rank, int tid) {
+  constexpr int MP = (M + 1) & ~1;
+  const int c = tid;
+  const bool own = c < M;
+
+  // ---- reported coefficient block Bout = R (times prevB); rows of deflated positions zero
+  if (own) {
+    if (d.prevB) {
+      double pb[MP];
+#pragma unroll
+      for (int u = 0; u < MP; ++u) pb[u] = u < M ? d.prevB[u * M + c] : 0.0;
+      for (int s0 = 0; s0 < M; ++s0) {
+        const double* Rs = Rl + s0 * MP;
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int u = 0; u < MP; u += 2) {
+          const double2 r2 = *(const double2*)(Rs + u);
+          a0 = fma(r2.x, pb[u], a0);
+          a1 = fma(r2.y, pb[u + 1], a1);
+        }
+        d.Bout[s0 * M + c] = kept[s0] ? a0 + a1 : 0.0;
+      }
+    } else {
+      for (int s0 = 0; s0 < M; ++s0) d.Bout[s0 * M + c] = kept[s0] ? Rl[s0 * MP + c] : 0.0;
+    }
+    d.mask[c] = kept[c] ? 0 : 1;
+  }
+  if (tid == 0 && d.rank_out) *d.rank_out = rank;
+
+  // ---- transpose of Rhat into Rl: row u = column u of Rhat = column perm[u] of R
+  double col[MP];
+  if (own) {
+    const int pc = perm[c];
+#pragma unroll
+    for (int s0 = 0; s0 < MP; ++s0) col[s0] = s0 < M ? Rl[s0 * MP + pc] : 0.0;
+  }
+  __syncthreads();
+  if (own) {
+#pragma unroll
+    for (int s0 = 0; s0 < MP; s0 += 2) *(double2*)(Rl + c * MP + s0) = double2{col[s0], col[s0 + 1]};
+  }
+  __syncthreads();
+
+  // ---- X = Rhat^{-1} by a right-looking sweep; lane c holds column c (pivot positions):
+  //      for q = M-1 .. 0 (kept): X[q][c] /= Rhat[q][q]; X[a][c] -= Rhat[a][q] X[q][c], a < q
+  if (own) {
+    double x[MP];
+#pragma unroll
+    for (int a = 0; a < MP; ++a) x[a] = (a == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int q = M - 1; q >= 0; --q) {
+      if (kept[q]) {
+        const double* Rq = Rl + q * MP;   // column q of Rhat
+        const double xq = x[q] * rinv[q];
+        x[q] = xq;
+#pragma unroll
+        for (int a = 0; a + 1 < q; a += 2) {
+          const double2 r2 = *(const double2*)(Rq + a);
+          x[a] = fma(-r2.x, xq, x[a]);
+          x[a + 1] = fma(-r2.y, xq, x[a + 1]);
+        }
+        if (q & 1) x[q - 1] = fma(-Rq[q - 1], xq, x[q - 1]);
+      }
+    }
+    // Mout[perm[a]][c] = X[a][c] for kept a <= c (Q column c = sum_a W column a * Mout[a][c])
+    const bool kc = kept[c];
+#pragma unroll
+    for (int a = 0; a < M; ++a) d.Mout[perm[a] * M + c] = (kc && kept[a] && a <= c) ? x[a] : 0.0;
+  }
+}
+
 // Factorization in a 2D block-cyclic layout: the GR x GR lanes of the first NWF waves own
 // element (a, c) of the Schur complement in register slot (a / GR, c / GR) when a % GR and
 // c % GR are the lane's row and column index.  Per pivot step a lane needs only the S = M / GR
@@ -71,6 +158,7 @@ void k_qr_m(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) {
   constexpr int NCH = (M + 63) / 64;               // 64-bit words of the chosen-column mask
   const QrDesc d = descs[blockIdx.z];
   if (!is_active(act, d.active)) return;
+  if (d.retry && *d.retry == 0) return;   // the unpivoted attempt succeeded
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* Rl = (double*)smem_raw;
@@ -237,74 +325,128 @@ void k_qr_m(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) {
     }
   }
   __syncthreads();
-  const int rank = wi[8];
-  const int c = tid;
-  const bool own = c < M;
+  qr_epilogue<M>(d, Rl, perm, kept, rinv, wi[8], tid);
+}
 
-  // ---- reported coefficient block Bout = R (times prevB); rows of deflated positions zero
-  if (own) {
-    if (d.prevB) {
-      double pb[MP];
-#pragma unroll
-      for (int u = 0; u < MP; ++u) pb[u] = u < M ? d.prevB[u * M + c] : 0.0;
-      for (int s0 = 0; s0 < M; ++s0) {
-        const double* Rs = Rl + s0 * MP;
-        double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-        for (int u = 0; u < MP; u += 2) {
-          const double2 r2 = *(const double2*)(Rs + u);
-          a0 = fma(r2.x, pb[u], a0);
-          a1 = fma(r2.y, pb[u + 1], a1);
-        }
-        d.Bout[s0 * M + c] = kept[s0] ? a0 + a1 : 0.0;
-      }
-    } else {
-      for (int s0 = 0; s0 < M; ++s0) d.Bout[s0 * M + c] = kept[s0] ? Rl[s0 * MP + c] : 0.0;
-    }
-    d.mask[c] = kept[c] ? 0 : 1;
-  }
-  if (tid == 0 && d.rank_out) *d.rank_out = rank;
+// Unpivoted attempt at the same factorization, for the common case of a well-conditioned block:
+// the pivot of step s is column s, so the loop over s is unrolled and the pivot column's register
+// slot is a compile-time constant (no argmax, no slot selection).  Any relative Schur pivot below
+// max(tau, 1e-8), or any deflation test that fires, aborts the attempt: retry is set and the
+// pivoted kernel launched after this one redoes the factorization.
+template <int M, int GR, int NWF>
+__global__ __launch_bounds__(64 * ((M + 63) / 64 > NWF ? (M + 63) / 64 : NWF))
+void k_qr_np(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) {
+  constexpr int NWC = (M + 63) / 64;
+  constexpr int NT = 64 * (NWC > NWF ? NWC : NWF);
+  static_assert(GR * GR == 64 * NWF, "lane grid must fill the factorization waves");
+  static_assert(NWF == 1 || NWF == NT / 64, "either one factorization wave or all waves");
+  constexpr int S = (M + GR - 1) / GR;
+  constexpr int MP = (M + 1) & ~1;
+  constexpr int PB = MP + 2;
+  const QrDesc d = descs[blockIdx.z];
+  if (!is_active(act, d.active)) return;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* Rl = (double*)smem_raw;
+  double* prow = Rl + M * MP;
+  int* wi = (int*)(prow + 2 * PB);
+  int* perm = wi + 16;
+  int* kept = perm + M;
+  double* rinv = (double*)(((uintptr_t)(kept + M) + 15) & ~(uintptr_t)15);
+  const double* __restrict__ G = d.G;
+  const int64_t ldg = d.ldg;
+  const double tau = fmax(d.tau, 1e-8);
 
-  // ---- transpose of Rhat into Rl: row u = column u of Rhat = column perm[u] of R
-  double col[MP];
-  if (own) {
-    const int pc = perm[c];
-#pragma unroll
-    for (int s0 = 0; s0 < MP; ++s0) col[s0] = s0 < M ? Rl[s0 * MP + pc] : 0.0;
-  }
-  __syncthreads();
-  if (own) {
-#pragma unroll
-    for (int s0 = 0; s0 < MP; s0 += 2) *(double2*)(Rl + c * MP + s0) = double2{col[s0], col[s0 + 1]};
+  for (int e = tid; e < M * MP; e += NT) Rl[e] = 0.0;
+  for (int i = tid; i < M; i += NT) {
+    perm[i] = i;
+    kept[i] = 1;
   }
   __syncthreads();
 
-  // ---- X = Rhat^{-1} by a right-looking sweep; lane c holds column c (pivot positions):
-  //      for q = M-1 .. 0 (kept): X[q][c] /= Rhat[q][q]; X[a][c] -= Rhat[a][q] X[q][c], a < q
-  if (own) {
-    double x[MP];
+  if (wave < NWF) {
+    const int rl = tid % GR, cl = tid / GR;
+    const bool dl = rl == cl;
+    double v[S][S];
 #pragma unroll
-    for (int a = 0; a < MP; ++a) x[a] = (a == c) ? 1.0 : 0.0;
+    for (int i = 0; i < S; ++i)
 #pragma unroll
-    for (int q = M - 1; q >= 0; --q) {
-      if (kept[q]) {
-        const double* Rq = Rl + q * MP;   // column q of Rhat
-        const double xq = x[q] * rinv[q];
-        x[q] = xq;
-#pragma unroll
-        for (int a = 0; a + 1 < q; a += 2) {
-          const double2 r2 = *(const double2*)(Rq + a);
-          x[a] = fma(-r2.x, xq, x[a]);
-          x[a + 1] = fma(-r2.y, xq, x[a + 1]);
-        }
-        if (q & 1) x[q - 1] = fma(-Rq[q - 1], xq, x[q - 1]);
+      for (int j = 0; j < S; ++j) {
+        const int a = rl + GR * i, c = cl + GR * j;
+        v[i][j] = (a < M && c < M) ? G[(int64_t)a * ldg + c] : 0.0;
       }
-    }
-    // Mout[perm[a]][c] = X[a][c] for kept a <= c (Q column c = sum_a W column a * Mout[a][c])
-    const bool kc = kept[c];
+    double dref[S], pre[S];
 #pragma unroll
-    for (int a = 0; a < M; ++a) d.Mout[perm[a] * M + c] = (kc && kept[a] && a <= c) ? x[a] : 0.0;
+    for (int i = 0; i < S; ++i) {
+      const int a = rl + GR * i;
+      dref[i] = (dl && a < M) ? v[i][i] : 0.0;
+      pre[i] = (dl && a < M && d.pre) ? d.pre[(int64_t)a * d.pre_stride] : -1.0;
+    }
+    bool ok = true;
+    // pivots s = GR js + r: the slot column js is a compile-time constant, r runs at run time
+    static_for<S>([&](auto jc) {
+      constexpr int js = decltype(jc)::value;
+      for (int r = 0; r < GR; ++r) {
+        const int s = GR * js + r;
+        if (s >= M || !ok) break;   // uniform
+        double* pr = prow + (s & 1) * PB;
+        if (cl == r) {
+#pragma unroll
+          for (int i = 0; i < S; ++i) {
+            const int a = rl + GR * i;
+            if (a < M) pr[a] = v[i][js];
+          }
+          if (dl) {
+            pr[MP] = dref[js];
+            pr[MP + 1] = pre[js];
+          }
+        }
+        if constexpr (NWF > 1) __syncthreads();
+        else __builtin_amdgcn_wave_barrier();
+        const double piv2 = pr[s];
+        const double drp = pr[MP], prp = pr[MP + 1];
+        bool bad;
+        if (d.force_first && s == 0) bad = !(piv2 > 0.0);
+        else
+          bad = !(drp > 0.0) || !(piv2 > tau * drp) || (prp >= 0.0 && !(piv2 > d.eta2 * prp)) ||
+                !(piv2 > d.floor2);
+        if (bad) {
+          ok = false;
+          break;
+        }
+        double ra[S], rc[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+          const int a = rl + GR * i, c = cl + GR * i;
+          ra[i] = a < M ? pr[a] : 0.0;
+          rc[i] = c < M ? pr[c] : 0.0;
+        }
+        const double irp = 1.0 / sqrt(piv2);
+        const double f = irp * irp;
+        if (tid == 0) rinv[s] = irp;
+        if (rl == 0) {
+#pragma unroll
+          for (int j = 0; j < S; ++j) {
+            const int c = cl + GR * j;
+            if (c < M) Rl[s * MP + c] = c < s ? 0.0 : rc[j] * irp;
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+          const double ri = ra[i] * f;
+#pragma unroll
+          for (int j = 0; j < S; ++j) v[i][j] = fma(-ri, rc[j], v[i][j]);
+        }
+      }
+    });
+    if (tid == 0) {
+      wi[8] = ok ? M : -1;
+      if (d.retry) *d.retry = ok ? 0 : 1;
+    }
   }
+  __syncthreads();
+  if (wi[8] < 0) return;   // the pivoted kernel takes over
+  qr_epilogue<M>(d, Rl, perm, kept, rinv, M, tid);
 }
 
 template <int M, int GR, int NWF>
@@ -321,9 +463,23 @@ static hipError_t launch_qr_m_t(const QrDesc* dd, int nz, const int32_t* act, hi
     if (e != hipSuccess) return e;
     attr = true;
   }
+  static bool attr_np = false;
+  const void* kern_np = (const void*)k_qr_np<M, GR, NWF>;
+  if (!attr_np) {
+    hipFuncAttributes fa;
+    hipError_t e = hipFuncGetAttributes(&fa, kern_np);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(kern_np, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - (int)fa.sharedSizeBytes);
+    if (e != hipSuccess) return e;
+    attr_np = true;
+  }
   void* args[] = {(void*)&dd, (void*)&act};
   constexpr int NWC = (M + 63) / 64;
-  return hipLaunchKernel(kern, dim3(1, 1, nz), dim3(64 * (NWC > NWF ? NWC : NWF)), args, lds, st);
+  const dim3 block(64 * (NWC > NWF ? NWC : NWF));
+  // unpivoted attempt first; the pivoted kernel returns at once for problems it did not flag
+  hipError_t e = hipLaunchKernel(kern_np, dim3(1, 1, nz), block, args, lds, st);
+  if (e != hipSuccess) return e;
+  return hipLaunchKernel(kern, dim3(1, 1, nz), block, args, lds, st);
 }
 
 bool qr_m_supported(int m) { return m == 9 || m == 17 || m == 33 || m == 65 || m == 129; }

@@ -29,6 +29,9 @@ namespace rbcg {
 bool sqrt_rule(double lo, double hi, int N, double* shifts, double* weights);
 hipError_t mv_f32(int tn, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act, hipStream_t st);
 hipError_t mv_f64(int tn, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act, hipStream_t st);
+hipError_t mv_f32f64(int tn, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act,
+                     hipStream_t st);
+constexpr int DT_F32F64 = 3;   // FP32 values of P, FP64 arithmetic
 }
 
 using namespace rbcg;
@@ -279,7 +282,7 @@ struct Prob {
   bool monitor = true;
   // buffers
   double *C1, *C2, *G, *M1, *M2, *Bc1, *D, *Bsub, *R0, *part, *Lw, *Xw, *Zw, *est, *scale, *ybuf;
-  int32_t *mask, *masktmp, *rank, *fail, *done_at;
+  int32_t *mask, *masktmp, *rank, *fail, *done_at, *qrflag;
   size_t part_elems = 0;
   RowOp rows(int64_t first_row = 0) const {
     // basis rows starting at `first_row` (a multiple of m)
@@ -412,8 +415,11 @@ static hipError_t enqueue(const Launch& L, unsigned char* dbase, const int32_t* 
       if (L.a0 & (1 << 9)) {   // tall block product (64-row tiles, X staged in LDS)
         const int tn = (L.a2 + 15) / 16;
         const bool pvec = (L.a0 >> 10) & 1;
-        return (L.a0 & 0xff) == DT_F32 ? mv_f32(tn, pvec, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a3, act, st)
-                                       : mv_f64(tn, pvec, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a3, act, st);
+        switch (L.a0 & 0xff) {
+          case DT_F32: return mv_f32(tn, pvec, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a3, act, st);
+          case DT_F32F64: return mv_f32f64(tn, pvec, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a3, act, st);
+          default: return mv_f64(tn, pvec, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a3, act, st);
+        }
       }
       return launch_gemm_nt_ex(L.a0 & 0xff, (L.a0 >> 8) & 1, L.flag, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a2,
                                L.a3, act, st);
@@ -663,6 +669,7 @@ static void add_cholqr(Program& pg, std::vector<Launch>& out, Engine& E, int slo
       d.prevB = nullptr;
       d.mask = pr.masktmp;
       d.rank_out = nullptr;
+      d.retry = pr.qrflag;
       d.m = pr.m;
       d.pivot = 1;
       d.force_first = (start && pr.force_first) ? 1 : 0;
@@ -717,7 +724,55 @@ static void add_cholqr(Program& pg, std::vector<Launch>& out, Engine& E, int slo
 }
 
 // The block product W = A Q_j into block slot j+1 for every group.
+// Dense groups of one precision that are batched together: one launch each for the conversion,
+// the product and the split-K finish, problems indexed by blockIdx.z.
+struct DenseBatch {
+  std::vector<CvtDesc> cvt;
+  std::vector<NtDesc> nt;
+  std::vector<FinDesc> fin;
+  int maxd = 0, maxN = 0, splits = 1;
+  bool pvec = true;
+  double flops = 0.0, bytes = 0.0;
+};
+
+static bool batched_dense(const Engine& E, const MvGroup& G) {
+  return E.Gs.size() > 1 && G.op->kind == RBCG_OP_DENSE && G.N <= 144;
+}
+
+static void emit_dense_batch(Program& pg, std::vector<Launch>& out, DenseBatch& B, int dtype) {
+  if (B.nt.empty()) return;
+  if (!B.cvt.empty()) {
+    Launch C{Launch::CVT};
+    C.off = pg.stg.add(B.cvt);
+    C.nz = (int)B.cvt.size();
+    C.a1 = B.maxN;
+    C.a2 = B.maxd;
+    out.push_back(C);
+  }
+  Launch L{Launch::NT};
+  L.off = pg.stg.add(B.nt);
+  L.nz = (int)B.nt.size();
+  L.a0 = dtype | (1 << 8) | (1 << 9) | (B.pvec ? (1 << 10) : 0);
+  L.a1 = B.maxd;
+  L.a2 = B.maxN;
+  L.a3 = B.splits;
+  L.prof = true;
+  L.flops = B.flops;
+  L.bytes = B.bytes;
+  out.push_back(L);
+  if (B.splits > 1) {
+    Launch F{Launch::FIN};
+    F.off = pg.stg.add(B.fin);
+    F.nz = (int)B.fin.size();
+    F.a1 = B.maxd;
+    F.a2 = B.maxN;
+    out.push_back(F);
+  }
+}
+
+// The block product W = A Q_j into block slot j+1 for every group.
 static void add_matvec(Program& pg, std::vector<Launch>& out, Engine& E, int j) {
+  DenseBatch batch64, batch32;
   for (size_t g = 0; g < E.Gs.size(); ++g) {
     MvGroup& G = E.Gs[g];
     const rbcg_op* op = G.op;
@@ -725,6 +780,52 @@ static void add_matvec(Program& pg, std::vector<Launch>& out, Engine& E, int j) 
     const RowOp Xb{G.q + (int64_t)j * G.bs, G.ldv, 0, 0x3fffffff, 0};
     const RowOp Wb{G.q + (int64_t)(j + 1) * G.bs, G.ldv, 0, 0x3fffffff, 0};
     const int d = (int)op->d;
+    if (batched_dense(E, G)) {
+      DenseBatch& B = G.mv_t == RBCG_F32 ? batch32 : batch64;
+      NtDesc nd{};
+      nd.M = d;
+      nd.N = G.N;
+      nd.K = d;
+      nd.active = act_idx;
+      nd.part = G.part;
+      nd.O = Wb;
+      nd.out = nullptr;
+      nd.out_t = DT_F64;
+      if (G.mv_t == RBCG_F32) {
+        CvtDesc c{};
+        c.src = Xb;
+        c.dst = plain_rows(G.xlo, G.ld_xlo);
+        c.rows = G.N;
+        c.cols = d;
+        c.src_t = DT_F64;
+        c.dst_t = DT_F32;
+        c.active = act_idx;
+        B.cvt.push_back(c);
+        nd.P = plain_rows(op->lo, op->ld_lo);
+        nd.X = plain_rows(G.xlo, G.ld_xlo);
+      } else {
+        nd.P = plain_rows(op->data, op->ld);
+        nd.X = Xb;
+        B.pvec = B.pvec && op->ld % 2 == 0 && ((uintptr_t)op->data % 16) == 0;
+      }
+      B.nt.push_back(nd);
+      FinDesc f{};
+      f.part = G.part;
+      f.M = d;
+      f.N = G.N;
+      f.splits = G.splits2;
+      f.mode = FIN_TRANS;
+      f.O = Wb;
+      f.alpha = 1.0;
+      f.active = act_idx;
+      B.fin.push_back(f);
+      B.maxd = std::max(B.maxd, d);
+      B.maxN = std::max(B.maxN, G.N);
+      B.splits = G.splits2;   // common to all batched dense groups (size_partials)
+      B.flops += 2.0 * d * (double)d * G.N;
+      B.bytes += (double)d * d * (G.mv_t == RBCG_F32 ? 4.0 : 8.0);
+      continue;
+    }
     if (op->kind == RBCG_OP_DENSE) {
       NtDesc nd{};
       nd.M = d;
@@ -882,7 +983,9 @@ static void add_matvec(Program& pg, std::vector<Launch>& out, Engine& E, int j) 
         Launch L1{Launch::NT};
         L1.off = pg.stg.add(std::vector<NtDesc>{n1});
         L1.nz = 1;
-        L1.a0 = 3;   // FP32 P, FP64 arithmetic
+        L1.a0 = DT_F32F64;   // FP32 P, FP64 arithmetic
+        if (G.N <= 144 && op->ld % 4 == 0 && ((uintptr_t)op->data % 16) == 0)
+          L1.a0 |= (1 << 9) | (1 << 10);   // tall kernel, 16-byte rows of Z
         L1.a1 = n;
         L1.a2 = G.N;
         L1.a3 = 1;
@@ -934,6 +1037,8 @@ static void add_matvec(Program& pg, std::vector<Launch>& out, Engine& E, int j) 
       }
     }
   }
+  emit_dense_batch(pg, out, batch64, DT_F64);
+  emit_dense_batch(pg, out, batch32, DT_F32);
 }
 
 // Monitor: one block of the shifted block-Cholesky of T + sigma I and the residual estimate,
@@ -1151,6 +1256,23 @@ static void size_partials(Engine& E) {
     }
     G.part_elems = G.splits2 > 1 ? (size_t)G.splits2 * d * G.N : 0;
   }
+  // batched dense groups share one product launch per precision: one split count for all of them,
+  // about 1024 workgroups in total
+  for (int prec : {RBCG_F64, RBCG_F32}) {
+    int tiles = 0, mind = 1 << 30;
+    for (auto& G : E.Gs)
+      if (batched_dense(E, G) && G.mv_t == prec) {
+        tiles += ((int)G.op->d + 63) / 64;
+        mind = std::min(mind, (int)G.op->d);
+      }
+    if (tiles == 0) continue;
+    const int sp = std::max(1, std::min(1024 / tiles, mind / 512));
+    for (auto& G : E.Gs)
+      if (batched_dense(E, G) && G.mv_t == prec) {
+        G.splits2 = sp;
+        G.part_elems = sp > 1 ? (size_t)sp * G.op->d * G.N : 0;
+      }
+  }
 }
 
 // Carve all per-problem and per-group buffers. `extra` adds caller-specific buffers later.
@@ -1198,6 +1320,7 @@ static void carve(Arena& ar, Engine& E) {
     pr.ybuf = ar.take<double>(T * pr.m);
     pr.mask = ar.take<int32_t>((T + 1) * pr.m);
     pr.masktmp = ar.take<int32_t>(pr.m);
+    pr.qrflag = ar.take<int32_t>(4);
     pr.rank = ar.take<int32_t>(1);
     pr.fail = ar.take<int32_t>(1);
     pr.done_at = ar.take<int32_t>(1);

@@ -93,6 +93,9 @@ struct QrDesc {
   double floor2;           // absolute floor on the squared Schur pivot (second pass: columns are
                            // nominally unit, so a pivot below it came from a rounding-dominated
                            // first-pass Schur complement); 0 = none
+  int32_t* retry;          // exact-width first pass: set to 1 by the unpivoted attempt when a
+                           // pivot is small or a column deflates (the pivoted kernel then redoes
+                           // the factorization), 0 otherwise; null = always pivot
 };
 
 // Symmetrised diagonal block of T from the two projection passes.

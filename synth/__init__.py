@@ -155,3 +155,50 @@ def batch_system(config_id: int, params: dict) -> dict:
     Om = gaussian_block(params["d"], params["k"], rng(config_id * 100000 + sub, 2))
     return {"A": A, "lam": lam, "b": b, "omega": Om, "mu": params["mu"],
             "d": params["d"], "k": params["k"]}
+
+
+# ---- batches at full size: spectra exact, eigenvectors from a few Householder reflectors, so a
+#      d = 16000 system is formed in O(d^2) (on the GPU for the benchmark, in numpy for oracle checks)
+
+def reflector_vectors(d: int, r: int, g: np.random.Generator) -> np.ndarray:
+    """r unit vectors of length d (shape (r, d)), Gaussian directions."""
+    V = g.standard_normal((r, d))
+    return V / np.linalg.norm(V, axis=1, keepdims=True)
+
+
+def spd_from_reflectors(lam: np.ndarray, V: np.ndarray) -> np.ndarray:
+    """A = H_r ... H_1 diag(lam) H_1 ... H_r with H_i = I - 2 v_i v_i^T (numpy, FP64)."""
+    A = np.diag(np.asarray(lam, dtype=np.float64))
+    for v in V:
+        w = A @ v
+        A = A - 2.0 * np.outer(v, w) - 2.0 * np.outer(w, v) + 4.0 * float(v @ w) * np.outer(v, v)
+    return np.ascontiguousarray(0.5 * (A + A.T))
+
+
+def spd_from_reflectors_torch(lam: np.ndarray, V: np.ndarray, device):
+    """The same matrix formed with torch on `device` (FP64), for sizes the host cannot hold."""
+    import torch
+    lam_t = torch.as_tensor(np.asarray(lam, dtype=np.float64), device=device)
+    A = torch.diag(lam_t)
+    for v in V:
+        vt = torch.as_tensor(v, device=device)
+        w = A @ vt
+        A.addr_(vt, w, alpha=-2.0)
+        A.addr_(w, vt, alpha=-2.0)
+        A.addr_(vt, vt, alpha=4.0 * float(vt @ w))
+    A = 0.5 * (A + A.T)
+    return A.contiguous()
+
+
+def batch_system_fast(config_id: int, params: dict, reflectors: int = 4) -> dict:
+    """One system of a batch with a reflector-built eigenbasis: the spectrum, right-hand side,
+    Gaussian block and reflector vectors (A itself is formed by the caller, on the device or in
+    numpy)."""
+    i = params["sys"]
+    sub = 1000 + i
+    d = params["d"]
+    lam = power_spectrum(d, params["p"])
+    V = reflector_vectors(d, reflectors, rng(config_id * 100000 + sub, 3))
+    b = rng(config_id * 100000 + sub, 1).standard_normal(d)
+    Om = gaussian_block(d, params["k"], rng(config_id * 100000 + sub, 2))
+    return {"lam": lam, "V": V, "b": b, "omega": Om, "mu": params["mu"], "d": d, "k": params["k"]}
