@@ -31,7 +31,7 @@ PEAK_HBM_GBS = 8000.0
 # HBM traffic of the dominant kernel comes from rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarised in
 # this file; it is used only while the kernel's source is the one the counters were taken on.
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_block_product_f32_d8192.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2501_18717_amd", "csrc", f) for f in ("device_common.inc", "gemm_nt_f32.hip")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2501_18717_amd", "csrc", f) for f in ("device_common.inc", "mv_f32_wide.hip")]
 
 
 def kernel_source_hash():
@@ -218,7 +218,7 @@ def main():
                                "products + FP64 refinement)", "d": d, "k": k, "mu": mu, "rtol": rtol},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS["f32"], "traffic": measured_traffic(),
-                     "kernel": "k_mv_tall<DT_F32, TN=5> (A X block product)",
+                     "kernel": "k_mv_wide<2, 1, 4> (A X block product, FP32 32x32x2 MFMA + one VALU column)",
                      "avg_launch_ms": avg_ms, "launches": prof["launches"]},
         "fp64_gpu": {"value": args.steps / t_64, "unit": "solves/s", "ms_per_step": 1e3 * t_64 / args.steps,
                      "iters": info_64["iters"], "relres": info_64["relres"], "rel_a_err_vs_oracle": err_64,

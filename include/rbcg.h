@@ -111,6 +111,10 @@ typedef struct {
   int32_t group;       /* rbcg_sqrt_apply: samples per Krylov block (default 32 when 0) */
   double eta;          /* deflation threshold relative to a block's pre-projection norm
                           (default 1e-10 when 0) */
+  double sweep_tol;    /* low-precision products with rtol > 0: reduction of the residual
+                          that one Krylov space aims for before the next FP64 residual
+                          (0 = default: 1e-6 for FP32, 1e-3 for BF16); never below what
+                          the remaining rtol needs */
 } rbcg_opts;
 
 /* Per-result report. */

@@ -13,19 +13,8 @@
 // over rows is unrolled.
 #include "device_common.inc"
 
-#include <utility>
 
 namespace rbcg {
-
-// Compile-time loop: f(std::integral_constant<int, I>) for I = 0 .. N-1, fully expanded.
-template <typename F, int... I>
-__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, I...>) {
-  (f(std::integral_constant<int, I>{}), ...);
-}
-template <int N, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-  static_for_impl(f, std::make_integer_sequence<int, N>{});
-}
 
 // Maximum of a 32-bit key over the 64 lanes of a wave: four DPP stages give every lane the
 // maximum of its row of 16, then the four row maxima are read out (uniform result).
@@ -146,8 +135,7 @@ __device__ __forceinline__ void qr_epilogue(const QrDesc& d, double* Rl, const i
 // pivot-column values of its rows and of its columns, and applies S x S register FMAs.  The
 // triangular inverse and the outputs then run one lane per column.
 template <int M, int GR, int NWF>
-__global__ __launch_bounds__(64 * ((M + 63) / 64 > NWF ? (M + 63) / 64 : NWF))
-void k_qr_m(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) {
+__device__ __forceinline__ void qr_pivoted(const QrDesc& d) {
   constexpr int NWC = (M + 63) / 64;               // waves for the one-lane-per-column phases
   constexpr int NT = 64 * (NWC > NWF ? NWC : NWF);
   static_assert(GR * GR == 64 * NWF, "lane grid must fill the factorization waves");
@@ -156,9 +144,6 @@ void k_qr_m(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) {
   constexpr int MP = (M + 1) & ~1;
   constexpr int PB = MP + 2;
   constexpr int NCH = (M + 63) / 64;               // 64-bit words of the chosen-column mask
-  const QrDesc d = descs[blockIdx.z];
-  if (!is_active(act, d.active)) return;
-  if (d.retry && *d.retry == 0) return;   // the unpivoted attempt succeeded
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* Rl = (double*)smem_raw;
@@ -331,8 +316,8 @@ void k_qr_m(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) {
 // Unpivoted attempt at the same factorization, for the common case of a well-conditioned block:
 // the pivot of step s is column s, so the loop over s is unrolled and the pivot column's register
 // slot is a compile-time constant (no argmax, no slot selection).  Any relative Schur pivot below
-// max(tau, 1e-8), or any deflation test that fires, aborts the attempt: retry is set and the
-// pivoted kernel launched after this one redoes the factorization.
+// max(tau, 1e-8), or any deflation test that fires, aborts the attempt, and the same workgroup
+// redoes the factorization with pivoting.
 template <int M, int GR, int NWF>
 __global__ __launch_bounds__(64 * ((M + 63) / 64 > NWF ? (M + 63) / 64 : NWF))
 void k_qr_np(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) {
@@ -386,6 +371,7 @@ void k_qr_np(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) 
     // pivots s = GR js + r: the slot column js is a compile-time constant, r runs at run time
     static_for<S>([&](auto jc) {
       constexpr int js = decltype(jc)::value;
+#pragma nounroll
       for (int r = 0; r < GR; ++r) {
         const int s = GR * js + r;
         if (s >= M || !ok) break;   // uniform
@@ -439,13 +425,14 @@ void k_qr_np(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) 
         }
       }
     });
-    if (tid == 0) {
-      wi[8] = ok ? M : -1;
-      if (d.retry) *d.retry = ok ? 0 : 1;
-    }
+    if (tid == 0) wi[8] = ok ? M : -1;
   }
   __syncthreads();
-  if (wi[8] < 0) return;   // the pivoted kernel takes over
+  if (wi[8] < 0) {   // uniform: redo the factorization with pivoting
+    __syncthreads();
+    qr_pivoted<M, GR, NWF>(d);
+    return;
+  }
   qr_epilogue<M>(d, Rl, perm, kept, rinv, M, tid);
 }
 
@@ -453,8 +440,8 @@ template <int M, int GR, int NWF>
 static hipError_t launch_qr_m_t(const QrDesc* dd, int nz, const int32_t* act, hipStream_t st) {
   const size_t lds = qr_m_lds(M);
   if (lds > kLdsCap) return hipErrorInvalidValue;
-  const void* kern = (const void*)k_qr_m<M, GR, NWF>;
   static bool attr = false;
+  const void* kern = (const void*)k_qr_np<M, GR, NWF>;
   if (!attr) {
     hipFuncAttributes fa;
     hipError_t e = hipFuncGetAttributes(&fa, kern);
@@ -463,22 +450,9 @@ static hipError_t launch_qr_m_t(const QrDesc* dd, int nz, const int32_t* act, hi
     if (e != hipSuccess) return e;
     attr = true;
   }
-  static bool attr_np = false;
-  const void* kern_np = (const void*)k_qr_np<M, GR, NWF>;
-  if (!attr_np) {
-    hipFuncAttributes fa;
-    hipError_t e = hipFuncGetAttributes(&fa, kern_np);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(kern_np, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - (int)fa.sharedSizeBytes);
-    if (e != hipSuccess) return e;
-    attr_np = true;
-  }
   void* args[] = {(void*)&dd, (void*)&act};
   constexpr int NWC = (M + 63) / 64;
   const dim3 block(64 * (NWC > NWF ? NWC : NWF));
-  // unpivoted attempt first; the pivoted kernel returns at once for problems it did not flag
-  hipError_t e = hipLaunchKernel(kern_np, dim3(1, 1, nz), block, args, lds, st);
-  if (e != hipSuccess) return e;
   return hipLaunchKernel(kern, dim3(1, 1, nz), block, args, lds, st);
 }
 
@@ -489,7 +463,7 @@ hipError_t launch_qr_m(const QrDesc* dd, int nz, int m, const int32_t* act, hipS
     case 9: return launch_qr_m_t<9, 8, 1>(dd, nz, act, st);
     case 17: return launch_qr_m_t<17, 8, 1>(dd, nz, act, st);
     case 33: return launch_qr_m_t<33, 8, 1>(dd, nz, act, st);
-    case 65: return launch_qr_m_t<65, 8, 1>(dd, nz, act, st);
+    case 65: return launch_qr_m_t<65, 16, 4>(dd, nz, act, st);
     case 129: return launch_qr_m_t<129, 16, 4>(dd, nz, act, st);
     default: return hipErrorInvalidValue;
   }

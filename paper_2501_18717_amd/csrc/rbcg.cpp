@@ -29,6 +29,8 @@ namespace rbcg {
 bool sqrt_rule(double lo, double hi, int N, double* shifts, double* weights);
 hipError_t mv_f32(int tn, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act, hipStream_t st);
 hipError_t mv_f64(int tn, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act, hipStream_t st);
+hipError_t mv_f32_wide(int t2, int ne, int w, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act,
+                       hipStream_t st);
 hipError_t mv_f32f64(int tn, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act,
                      hipStream_t st);
 constexpr int DT_F32F64 = 3;   // FP32 values of P, FP64 arithmetic
@@ -282,7 +284,7 @@ struct Prob {
   bool monitor = true;
   // buffers
   double *C1, *C2, *G, *M1, *M2, *Bc1, *D, *Bsub, *R0, *part, *Lw, *Xw, *Zw, *est, *scale, *ybuf;
-  int32_t *mask, *masktmp, *rank, *fail, *done_at, *qrflag;
+  int32_t *mask, *masktmp, *rank, *fail, *done_at;
   size_t part_elems = 0;
   RowOp rows(int64_t first_row = 0) const {
     // basis rows starting at `first_row` (a multiple of m)
@@ -342,6 +344,26 @@ static int proj_splits(int M, int nz, int K) {
   const int want = std::max(1, 768 / std::max(1, tiles * nz));
   const int cap = std::max(1, K / 256);
   return std::max(1, std::min(want, std::min(cap, 64)));
+}
+
+// Widths served by the FP32 32x32x2 product kernel: N = 32 t2 + ne (ne = 1: the last column on
+// the vector ALU).
+static bool wide_shape(int N, int* t2, int* ne) {
+  switch (N) {
+    case 33: *t2 = 1; *ne = 1; return true;
+    case 64: *t2 = 2; *ne = 0; return true;
+    case 65: *t2 = 2; *ne = 1; return true;
+    case 129: *t2 = 4; *ne = 1; return true;
+    default: return false;
+  }
+}
+
+// Splits of the wide FP32 product (128-row workgroups): about 512 workgroups (256 for the
+// 129-wide kernel, whose register use allows one wave per SIMD), at least 512 values of k each.
+static int wide_splits(int d, int N) {
+  const int tiles = (d + 127) / 128;
+  const int want = std::max(1, (N > 96 ? 256 : 512) / tiles);
+  return std::max(1, std::min(want, std::max(1, d / 512)));
 }
 
 // Descriptor staging: host copies, later uploaded in one transfer.
@@ -412,6 +434,11 @@ static void prof_collect(rbcg_ctx* c) {
 static hipError_t enqueue(const Launch& L, unsigned char* dbase, const int32_t* act, hipStream_t st) {
   switch (L.kind) {
     case Launch::NT:
+      if (L.a0 & (1 << 11)) {   // FP32 product on the 32x32x2 kernel
+        int t2 = 0, ne = 0;
+        if (!wide_shape(L.a2, &t2, &ne)) return hipErrorInvalidValue;
+        return mv_f32_wide(t2, ne, 4, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a3, act, st);
+      }
       if (L.a0 & (1 << 9)) {   // tall block product (64-row tiles, X staged in LDS)
         const int tn = (L.a2 + 15) / 16;
         const bool pvec = (L.a0 >> 10) & 1;
@@ -431,6 +458,10 @@ static hipError_t enqueue(const Launch& L, unsigned char* dbase, const int32_t* 
     case Launch::QR: return launch_qr_factor(dptr<QrDesc>(dbase, L.off), L.nz, L.a1, L.flag, act, st);
     case Launch::DIAG: return launch_diag(dptr<DiagDesc>(dbase, L.off), L.nz, L.a1, act, st);
     case Launch::TRIF:
+      if (L.flag) {   // one block width for every problem of the launch
+        const hipError_t e = launch_tri_exact(dptr<TriDesc>(dbase, L.off), L.nz, L.a1, L.a2, L.a3, L.a3 + 1, act, st);
+        if (e != hipErrorNotSupported) return e;
+      }
       return launch_tri_forward(dptr<TriDesc>(dbase, L.off), L.nz, L.a1, L.a2, L.a3, L.a3 + 1, act, st);
     case Launch::CONV: return launch_converge(dptr<ConvDesc>(dbase, L.off), L.nz, st);
     case Launch::CVT: return launch_convert(dptr<CvtDesc>(dbase, L.off), L.nz, L.a1, L.a2, act, st);
@@ -445,6 +476,7 @@ struct Program {
   Staging stg;
   std::vector<std::vector<Launch>> steps;   // steps[0] = start block, steps[j+1] = Lanczos step j
   std::vector<std::vector<Launch>> mon;     // mon[j]: monitor of step j (runs on the side stream)
+  std::vector<int> prod_end;                // steps[j][0 .. prod_end[j]) is the block product
 };
 
 // Build NT descriptors "rows [0, M) of basis p against block rows X" for all problems.
@@ -645,6 +677,14 @@ static void add_rmul(Program& pg, std::vector<Launch>& out, Engine& E, int slot,
 
 // Two rounds of pivoted Cholesky QR of block slot `slot`; the second writes the basis mask of
 // that slot and the coefficient block (R0 for the start block, B_j afterwards).
+// Forward sweep over blocks [j0, j1) for descriptors of one block width m: the exact-width
+// kernel where it applies, else the generic one.
+static hipError_t tri_forward_any(const TriDesc* dd, int nz, int m, int r, int j0, int j1, hipStream_t st) {
+  const hipError_t e = launch_tri_exact(dd, nz, m, r, j0, j1, nullptr, st);
+  if (e != hipErrorNotSupported) return e;
+  return launch_tri_forward(dd, nz, m, r, j0, j1, nullptr, st);
+}
+
 static bool uniform_width(const Engine& E) {
   for (const auto& pr : E.P)
     if (pr.m != E.maxm) return false;
@@ -669,7 +709,6 @@ static void add_cholqr(Program& pg, std::vector<Launch>& out, Engine& E, int slo
       d.prevB = nullptr;
       d.mask = pr.masktmp;
       d.rank_out = nullptr;
-      d.retry = pr.qrflag;
       d.m = pr.m;
       d.pivot = 1;
       d.force_first = (start && pr.force_first) ? 1 : 0;
@@ -864,7 +903,9 @@ static void add_matvec(Program& pg, std::vector<Launch>& out, Engine& E, int j) 
       L.off = pg.stg.add(std::vector<NtDesc>{nd});
       L.nz = 1;
       const bool pvec = dtype == DT_F32 || (op->ld % 2 == 0 && ((uintptr_t)op->data % 16) == 0);
-      L.a0 = dtype | (1 << 8) | (G.N <= 144 ? (1 << 9) : 0) | (pvec ? (1 << 10) : 0);
+      int t2 = 0, ne = 0;
+      const bool wide = dtype == DT_F32 && wide_shape(G.N, &t2, &ne);
+      L.a0 = dtype | (1 << 8) | (G.N <= 144 ? (1 << 9) : 0) | (pvec ? (1 << 10) : 0) | (wide ? (1 << 11) : 0);
       L.a1 = d;
       L.a2 = G.N;
       L.a3 = splits;
@@ -1078,6 +1119,7 @@ static void add_monitor(Program& pg, std::vector<Launch>& out, Engine& E, int j,
   Launch L{Launch::TRIF};
   L.off = pg.stg.add(td);
   L.nz = (int)td.size();
+  L.flag = uniform_width(E);
   L.a1 = E.maxm;
   L.a2 = 1;
   L.a3 = j;
@@ -1104,6 +1146,7 @@ static void build_program(Program& pg, Engine& E, const std::vector<double>& tol
                           const Refill* refill = nullptr) {
   pg.steps.assign(E.t_max + 1, {});
   pg.mon.assign(E.t_max, {});
+  pg.prod_end.assign(E.t_max + 1, 0);
   // start block: caller-provided copies into block 0, then Cholesky QR (R0 = coefficients)
   {
     auto& out = pg.steps[0];
@@ -1180,6 +1223,7 @@ static void build_program(Program& pg, Engine& E, const std::vector<double>& tol
   for (int j = 0; j < E.t_max; ++j) {
     auto& out = pg.steps[j + 1];
     add_matvec(pg, out, E, j);
+    pg.prod_end[j + 1] = (int)out.size();
     std::vector<double*> c1(E.P.size()), c2(E.P.size()), coef(E.P.size());
     std::vector<const double*> pre(E.P.size());
     for (size_t p = 0; p < E.P.size(); ++p) {
@@ -1213,7 +1257,7 @@ static void build_program(Program& pg, Engine& E, const std::vector<double>& tol
       L.off = pg.stg.add(dd);
       L.nz = (int)dd.size();
       L.a1 = E.maxm;
-      out.push_back(L);
+      out.push_back(L);   // before the next step's projections overwrite C1 and C2
     }
     std::vector<const double*> g1(E.P.size());
     for (size_t p = 0; p < E.P.size(); ++p) g1[p] = E.P[p].C2 + (int64_t)(j + 1) * E.P[p].m * E.P[p].m;
@@ -1241,11 +1285,13 @@ static void size_partials(Engine& E) {
   for (auto& pr : E.P) pr.part_elems = need;
   for (auto& G : E.Gs) {
     const int d = (int)G.op->d;
-    int tiles = (d + 15) / 16;
+    int tiles = (d + 15) / 16, t2w = 0, new_ = 0;
     int Kp = (G.op->kind == RBCG_OP_GRAM && G.mv_t == RBCG_BF16) ? (int)G.op->n : d;
     if (G.op->kind == RBCG_OP_GRAM && G.mv_t != RBCG_BF16) {
       // FP64 path: the second product W = Z^T (Z X) on the tall NN kernel (widths <= 144)
       G.splits2 = G.N <= 144 ? nn_splits(d, (int)G.op->n, 1) : 1;
+    } else if (G.op->kind == RBCG_OP_DENSE && G.mv_t == RBCG_F32 && wide_shape(G.N, &t2w, &new_)) {
+      G.splits2 = wide_splits(d, G.N);
     } else if (G.op->kind == RBCG_OP_DENSE && G.N <= 144) {
       const int t64 = (d + 63) / 64;
       // about 1024 workgroups: finer granularity lets other CUs absorb a CU held by the
@@ -1320,7 +1366,6 @@ static void carve(Arena& ar, Engine& E) {
     pr.ybuf = ar.take<double>(T * pr.m);
     pr.mask = ar.take<int32_t>((T + 1) * pr.m);
     pr.masktmp = ar.take<int32_t>(pr.m);
-    pr.qrflag = ar.take<int32_t>(4);
     pr.rank = ar.take<int32_t>(1);
     pr.fail = ar.take<int32_t>(1);
     pr.done_at = ar.take<int32_t>(1);
@@ -1369,14 +1414,33 @@ static int run_steps(rbcg_ctx* ctx, Engine& E, Program& pg, unsigned char* dbase
     return e;
   };
   int32_t* flags_h = E.active_h;
+  // The monitor of step j (one workgroup per problem on the side stream) is started after the
+  // block product of step j + 1 has been issued, so that it overlaps the small kernels of that
+  // step rather than holding a compute unit the product's workgroups wait for.
+  int pending = -1;
+  auto start_monitor = [&](int jm) -> hipError_t {
+    hipError_t e = hipEventRecord(ctx->ev_mon, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->side, ctx->ev_mon, 0);
+    for (const auto& L : pg.mon[jm])
+      if (e == hipSuccess) e = enqueue(L, dbase, E.active, ctx->side);
+    return e;
+  };
   int j = 0;
   for (; j < E.t_max; ++j) {
-    for (const auto& L : pg.steps[j + 1]) HIP_TRY(run(L));
-    if (!pg.mon[j].empty()) {
-      HIP_TRY(hipEventRecord(ctx->ev_mon, st));
-      HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->ev_mon, 0));
-      for (const auto& L : pg.mon[j]) HIP_TRY(enqueue(L, dbase, E.active, ctx->side));
+    const auto& steps = pg.steps[j + 1];
+    const int pe = (int)pg.prod_end.size() > j + 1 ? pg.prod_end[j + 1] : 0;
+    for (int i = 0; i < (int)steps.size(); ++i) {
+      HIP_TRY(run(steps[i]));
+      if (i + 1 == pe && pending >= 0) {
+        HIP_TRY(start_monitor(pending));
+        pending = -1;
+      }
     }
+    if (pending >= 0) {
+      HIP_TRY(start_monitor(pending));
+      pending = -1;
+    }
+    if (!pg.mon[j].empty()) pending = j;
     // read the flags of this step asynchronously; decide on the previous step's copy
     int32_t* dst = flags_h + (j & 1) * np;
     HIP_TRY(hipMemcpyAsync(dst, E.active, np * sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -1389,6 +1453,7 @@ static int run_steps(rbcg_ctx* ctx, Engine& E, Program& pg, unsigned char* dbase
       if (!any) { ++j; break; }
     }
   }
+  if (pending >= 0) HIP_TRY(start_monitor(pending));
   HIP_TRY(hipStreamSynchronize(st));
   HIP_TRY(hipStreamSynchronize(ctx->side));
   prof_collect(ctx);
@@ -1541,6 +1606,13 @@ static int sqnorms(rbcg_ctx* ctx, RowOp x, int rows, int n, double* dout, double
   return RBCG_OK;
 }
 
+// Residual reduction one low-precision Krylov space aims for (plain FP64: none).
+static double sweep_floor(const rbcg_opts& o) {
+  if (o.matvec == RBCG_F64) return 0.0;
+  if (o.sweep_tol > 0.0) return o.sweep_tol;
+  return o.matvec == RBCG_F32 ? 1e-6 : 1e-3;
+}
+
 static bool valid_opts(const rbcg_opts* o) {
   if (!o) return false;
   if (o->t_max < 1 || o->t_max > 4096) return false;
@@ -1548,6 +1620,7 @@ static bool valid_opts(const rbcg_opts* o) {
   if (o->matvec != RBCG_F64 && o->matvec != RBCG_F32 && o->matvec != RBCG_BF16) return false;
   if (o->rtol > 0.0 && o->refine_max < 1) return false;
   if (o->nquad < 0 || o->group < 0 || !(o->eta >= 0.0)) return false;
+  if (!(o->sweep_tol >= 0.0) || !(o->sweep_tol < 1.0)) return false;
   return true;
 }
 
@@ -1783,8 +1856,7 @@ extern "C" int rbcg_solve(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops
       rnorm[s] = sweep == 0 ? bnorm[s] : relres[s] * bnorm[s];
       if (opts[s].rtol > 0.0) {
         double t = 0.5 * opts[s].rtol * bnorm[s] / std::max(rnorm[s], 1e-300);
-        if (opts[s].matvec == RBCG_F32) t = std::max(t, 1e-6);
-        if (opts[s].matvec == RBCG_BF16) t = std::max(t, 1e-3);
+        t = std::max(t, sweep_floor(opts[s]));
         tol[s] = std::min(t, 0.5);
       }
     }
@@ -2041,8 +2113,7 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
     if (refine) {
       if (sweep > 0) rmax = relres[l_min] * bnorm;
       double t = 0.5 * opts->rtol * bnorm / std::max(rmax, 1e-300);
-      if (opts->matvec == RBCG_F32) t = std::max(t, 1e-6);
-      if (opts->matvec == RBCG_BF16) t = std::max(t, 1e-3);
+      t = std::max(t, sweep_floor(*opts));
       tol[0] = std::min(t, 0.5);
     }
     Program pg;
@@ -2112,7 +2183,7 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
     const size_t o2 = stg.add(std::vector<NnDesc>{nn});
     rc = upload(ctx, stg, dscr);
     if (rc) return rc;
-    HIP_TRY(launch_tri_forward(dptr<TriDesc>(dscr, o1), (int)L, m, 1, 0, t, nullptr, st));
+    HIP_TRY(tri_forward_any(dptr<TriDesc>(dscr, o1), (int)L, m, 1, 0, t, st));
     HIP_TRY(launch_tri_backward(dptr<TriDesc>(dscr, o1), (int)L, m, 1, t, nullptr, st));
     HIP_TRY(launch_gemm_nn_ex(false, dptr<NnDesc>(dscr, o2), 1, (int)L, d, nullptr, st));
     std::vector<int32_t> fh(L);
@@ -2320,7 +2391,7 @@ extern "C" int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, con
       rc = upload(ctx, stg, dscr);
       if (rc) return rc;
       HIP_TRY(hipMemsetAsync(failT, 0, (size_t)ngroups * ntr * 4, st));
-      HIP_TRY(launch_tri_forward(dptr<TriDesc>(dscr, o), ngroups * ntr, m, 1, 0, t, nullptr, st));
+      HIP_TRY(tri_forward_any(dptr<TriDesc>(dscr, o), ngroups * ntr, m, 1, 0, t, st));
       std::vector<int32_t> fh((size_t)ngroups * ntr);
       HIP_TRY(hipMemcpyAsync(fh.data(), failT, fh.size() * 4, hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
@@ -2410,7 +2481,7 @@ extern "C" int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, con
     rc = upload(ctx, stg, dscr);
     if (rc) return rc;
     HIP_TRY(hipMemsetAsync(failN, 0, (size_t)ngroups * nq * 4, st));
-    HIP_TRY(launch_tri_forward(dptr<TriDesc>(dscr, o1), ngroups * nq, m, m, 0, t, nullptr, st));
+    HIP_TRY(tri_forward_any(dptr<TriDesc>(dscr, o1), ngroups * nq, m, m, 0, t, st));
     HIP_TRY(launch_tri_backward(dptr<TriDesc>(dscr, o1), ngroups * nq, m, m, t, nullptr, st));
     HIP_TRY(launch_wsum(dptr<WsumDesc>(dscr, o2), ngroups, (int64_t)t * m * m, nullptr, st));
     HIP_TRY(launch_tmul(dptr<TmulDesc>(dscr, o3), ngroups, (int64_t)(t + 1) * m * m, nullptr, st));

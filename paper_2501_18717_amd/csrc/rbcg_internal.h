@@ -93,9 +93,6 @@ struct QrDesc {
   double floor2;           // absolute floor on the squared Schur pivot (second pass: columns are
                            // nominally unit, so a pivot below it came from a rounding-dominated
                            // first-pass Schur complement); 0 = none
-  int32_t* retry;          // exact-width first pass: set to 1 by the unpivoted attempt when a
-                           // pivot is small or a column deflates (the pivoted kernel then redoes
-                           // the factorization), 0 otherwise; null = always pivot
 };
 
 // Symmetrised diagonal block of T from the two projection passes.
@@ -161,6 +158,11 @@ hipError_t launch_qr_factor(const QrDesc* d_desc, int nz, int maxm, bool uniform
 bool qr_m_supported(int m);
 hipError_t launch_qr_m(const QrDesc* d_desc, int nz, int m, const int32_t* active, hipStream_t st);
 hipError_t launch_diag(const DiagDesc* d_desc, int nz, int maxm, const int32_t* active, hipStream_t st);
+// Forward sweep for one exact block width m in {9, 17, 33, 65, 129} (every descriptor of the
+// launch has that width); hipErrorNotSupported for other widths or when the LDS image does not
+// fit, in which case launch_tri_forward serves.
+hipError_t launch_tri_exact(const TriDesc* d_desc, int nz, int m, int r, int j0, int j1, const int32_t* active,
+                            hipStream_t st);
 hipError_t launch_tri_forward(const TriDesc* d_desc, int nz, int maxm, int maxr, int j0, int j1,
                               const int32_t* active, hipStream_t st);
 hipError_t launch_tri_backward(const TriDesc* d_desc, int nz, int maxm, int maxr, int t,

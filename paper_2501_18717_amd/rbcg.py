@@ -28,7 +28,7 @@ STATUS = {0: "OK", -1: "INVALID_ARG", -2: "NOT_SPD", -3: "BREAKDOWN", -4: "NO_CO
 class Opts(ctypes.Structure):
     _fields_ = [("t_max", ctypes.c_int32), ("rtol", ctypes.c_double), ("matvec", ctypes.c_int32),
                 ("refine_max", ctypes.c_int32), ("nquad", ctypes.c_int32), ("group", ctypes.c_int32),
-                ("eta", ctypes.c_double)]
+                ("eta", ctypes.c_double), ("sweep_tol", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -117,8 +117,9 @@ def _need(t, dtype, shape=None, name="tensor"):
 
 
 def opts(t_max: int, rtol: float = 0.0, matvec: str = "f64", refine_max: int = 1, nquad: int = 0, group: int = 0,
-         eta: float = 0.0) -> Opts:
-    return Opts(int(t_max), float(rtol), DTYPES[matvec], int(refine_max), int(nquad), int(group), float(eta))
+         eta: float = 0.0, sweep_tol: float = 0.0) -> Opts:
+    return Opts(int(t_max), float(rtol), DTYPES[matvec], int(refine_max), int(nquad), int(group), float(eta),
+                float(sweep_tol))
 
 
 class Context:
