@@ -1722,6 +1722,10 @@ extern "C" int rbcg_op_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t N, const 
 }
 
 // ------------------------------------------------------------------------------ solve
+static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, const double* mu,
+                       const double* const* b, const double* const* omega, const int32_t* k, double* const* x,
+                       const rbcg_opts* opts, rbcg_info* info);
+
 extern "C" int rbcg_solve(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, const double* mu,
                           const double* const* b, const double* const* omega, const int32_t* k, double* const* x,
                           const rbcg_opts* opts, rbcg_info* info) {
@@ -1736,6 +1740,49 @@ extern "C" int rbcg_solve(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops
     if (op->device != ctx->device) return RBCG_ERR_INVALID_ARG;
     if (tri_forward_lds(k[s] + 1, 1) > kLdsCap) return RBCG_ERR_INVALID_ARG;
   }
+  // Systems of one block width share every launch of a step; the widths are solved one after the
+  // other, so that each launch is sized (and its kernels specialised) for its own width.
+  std::vector<int> widths;
+  for (int64_t s = 0; s < nsys; ++s)
+    if (std::find(widths.begin(), widths.end(), k[s]) == widths.end()) widths.push_back(k[s]);
+  if (widths.size() == 1) return solve_group(ctx, nsys, ops, mu, b, omega, k, x, opts, info);
+  int ret = RBCG_OK;
+  for (int w : widths) {
+    std::vector<int64_t> idx;
+    for (int64_t s = 0; s < nsys; ++s)
+      if (k[s] == w) idx.push_back(s);
+    const int64_t n = (int64_t)idx.size();
+    std::vector<const rbcg_op*> o(n);
+    std::vector<double> m(n);
+    std::vector<const double*> bb(n), om(n);
+    std::vector<int32_t> kk(n);
+    std::vector<double*> xx(n);
+    std::vector<rbcg_opts> op(n);
+    std::vector<rbcg_info> inf(n);
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t s = idx[i];
+      o[i] = ops[s];
+      m[i] = mu[s];
+      bb[i] = b[s];
+      om[i] = omega ? omega[s] : nullptr;
+      kk[i] = k[s];
+      xx[i] = x[s];
+      op[i] = opts[s];
+    }
+    const int rc = solve_group(ctx, n, o.data(), m.data(), bb.data(), omega ? om.data() : nullptr, kk.data(),
+                               xx.data(), op.data(), inf.data());
+    for (int64_t i = 0; i < n; ++i) info[idx[i]] = inf[i];
+    if (rc == RBCG_ERR_HIP || rc == RBCG_ERR_OOM || rc == RBCG_ERR_INVALID_ARG) return rc;
+  }
+  for (int64_t s = 0; s < nsys; ++s)   // the first failing system's status, as for one width
+    if (info[s].status != RBCG_OK) return info[s].status;
+  return ret;
+}
+
+// One batched solve of systems (any widths; rbcg_solve passes one width at a time).
+static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, const double* mu,
+                       const double* const* b, const double* const* omega, const int32_t* k, double* const* x,
+                       const rbcg_opts* opts, rbcg_info* info) {
   hipStream_t st = ctx->stream;
   Engine E;
   E.t_max = 1;
