@@ -23,6 +23,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace rbcg {
@@ -56,6 +57,11 @@ struct rbcg_ctx {
   std::vector<double> prof_flops, prof_bytes;
   int64_t prof_launches = 0;
   double prof_ms = 0.0, prof_flops_total = 0.0, prof_bytes_total = 0.0;
+  // batches of several block widths: one child context (own streams and workspace) per
+  // further width, driven from its own host thread
+  std::vector<rbcg_ctx*> children;
+  bool owns_stream = false;
+  hipEvent_t ev_in = nullptr;   // caller's stream position the children wait for
 };
 
 struct rbcg_op {
@@ -125,6 +131,13 @@ extern "C" int rbcg_create(rbcg_ctx** out, void* stream) {
 
 extern "C" int rbcg_destroy(rbcg_ctx* c) {
   if (!c) return RBCG_ERR_INVALID_ARG;
+  for (rbcg_ctx* ch : c->children) {
+    const bool own = ch->owns_stream;
+    hipStream_t s = ch->stream;
+    rbcg_destroy(ch);
+    if (own && s) (void)hipStreamDestroy(s);
+  }
+  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->ws) (void)hipFree(c->ws);
   if (c->pinned) (void)hipHostFree(c->pinned);
   for (auto& e : c->ev)
@@ -1746,34 +1759,72 @@ extern "C" int rbcg_solve(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops
   for (int64_t s = 0; s < nsys; ++s)
     if (std::find(widths.begin(), widths.end(), k[s]) == widths.end()) widths.push_back(k[s]);
   if (widths.size() == 1) return solve_group(ctx, nsys, ops, mu, b, omega, k, x, opts, info);
-  int ret = RBCG_OK;
-  for (int w : widths) {
-    std::vector<int64_t> idx;
-    for (int64_t s = 0; s < nsys; ++s)
-      if (k[s] == w) idx.push_back(s);
-    const int64_t n = (int64_t)idx.size();
-    std::vector<const rbcg_op*> o(n);
-    std::vector<double> m(n);
-    std::vector<const double*> bb(n), om(n);
-    std::vector<int32_t> kk(n);
-    std::vector<double*> xx(n);
-    std::vector<rbcg_opts> op(n);
-    std::vector<rbcg_info> inf(n);
-    for (int64_t i = 0; i < n; ++i) {
-      const int64_t s = idx[i];
-      o[i] = ops[s];
-      m[i] = mu[s];
-      bb[i] = b[s];
-      om[i] = omega ? omega[s] : nullptr;
-      kk[i] = k[s];
-      xx[i] = x[s];
-      op[i] = opts[s];
+  // child contexts for the widths after the first, each on a stream of its own that starts where
+  // the caller's stream stands now
+  const size_t nch = widths.size() - 1;
+  while (ctx->children.size() < nch) {
+    hipStream_t s = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    rbcg_ctx* ch = nullptr;
+    const int rc = rbcg_create(&ch, (void*)s);
+    if (rc != RBCG_OK) {
+      (void)hipStreamDestroy(s);
+      return rc;
     }
-    const int rc = solve_group(ctx, n, o.data(), m.data(), bb.data(), omega ? om.data() : nullptr, kk.data(),
-                               xx.data(), op.data(), inf.data());
-    for (int64_t i = 0; i < n; ++i) info[idx[i]] = inf[i];
-    if (rc == RBCG_ERR_HIP || rc == RBCG_ERR_OOM || rc == RBCG_ERR_INVALID_ARG) return rc;
+    ch->owns_stream = true;
+    ctx->children.push_back(ch);
   }
+  if (!ctx->ev_in) HIP_TRY(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(ctx->ev_in, ctx->stream));
+  for (size_t i = 0; i < nch; ++i) HIP_TRY(hipStreamWaitEvent(ctx->children[i]->stream, ctx->ev_in, 0));
+  struct Part {
+    std::vector<int64_t> idx;
+    std::vector<const rbcg_op*> o;
+    std::vector<double> m;
+    std::vector<const double*> bb, om;
+    std::vector<int32_t> kk;
+    std::vector<double*> xx;
+    std::vector<rbcg_opts> op;
+    std::vector<rbcg_info> inf;
+    int rc = RBCG_OK;
+  };
+  std::vector<Part> parts(widths.size());
+  for (size_t w = 0; w < widths.size(); ++w) {
+    Part& P = parts[w];
+    for (int64_t s = 0; s < nsys; ++s)
+      if (k[s] == widths[w]) P.idx.push_back(s);
+    for (int64_t s : P.idx) {
+      P.o.push_back(ops[s]);
+      P.m.push_back(mu[s]);
+      P.bb.push_back(b[s]);
+      P.om.push_back(omega ? omega[s] : nullptr);
+      P.kk.push_back(k[s]);
+      P.xx.push_back(x[s]);
+      P.op.push_back(opts[s]);
+    }
+    P.inf.resize(P.idx.size());
+  }
+  auto run_part = [&](size_t w) {
+    Part& P = parts[w];
+    rbcg_ctx* c = w == 0 ? ctx : ctx->children[w - 1];
+    if (w > 0 && hipSetDevice(c->device) != hipSuccess) {
+      P.rc = RBCG_ERR_HIP;
+      return;
+    }
+    P.rc = solve_group(c, (int64_t)P.idx.size(), P.o.data(), P.m.data(), P.bb.data(), omega ? P.om.data() : nullptr,
+                       P.kk.data(), P.xx.data(), P.op.data(), P.inf.data());
+  };
+  std::vector<std::thread> threads;
+  for (size_t w = 1; w < widths.size(); ++w) threads.emplace_back(run_part, w);
+  run_part(0);
+  for (auto& t : threads) t.join();
+  int ret = RBCG_OK;
+  for (size_t w = 0; w < widths.size(); ++w) {
+    for (size_t i = 0; i < parts[w].idx.size(); ++i) info[parts[w].idx[i]] = parts[w].inf[i];
+    const int rc = parts[w].rc;
+    if (rc == RBCG_ERR_HIP || rc == RBCG_ERR_OOM || rc == RBCG_ERR_INVALID_ARG) ret = ret == RBCG_OK ? rc : ret;
+  }
+  if (ret != RBCG_OK) return ret;
   for (int64_t s = 0; s < nsys; ++s)   // the first failing system's status, as for one width
     if (info[s].status != RBCG_OK) return info[s].status;
   return ret;
