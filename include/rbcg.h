@@ -113,7 +113,7 @@ typedef struct {
                           (default 1e-10 when 0) */
   double sweep_tol;    /* low-precision products with rtol > 0: reduction of the residual
                           that one Krylov space aims for before the next FP64 residual
-                          (0 = default: 1e-6 for FP32, 1e-3 for BF16); never below what
+                          (0 = default: 1e-4 for FP32, 1e-3 for BF16); never below what
                           the remaining rtol needs */
 } rbcg_opts;
 

@@ -1623,7 +1623,7 @@ static int sqnorms(rbcg_ctx* ctx, RowOp x, int rows, int n, double* dout, double
 static double sweep_floor(const rbcg_opts& o) {
   if (o.matvec == RBCG_F64) return 0.0;
   if (o.sweep_tol > 0.0) return o.sweep_tol;
-  return o.matvec == RBCG_F32 ? 1e-6 : 1e-3;
+  return o.matvec == RBCG_F32 ? 1e-4 : 1e-3;
 }
 
 static bool valid_opts(const rbcg_opts* o) {
