@@ -463,7 +463,7 @@ hipError_t launch_qr_m(const QrDesc* dd, int nz, int m, const int32_t* act, hipS
     case 9: return launch_qr_m_t<9, 8, 1>(dd, nz, act, st);
     case 17: return launch_qr_m_t<17, 8, 1>(dd, nz, act, st);
     case 33: return launch_qr_m_t<33, 8, 1>(dd, nz, act, st);
-    case 65: return launch_qr_m_t<65, 16, 4>(dd, nz, act, st);
+    case 65: return launch_qr_m_t<65, 8, 1>(dd, nz, act, st);
     case 129: return launch_qr_m_t<129, 16, 4>(dd, nz, act, st);
     default: return hipErrorInvalidValue;
   }

@@ -23,7 +23,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <map>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 namespace rbcg {
@@ -61,6 +63,9 @@ struct rbcg_ctx {
   // further width, driven from its own host thread
   std::vector<rbcg_ctx*> children;
   bool owns_stream = false;
+  // autotuned split counts of dense block products: (precision, d, N) -> splits
+  std::map<std::tuple<int, int64_t, int>, int> tuned_splits;
+  hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;   // tuning timers
   hipEvent_t ev_in = nullptr;   // caller's stream position the children wait for
 };
 
@@ -138,6 +143,8 @@ extern "C" int rbcg_destroy(rbcg_ctx* c) {
     if (own && s) (void)hipStreamDestroy(s);
   }
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+  if (c->ev_t0) (void)hipEventDestroy(c->ev_t0);
+  if (c->ev_t1) (void)hipEventDestroy(c->ev_t1);
   if (c->ws) (void)hipFree(c->ws);
   if (c->pinned) (void)hipHostFree(c->pinned);
   for (auto& e : c->ev)
@@ -322,6 +329,7 @@ struct MvGroup {
   double* part = nullptr;
   size_t part_elems = 0;
   int splits2 = 1;           // splits of the second gram pass (or of the dense product)
+  std::vector<int> tune;     // dense product: split counts to time before the first step
 };
 
 struct Engine {
@@ -1280,7 +1288,17 @@ static void build_program(Program& pg, Engine& E, const std::vector<double>& tol
 }
 
 // Partial-buffer sizes of the per-problem products (max over all steps) and of the groups.
-static void size_partials(Engine& E) {
+// Split counts worth timing for a dense block product around the heuristic `base`: base / 2,
+// base, 2 base, each at least 2 and leaving at least 512 values of k per split.
+static std::vector<int> split_candidates(int d, int base) {
+  std::vector<int> c;
+  for (int s : {base / 2, base, 2 * base})
+    if (s >= 2 && s <= std::max(1, d / 512) && std::find(c.begin(), c.end(), s) == c.end()) c.push_back(s);
+  return c;
+}
+
+static void size_partials(Engine& E, const rbcg_ctx* ctx = nullptr);
+static void size_partials(Engine& E, const rbcg_ctx* ctx) {
   int K = 0;
   for (auto& pr : E.P) K = std::max(K, pr.d);
   const int nz = (int)E.P.size();
@@ -1313,7 +1331,20 @@ static void size_partials(Engine& E) {
     } else {
       G.splits2 = pick_splits(tiles, 1, Kp);
     }
-    G.part_elems = G.splits2 > 1 ? (size_t)G.splits2 * d * G.N : 0;
+    G.tune.clear();
+    if (ctx && E.Gs.size() == 1 && G.op->kind == RBCG_OP_DENSE && G.N <= 144) {
+      const auto key = std::make_tuple(G.mv_t, (int64_t)d, G.N);
+      const auto it = ctx->tuned_splits.find(key);
+      if (it != ctx->tuned_splits.end()) {
+        G.splits2 = it->second;
+      } else {
+        G.tune = split_candidates(d, G.splits2);
+        if (G.tune.size() < 2) G.tune.clear();
+      }
+    }
+    int smax = G.splits2;
+    for (int s : G.tune) smax = std::max(smax, s);
+    G.part_elems = smax > 1 ? (size_t)smax * d * G.N : 0;
   }
   // batched dense groups share one product launch per precision: one split count for all of them,
   // about 1024 workgroups in total
@@ -1739,6 +1770,45 @@ static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, c
                        const double* const* b, const double* const* omega, const int32_t* k, double* const* x,
                        const rbcg_opts* opts, rbcg_info* info);
 
+// First use of a dense block-product shape in this context: time each candidate split count
+// (the product and its split-K reduction, on the real operator and the carved buffers, before the
+// first step) and keep the fastest for later solves of the same shape.
+static int tune_products(rbcg_ctx* ctx, Engine& E, unsigned char* ddesc) {
+  hipStream_t st = ctx->stream;
+  for (auto& G : E.Gs) {
+    if (G.tune.empty()) continue;
+    if (!ctx->ev_t0) HIP_TRY(hipEventCreate(&ctx->ev_t0));
+    if (!ctx->ev_t1) HIP_TRY(hipEventCreate(&ctx->ev_t1));
+    int best = G.splits2;
+    float best_ms = 0.f;
+    for (int s : G.tune) {
+      G.splits2 = s;
+      Program tp;
+      std::vector<Launch> lv;
+      add_matvec(tp, lv, E, 0);   // W into basis slot 1 from slot 0: scratch before the first step
+      const int rc = upload(ctx, tp.stg, ddesc);
+      if (rc) return rc;
+      for (int rep = 0; rep < 4; ++rep) {
+        if (rep == 1) HIP_TRY(hipEventRecord(ctx->ev_t0, st));
+        for (const auto& L : lv) HIP_TRY(enqueue(L, ddesc, nullptr, st));
+      }
+      HIP_TRY(hipEventRecord(ctx->ev_t1, st));
+      HIP_TRY(hipEventSynchronize(ctx->ev_t1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, ctx->ev_t0, ctx->ev_t1));
+      if (best_ms == 0.f || ms < best_ms) {
+        best_ms = ms;
+        best = s;
+      }
+    }
+    G.splits2 = best;
+    G.tune.clear();
+    ctx->tuned_splits[std::make_tuple(G.mv_t, G.op->d, G.N)] = best;
+  }
+  return RBCG_OK;
+}
+
+
 extern "C" int rbcg_solve(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, const double* mu,
                           const double* const* b, const double* const* omega, const int32_t* k, double* const* x,
                           const rbcg_opts* opts, rbcg_info* info) {
@@ -1858,7 +1928,7 @@ static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, c
     G.ldv = pr.ldv;
     G.mv_t = opts[s].matvec;
   }
-  size_partials(E);
+  size_partials(E, ctx);
   // FP64 residual plans (the dense residual always goes through split partials)
   std::vector<ResidPlan> rplan(nsys);
   size_t rpart = 0, rys = 0;
@@ -1898,6 +1968,8 @@ static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, c
   a1.base = ctx->ws;
   carve_all(a1);
   unsigned char* ddesc = (unsigned char*)ctx->ws + desc_off;
+  rc = tune_products(ctx, E, ddesc);
+  if (rc) return rc;
   rc = ensure_pinned(ctx, (size_t)nsys * 64 + 4096);
   if (rc) return rc;
   E.active_h = (int32_t*)ctx->pinned;
