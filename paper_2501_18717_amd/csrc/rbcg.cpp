@@ -349,21 +349,21 @@ static int pick_splits(int tiles, int nz, int K) {
   return std::max(1, std::min(want, std::min(cap, 256)));
 }
 
-// Splits of the tall NN update (64 output columns per workgroup): about 384 workgroups, at
-// least 128 values of the reduction index per split.
+// Splits of the tall NN update (64 output columns per workgroup): about 768 workgroups, at
+// least 64 values of the reduction index per split.
 static int nn_splits(int N, int Ka, int nz) {
   const int tiles = (N + 63) / 64;
-  const int want = std::max(1, 384 / std::max(1, tiles * nz));
-  const int cap = std::max(1, Ka / 128);
+  const int want = std::max(1, 768 / std::max(1, tiles * nz));
+  const int cap = std::max(1, Ka / 64);
   return std::max(1, std::min(want, std::min(cap, 64)));
 }
 
 // Splits of the projection products [Q_0..Q_j W]^T W on the tall kernel (64-row tiles):
-// about 768 workgroups, at least 256 values of k per split.
+// about 1024 workgroups, at least 128 values of k per split.
 static int proj_splits(int M, int nz, int K) {
   const int tiles = (M + 63) / 64;
-  const int want = std::max(1, 768 / std::max(1, tiles * nz));
-  const int cap = std::max(1, K / 256);
+  const int want = std::max(1, 1024 / std::max(1, tiles * nz));
+  const int cap = std::max(1, K / 128);
   return std::max(1, std::min(want, std::min(cap, 64)));
 }
 
