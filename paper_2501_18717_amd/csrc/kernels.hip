@@ -49,6 +49,19 @@ static hipError_t set_big_lds(const void* k) {
 //   FIN_ROWMAJOR: part[s][i][c] -> out[i*ldo + c]
 //   FIN_TRANS / FIN_RESID: part[s][c][i] -> row c of O, element i
 // ---------------------------------------------------------------------------------------------
+// sum_s p[s * stride] in split order; the loads of four splits are issued together.
+__device__ __forceinline__ double split_sum(const double* __restrict__ p, int64_t stride, int splits) {
+  double v = 0.0;
+  int s = 0;
+  for (; s + 4 <= splits; s += 4) {
+    const double a = p[(int64_t)s * stride], b = p[(int64_t)(s + 1) * stride];
+    const double c = p[(int64_t)(s + 2) * stride], d = p[(int64_t)(s + 3) * stride];
+    v = (((v + a) + b) + c) + d;
+  }
+  for (; s < splits; ++s) v += p[(int64_t)s * stride];
+  return v;
+}
+
 __global__ __launch_bounds__(256) void k_finish(const FinDesc* __restrict__ descs, const int32_t* __restrict__ act) {
   const FinDesc f = descs[blockIdx.z];
   if (!is_active(act, f.active)) return;
@@ -60,8 +73,7 @@ __global__ __launch_bounds__(256) void k_finish(const FinDesc* __restrict__ desc
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
       const int c = (int)(e / f.M), i = (int)(e % f.M);
-      double v = 0.0;
-      for (int s = 0; s < f.splits; ++s) v += f.part[(int64_t)s * total + e];
+      const double v = split_sum(f.part + e, total, f.splits);
       f.out[(int64_t)i * f.ldo + c] = f.alpha * v;
     }
     return;
@@ -70,9 +82,7 @@ __global__ __launch_bounds__(256) void k_finish(const FinDesc* __restrict__ desc
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
     const int o = (int)(e / cols), in = (int)(e % cols);
-    double v = 0.0;
-    for (int s = 0; s < f.splits; ++s) v += f.part[(int64_t)s * total + e];
-    v *= f.alpha;
+    double v = split_sum(f.part + e, total, f.splits) * f.alpha;
     if (rowmajor) {
       f.out[(int64_t)o * f.ldo + in] = v;
     } else if (f.mode == FIN_TRANS) {
