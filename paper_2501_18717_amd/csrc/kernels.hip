@@ -350,6 +350,7 @@ template <int NS>
 __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) {
   const QrDesc d = descs[blockIdx.z];
   if (!is_active(act, d.active)) return;
+  if (d.dg.D) diag_block(d.dg, threadIdx.x, 1024);
   const int m = d.m;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int stripes = 1024 / m;
@@ -624,15 +625,7 @@ hipError_t launch_qr_factor(const QrDesc* dd, int nz, int maxm, bool uniform, co
 __global__ __launch_bounds__(256) void k_diag(const DiagDesc* __restrict__ descs, const int32_t* __restrict__ act) {
   const DiagDesc d = descs[blockIdx.z];
   if (!is_active(act, d.active)) return;
-  const int m = d.m;
-  for (int e = threadIdx.x; e < m * m; e += 256) {
-    const int a = e / m, b = e % m;
-    double v = d.C1[(int64_t)a * d.ldc + b] + d.C1[(int64_t)b * d.ldc + a];
-    if (d.has_c2) v += d.C2[(int64_t)a * d.ldc + b] + d.C2[(int64_t)b * d.ldc + a];
-    v *= 0.5;
-    if (d.mask && (d.mask[a] || d.mask[b])) v = (a == b) ? 1.0 : 0.0;
-    d.D[e] = v;
-  }
+  diag_block(d, threadIdx.x, 256);
 }
 
 hipError_t launch_diag(const DiagDesc* dd, int nz, int maxm, const int32_t* act, hipStream_t st) {
@@ -1139,6 +1132,7 @@ __global__ void k_converge(const ConvDesc* __restrict__ descs, int nz) {
   if (*c.est <= c.tol * (*c.scale)) {
     *c.active_flag = 0;
     *c.done_at = c.step;
+    if (c.host_flag) __hip_atomic_store(c.host_flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 hipError_t launch_converge(const ConvDesc* dd, int nz, hipStream_t st) {

@@ -330,6 +330,8 @@ void k_qr_np(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) 
   constexpr int PB = MP + 2;
   const QrDesc d = descs[blockIdx.z];
   if (!is_active(act, d.active)) return;
+  // the diagonal block of T: by the waves the factorization leaves idle, else up front
+  if (NWF == NT / 64 && d.dg.D) diag_block(d.dg, threadIdx.x, NT);
   const int tid = threadIdx.x, wave = tid >> 6;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* Rl = (double*)smem_raw;
@@ -426,6 +428,8 @@ void k_qr_np(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) 
       }
     });
     if (tid == 0) wi[8] = ok ? M : -1;
+  } else if (d.dg.D) {
+    diag_block(d.dg, tid - 64 * NWF, NT - 64 * NWF);
   }
   __syncthreads();
   if (wi[8] < 0) {   // uniform: redo the factorization with pivoting

@@ -339,7 +339,8 @@ struct Engine {
   int maxm = 1;
   double eta2 = 1e-20, tau = 1e-15;
   int32_t* active = nullptr;    // device, per problem
-  int32_t* active_h = nullptr;  // pinned mirror
+  int32_t* active_h = nullptr;  // pinned staging of the flags
+  int32_t* done_h = nullptr;    // pinned mirror the convergence kernel clears (null: copy the flags)
 };
 
 // splits for an NT product with `tiles` row tiles per problem, nz problems, reduction length K
@@ -713,7 +714,8 @@ static bool uniform_width(const Engine& E) {
 }
 
 static void add_cholqr(Program& pg, std::vector<Launch>& out, Engine& E, int slot, const double* const* pre,
-                       double** coef, bool start, const double* const* g1 = nullptr) {
+                       double** coef, bool start, const double* const* g1 = nullptr,
+                       const DiagDesc* dg = nullptr) {
   // first pass: the Gram matrix comes with the second projection (g1) or is formed here
   if (!g1) add_gram(pg, out, E, slot);
   {
@@ -736,6 +738,7 @@ static void add_cholqr(Program& pg, std::vector<Launch>& out, Engine& E, int slo
       d.active = (int)p;
       d.eta2 = E.eta2;
       d.tau = E.tau;
+      if (dg) d.dg = dg[p];   // the diagonal block of T of the previous basis block
       qr.push_back(d);
     }
     Launch L{Launch::QR};
@@ -1133,6 +1136,7 @@ static void add_monitor(Program& pg, std::vector<Launch>& out, Engine& E, int j,
     c.scale = pr.scale;
     c.tol = tol[p];
     c.active_flag = E.active + p;
+    c.host_flag = E.done_h ? E.done_h + p : nullptr;
     c.done_at = pr.done_at;
     c.step = j;
     cd.push_back(c);
@@ -1259,30 +1263,24 @@ static void build_program(Program& pg, Engine& E, const std::vector<double>& tol
     // Cholesky QR pass (the second update changes W only at rounding level)
     add_proj(pg, out, E, j, true, c2.data());
     add_update(pg, out, E, j, c2.data());
-    {
-      std::vector<DiagDesc> dd;
-      for (size_t p = 0; p < E.P.size(); ++p) {
-        const Prob& pr = E.P[p];
-        DiagDesc d{};
-        d.C1 = pr.C1 + (int64_t)j * pr.m * pr.m;
-        d.C2 = pr.C2 + (int64_t)j * pr.m * pr.m;
-        d.ldc = pr.m;
-        d.D = pr.D + (int64_t)j * pr.m * pr.m;
-        d.mask = pr.mask + (int64_t)j * pr.m;
-        d.m = pr.m;
-        d.has_c2 = 1;
-        d.active = (int)p;
-        dd.push_back(d);
-      }
-      Launch L{Launch::DIAG};
-      L.off = pg.stg.add(dd);
-      L.nz = (int)dd.size();
-      L.a1 = E.maxm;
-      out.push_back(L);   // before the next step's projections overwrite C1 and C2
+    // D_j = sym(C1 + C2) block j, formed by the first Cholesky-QR pass' workgroups
+    std::vector<DiagDesc> dd;
+    for (size_t p = 0; p < E.P.size(); ++p) {
+      const Prob& pr = E.P[p];
+      DiagDesc d{};
+      d.C1 = pr.C1 + (int64_t)j * pr.m * pr.m;
+      d.C2 = pr.C2 + (int64_t)j * pr.m * pr.m;
+      d.ldc = pr.m;
+      d.D = pr.D + (int64_t)j * pr.m * pr.m;
+      d.mask = pr.mask + (int64_t)j * pr.m;
+      d.m = pr.m;
+      d.has_c2 = 1;
+      d.active = (int)p;
+      dd.push_back(d);
     }
     std::vector<const double*> g1(E.P.size());
     for (size_t p = 0; p < E.P.size(); ++p) g1[p] = E.P[p].C2 + (int64_t)(j + 1) * E.P[p].m * E.P[p].m;
-    add_cholqr(pg, out, E, j + 1, pre.data(), coef.data(), false, g1.data());
+    add_cholqr(pg, out, E, j + 1, pre.data(), coef.data(), false, g1.data(), dd.data());
     if (monitor) add_monitor(pg, pg.mon[j], E, j, tol);
   }
 }
@@ -1485,6 +1483,18 @@ static int run_steps(rbcg_ctx* ctx, Engine& E, Program& pg, unsigned char* dbase
       pending = -1;
     }
     if (!pg.mon[j].empty()) pending = j;
+    HIP_TRY(hipEventRecord(ctx->ev[j & 1], st));
+    if (E.done_h) {
+      // the convergence kernels clear the pinned mirror themselves: no copy on the stream; the
+      // host runs at most one step ahead of the device
+      if (j >= 1) {
+        HIP_TRY(hipEventSynchronize(ctx->ev[(j - 1) & 1]));
+        bool any = false;
+        for (int p = 0; p < np; ++p) any |= __atomic_load_n(E.done_h + p, __ATOMIC_ACQUIRE) != 0;
+        if (!any) { ++j; break; }
+      }
+      continue;
+    }
     // read the flags of this step asynchronously; decide on the previous step's copy
     int32_t* dst = flags_h + (j & 1) * np;
     HIP_TRY(hipMemcpyAsync(dst, E.active, np * sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -1508,6 +1518,7 @@ static int run_steps(rbcg_ctx* ctx, Engine& E, Program& pg, unsigned char* dbase
 // --------------------------------------------------------------------------- helpers
 static int set_active_all(rbcg_ctx* ctx, Engine& E, const std::vector<int32_t>& vals) {
   std::memcpy(E.active_h, vals.data(), vals.size() * sizeof(int32_t));
+  if (E.done_h) std::memcpy(E.done_h, vals.data(), vals.size() * sizeof(int32_t));
   HIP_TRY(hipMemcpyAsync(E.active, E.active_h, vals.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   return RBCG_OK;
@@ -1974,6 +1985,7 @@ static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, c
   if (rc) return rc;
   E.active_h = (int32_t*)ctx->pinned;
   double* host_sq = (double*)((char*)ctx->pinned + round_up(nsys * 2 * sizeof(int32_t), 64));
+  E.done_h = (int32_t*)((char*)host_sq + round_up(nsys * sizeof(double), 64));
   HIP_TRY(hipMemcpyAsync(mu_dev, mu, nsys * sizeof(double), hipMemcpyHostToDevice, st));
 
   // ||b||

@@ -71,6 +71,15 @@ struct NnDesc {
   double* part;            // split partials of the tall variant ([s][b][i]) when splits > 1
 };
 
+// Symmetrised diagonal block of T from the two projection passes.
+struct DiagDesc {
+  const double* C1; const double* C2;  // rows of Q_j^T W from each pass (m x m, ld = ldc)
+  int64_t ldc;
+  double* D;                           // T diagonal block j (m x m)
+  const int32_t* mask;                 // deflated columns of Q_j
+  int32_t m, has_c2, active, pad_;
+};
+
 // Factorization of a small Gram matrix G = W^T W (m x m) for Cholesky QR
 // with rank-revealing pivoting and deflation.
 //   Mout[a][s]  : Q = W * Mout  (m x m, zero columns for deflated s)
@@ -93,16 +102,9 @@ struct QrDesc {
   double floor2;           // absolute floor on the squared Schur pivot (second pass: columns are
                            // nominally unit, so a pivot below it came from a rounding-dominated
                            // first-pass Schur complement); 0 = none
+  DiagDesc dg;             // also form this diagonal block of T (dg.D == null: none)
 };
 
-// Symmetrised diagonal block of T from the two projection passes.
-struct DiagDesc {
-  const double* C1; const double* C2;  // rows of Q_j^T W from each pass (m x m, ld = ldc)
-  int64_t ldc;
-  double* D;                           // T diagonal block j (m x m)
-  const int32_t* mask;                 // deflated columns of Q_j
-  int32_t m, has_c2, active, pad_;
-};
 
 // Shifted block-tridiagonal solve (T_t + sigma I) Y = RHS with RHS nonzero
 // only in the first block row.  Blocks: D[j] (diagonal, m x m), Bsub[j]
@@ -197,7 +199,12 @@ hipError_t launch_wsum(const WsumDesc* d_desc, int nz, int64_t maxTotal, const i
 hipError_t launch_tmul(const TmulDesc* d_desc, int nz, int64_t maxTotal, const int32_t* active, hipStream_t st);
 
 // Device-side convergence: clears *active_flag once *est <= tol * *scale, recording the step.
-struct ConvDesc { const double* est; const double* scale; double tol; int32_t* active_flag; int32_t* done_at; int32_t step, pad_; };
+// Convergence test of one problem after step `step`; a converged problem clears its device
+// flag and, when host_flag is set, its mirror in pinned host memory (read by the host loop).
+struct ConvDesc {
+  const double* est; const double* scale; double tol; int32_t* active_flag; int32_t* done_at; int32_t step, pad_;
+  int32_t* host_flag;
+};
 hipError_t launch_converge(const ConvDesc* d_desc, int nz, hipStream_t st);
 
 }  // namespace rbcg
