@@ -347,7 +347,8 @@ __device__ __forceinline__ void wave_argmax(double& v, int& i) {
 // Per pivot step: wave argmax over the published diagonal, publish the pivot row (zeros on
 // retired columns), one FMA per owned element.  Three barriers per step.
 template <int NS>
-__global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) {
+__global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act,
+                                                    int lds_bytes) {
   const QrDesc d = descs[blockIdx.z];
   if (!is_active(act, d.active)) return;
   if (d.dg.D) diag_block(d.dg, threadIdx.x, 1024);
@@ -376,11 +377,12 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
   if (!d.pivot && d.prevB) {
     __shared__ int s_small;
     __shared__ double s_wmax[16];
+    for (int i = tid; i < m; i += 1024) dref[i] = d.G[(int64_t)i * d.ldg + i];
+    __syncthreads();
     double emax = 0.0;
     for (int e = tid; e < m * m; e += 1024) {
       const int a = e / m, cc = e - a * m;
-      const double ga = d.G[(int64_t)a * d.ldg + a], gc = d.G[(int64_t)cc * d.ldg + cc];
-      if (ga == 0.0 || gc == 0.0) continue;   // deflated (zero) columns
+      if (dref[a] == 0.0 || dref[cc] == 0.0) continue;   // deflated (zero) columns
       const double g = d.G[(int64_t)a * d.ldg + cc];
       emax = fmax(emax, fabs(g - (a == cc ? 1.0 : 0.0)));
     }
@@ -396,8 +398,14 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
     __syncthreads();
     if (s_small) {
       // kept[i] = column i non-zero; F in Rl (upper), Bout = (I + F) prevB, Mout = I - F
-      for (int i = tid; i < m; i += 1024) kept[i] = d.G[(int64_t)i * d.ldg + i] != 0.0;
+      for (int i = tid; i < m; i += 1024) {
+        kept[i] = dref[i] != 0.0;
+        d.mask[i] = kept[i] ? 0 : 1;
+      }
       __syncthreads();
+      // prevB in LDS (behind the other arrays) when the launch reserved room, else 16-column panels
+      double* pb = (double*)(((uintptr_t)(kept + m) + 15) & ~(uintptr_t)15);
+      const bool whole = (int64_t)((unsigned char*)(pb + m * m) - smem_raw) <= lds_bytes;
       for (int e = tid; e < m * m; e += 1024) {
         const int a = e / m, cc = e - a * m;
         double f = 0.0;
@@ -407,14 +415,27 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
         }
         Rl[e] = f;
         d.Mout[e] = (kept[a] && kept[cc]) ? ((a == cc ? 1.0 : 0.0) - f) : 0.0;
+        if (whole) pb[e] = d.prevB[e];
       }
-      for (int i = tid; i < m; i += 1024) d.mask[i] = kept[i] ? 0 : 1;
       if (tid == 0 && d.rank_out) {
         int rk = 0;
         for (int i = 0; i < m; ++i) rk += kept[i];
         *d.rank_out = rk;
       }
       __syncthreads();
+      if (whole) {
+        for (int e = tid; e < m * m; e += 1024) {
+          const int s0 = e / m, cc = e - s0 * m;
+          double acc = 0.0;
+          if (kept[s0]) {
+            acc = pb[s0 * m + cc];
+            const double* Fs = Rl + s0 * m;
+            for (int u = s0; u < m; ++u) acc += Fs[u] * pb[u * m + cc];
+          }
+          d.Bout[s0 * m + cc] = acc;
+        }
+        return;
+      }
       for (int c0 = 0; c0 < m; c0 += 16) {
         const int nc = min(16, m - c0);
         for (int e = tid; e < m * 16; e += 1024) {
@@ -596,9 +617,11 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
 hipError_t launch_qr_factor(const QrDesc* dd, int nz, int maxm, bool uniform, const int32_t* act,
                             hipStream_t st) {
   if (uniform && qr_m_supported(maxm)) return launch_qr_m(dd, nz, maxm, act, st);
-  const size_t lds = ((size_t)maxm * maxm + 4 * (size_t)maxm + 16 * (size_t)maxm + 16) * 8 + 16 * 4 +
-                     (size_t)maxm * 3 * 4 + 64;
+  size_t lds = ((size_t)maxm * maxm + 4 * (size_t)maxm + 16 * (size_t)maxm + 16) * 8 + 16 * 4 +
+               (size_t)maxm * 3 * 4 + 64;
   if (lds > kLdsCap) return hipErrorInvalidValue;
+  // room for the whole previous factor behind the other arrays (first-order second pass)
+  if (lds + (size_t)maxm * maxm * 8 + 16 <= kLdsCap) lds += (size_t)maxm * maxm * 8 + 16;
   const int ns = (maxm + (1024 / maxm) - 1) / (1024 / maxm);   // rows per thread
   const void* kern;
   int slot;
@@ -615,7 +638,8 @@ hipError_t launch_qr_factor(const QrDesc* dd, int nz, int maxm, bool uniform, co
     if (e != hipSuccess) return e;
     attr[slot] = true;
   }
-  void* args[] = {(void*)&dd, (void*)&act};
+  int lb = (int)lds;
+  void* args[] = {(void*)&dd, (void*)&act, (void*)&lb};
   return hipLaunchKernel(kern, dim3(1, 1, nz), dim3(1024), args, lds, st);
 }
 
