@@ -170,12 +170,11 @@ template <typename PT, int TB>
 static hipError_t launch_nn_t(const NnDesc* dd, int nz, int maxN, const int32_t* act, hipStream_t st) {
   const size_t lds = (size_t)3 * TB * 4 * 64 * 8;
   auto kern = k_gemm_nn<PT, TB>;
-  static bool attr_set = false;
-  if (!attr_set && lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  attr_set = true;
+  // raised once per process; function-local static initialisation is thread-safe
+  static const hipError_t attr =
+      lds > 64 * 1024 ? hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
+                      : hipSuccess;
+  if (attr != hipSuccess) return attr;
   hipLaunchKernelGGL(kern, dim3((maxN + 15) / 16, 1, nz), dim3(256), lds, st, dd, act);
   return hipGetLastError();
 }
@@ -632,12 +631,11 @@ hipError_t launch_qr_factor(const QrDesc* dd, int nz, int maxm, bool uniform, co
   else if (ns <= 14) { kern = (const void*)k_qr_factor<14>; slot = 4; }
   else if (ns <= 19) { kern = (const void*)k_qr_factor<19>; slot = 5; }
   else return hipErrorInvalidValue;
-  static bool attr[6] = {false, false, false, false, false, false};
-  if (!attr[slot]) {
-    hipError_t e = set_big_lds(kern);
-    if (e != hipSuccess) return e;
-    attr[slot] = true;
-  }
+  static const hipError_t attr[6] = {
+      set_big_lds((const void*)k_qr_factor<1>), set_big_lds((const void*)k_qr_factor<2>),
+      set_big_lds((const void*)k_qr_factor<5>), set_big_lds((const void*)k_qr_factor<9>),
+      set_big_lds((const void*)k_qr_factor<14>), set_big_lds((const void*)k_qr_factor<19>)};
+  if (attr[slot] != hipSuccess) return attr[slot];
   int lb = (int)lds;
   void* args[] = {(void*)&dd, (void*)&act, (void*)&lb};
   return hipLaunchKernel(kern, dim3(1, 1, nz), dim3(1024), args, lds, st);
@@ -943,12 +941,11 @@ hipError_t launch_tri_forward(const TriDesc* dd, int nz, int maxm, int maxr, int
   else if (ns <= 14) { kern = (const void*)k_tri_forward<14>; slot = 4; }
   else if (ns <= 19) { kern = (const void*)k_tri_forward<19>; slot = 5; }
   else return hipErrorInvalidValue;
-  static bool attr[6] = {false, false, false, false, false, false};
-  if (!attr[slot]) {
-    hipError_t e = set_big_lds(kern);
-    if (e != hipSuccess) return e;
-    attr[slot] = true;
-  }
+  static const hipError_t attr[6] = {
+      set_big_lds((const void*)k_tri_forward<1>), set_big_lds((const void*)k_tri_forward<2>),
+      set_big_lds((const void*)k_tri_forward<5>), set_big_lds((const void*)k_tri_forward<9>),
+      set_big_lds((const void*)k_tri_forward<14>), set_big_lds((const void*)k_tri_forward<19>)};
+  if (attr[slot] != hipSuccess) return attr[slot];
   int lb = (int)lds;
   void* args[] = {(void*)&dd, (void*)&j0, (void*)&j1, (void*)&lb, (void*)&act};
   return hipLaunchKernel(kern, dim3(1, 1, nz), dim3(1024), args, lds, st);
@@ -956,8 +953,8 @@ hipError_t launch_tri_forward(const TriDesc* dd, int nz, int maxm, int maxr, int
 
 hipError_t launch_tri_backward(const TriDesc* dd, int nz, int maxm, int maxr, int t, const int32_t* act,
                                hipStream_t st) {
-  static bool attr = false;
-  if (!attr) { hipError_t e = set_big_lds((const void*)k_tri_backward); if (e != hipSuccess) return e; attr = true; }
+  static const hipError_t attr = set_big_lds((const void*)k_tri_backward);
+  if (attr != hipSuccess) return attr;
   const size_t lds = tri_backward_lds(maxm, maxr);
   if (lds > kLdsCap) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_tri_backward, dim3(1, 1, nz), dim3(1024), lds, st, dd, t, act);

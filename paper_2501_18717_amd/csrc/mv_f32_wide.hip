@@ -174,12 +174,11 @@ template <int T2, int NE, int W>
 static hipError_t launch_wide_t(const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act, hipStream_t st) {
   const size_t lds = mv_wide_lds(T2, NE);
   auto kern = k_mv_wide<T2, NE, W>;
-  static bool attr_set = false;
-  if (!attr_set && lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  attr_set = true;
+  // raised once per process; function-local static initialisation is thread-safe
+  static const hipError_t attr =
+      lds > 64 * 1024 ? hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
+                      : hipSuccess;
+  if (attr != hipSuccess) return attr;
   dim3 grid((maxM + 32 * W - 1) / (32 * W), splits, nz);
   hipLaunchKernelGGL(kern, grid, dim3(64 * W), lds, st, dd, splits, act);
   return hipGetLastError();

@@ -444,16 +444,15 @@ template <int M, int GR, int NWF>
 static hipError_t launch_qr_m_t(const QrDesc* dd, int nz, const int32_t* act, hipStream_t st) {
   const size_t lds = qr_m_lds(M);
   if (lds > kLdsCap) return hipErrorInvalidValue;
-  static bool attr = false;
   const void* kern = (const void*)k_qr_np<M, GR, NWF>;
-  if (!attr) {
+  static const hipError_t attr = [&] {   // once per process, thread-safe
     hipFuncAttributes fa;
     hipError_t e = hipFuncGetAttributes(&fa, kern);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - (int)fa.sharedSizeBytes);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - (int)fa.sharedSizeBytes);
+    return e;
+  }();
+  if (attr != hipSuccess) return attr;
   void* args[] = {(void*)&dd, (void*)&act};
   constexpr int NWC = (M + 63) / 64;
   const dim3 block(64 * (NWC > NWF ? NWC : NWF));

@@ -299,15 +299,14 @@ static hipError_t launch_tri_exact_t(const TriDesc* dd, int nz, int r, int j0, i
   const size_t lds = tri_exact_lds(M, r);
   if (lds > kLdsCap) return hipErrorNotSupported;
   const void* kern = (const void*)k_tri_exact<M, GR, NWF>;
-  static bool attr = false;
-  if (!attr) {
+  static const hipError_t attr = [&] {   // once per process, thread-safe
     hipFuncAttributes fa;
     hipError_t e = hipFuncGetAttributes(&fa, kern);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - (int)fa.sharedSizeBytes);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - (int)fa.sharedSizeBytes);
+    return e;
+  }();
+  if (attr != hipSuccess) return attr;
   void* args[] = {(void*)&dd, (void*)&j0, (void*)&j1, (void*)&act};
   return hipLaunchKernel(kern, dim3(1, 1, nz), dim3(256), args, lds, st);
 }
