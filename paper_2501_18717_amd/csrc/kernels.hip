@@ -895,9 +895,10 @@ __global__ __launch_bounds__(1024) void k_tri_backward(const TriDesc* __restrict
   double* S = (double*)smem_raw;   // B_j, then Sinv_j
   double* yb = S + mm;             // rhs'_j - B_j^T y_{j+1}
   double* yn = yb + m * r;         // y_{j+1}
-  for (int j = t - 1; j >= 0; --j) {
+  const int tt = d.nblk > 0 ? d.nblk : t;
+  for (int j = tt - 1; j >= 0; --j) {
     const double* zj = d.Zw + (int64_t)j * m * r;
-    if (j == t - 1) {
+    if (j == tt - 1) {
       for (int e = tid; e < m * r; e += 1024) yb[e] = zj[e];
     } else {
       const double* Bj = d.Bsub + j * mm;
@@ -1150,7 +1151,7 @@ __global__ void k_converge(const ConvDesc* __restrict__ descs, int nz) {
   if (z >= nz) return;
   const ConvDesc c = descs[z];
   if (*c.active_flag == 0) return;
-  if (*c.est <= c.tol * (*c.scale)) {
+  if (*c.est <= (*c.tol) * (*c.scale)) {
     *c.active_flag = 0;
     *c.done_at = c.step;
     if (c.host_flag) __hip_atomic_store(c.host_flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);

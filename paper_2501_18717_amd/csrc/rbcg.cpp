@@ -66,6 +66,12 @@ struct rbcg_ctx {
   // autotuned split counts of dense block products: (precision, d, N) -> splits
   std::map<std::tuple<int, int64_t, int>, int> tuned_splits;
   hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;   // tuning timers
+  // pinned staging of descriptor uploads: the copy runs asynchronously on the stream; the next
+  // upload waits for it before reusing the buffer
+  void* stage = nullptr;
+  size_t stage_cap = 0;
+  hipEvent_t ev_stage = nullptr;
+  bool stage_pending = false;
   hipEvent_t ev_in = nullptr;   // caller's stream position the children wait for
 };
 
@@ -145,6 +151,9 @@ extern "C" int rbcg_destroy(rbcg_ctx* c) {
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->ev_t0) (void)hipEventDestroy(c->ev_t0);
   if (c->ev_t1) (void)hipEventDestroy(c->ev_t1);
+  if (c->stage_pending && c->ev_stage) (void)hipEventSynchronize(c->ev_stage);
+  if (c->stage) (void)hipHostFree(c->stage);
+  if (c->ev_stage) (void)hipEventDestroy(c->ev_stage);
   if (c->ws) (void)hipFree(c->ws);
   if (c->pinned) (void)hipHostFree(c->pinned);
   for (auto& e : c->ev)
@@ -341,6 +350,11 @@ struct Engine {
   int32_t* active = nullptr;    // device, per problem
   int32_t* active_h = nullptr;  // pinned staging of the flags
   int32_t* done_h = nullptr;    // pinned mirror the convergence kernel clears (null: copy the flags)
+  // per-problem values set before each sweep, contiguous so that each is one copy
+  double* tolv = nullptr;       // monitor tolerance (relative to scale)
+  double* scales = nullptr;     // residual norm of the sweep's start vector
+  int32_t* fails = nullptr;
+  int32_t* done_ats = nullptr;
 };
 
 // splits for an NT product with `tiles` row tiles per problem, nz problems, reduction length K
@@ -1134,7 +1148,8 @@ static void add_monitor(Program& pg, std::vector<Launch>& out, Engine& E, int j,
     ConvDesc c{};
     c.est = pr.est + j;
     c.scale = pr.scale;
-    c.tol = tol[p];
+    c.tol = E.tolv + p;   // set before each sweep
+    (void)tol;
     c.active_flag = E.active + p;
     c.host_flag = E.done_h ? E.done_h + p : nullptr;
     c.done_at = pr.done_at;
@@ -1404,15 +1419,23 @@ static void carve(Arena& ar, Engine& E) {
     pr.Xw = ar.take<double>(T * mm);
     pr.Zw = ar.take<double>((T + 1) * pr.m);
     pr.est = ar.take<double>(T);
-    pr.scale = ar.take<double>(1);
+
     pr.ybuf = ar.take<double>(T * pr.m);
     pr.mask = ar.take<int32_t>((T + 1) * pr.m);
     pr.masktmp = ar.take<int32_t>(pr.m);
     pr.rank = ar.take<int32_t>(1);
-    pr.fail = ar.take<int32_t>(1);
-    pr.done_at = ar.take<int32_t>(1);
   }
-  E.active = ar.take<int32_t>(E.P.size());
+  const size_t np = E.P.size();
+  E.active = ar.take<int32_t>(np);
+  E.tolv = ar.take<double>(np);
+  E.scales = ar.take<double>(np);
+  E.fails = ar.take<int32_t>(np);
+  E.done_ats = ar.take<int32_t>(np);
+  for (size_t p = 0; p < np; ++p) {
+    E.P[p].scale = E.scales + p;
+    E.P[p].fail = E.fails + p;
+    E.P[p].done_at = E.done_ats + p;
+  }
 }
 
 static int ensure_ws(rbcg_ctx* ctx, size_t bytes) {
@@ -1436,10 +1459,28 @@ static int ensure_pinned(rbcg_ctx* ctx, size_t bytes) {
 }
 
 // Upload the staged descriptors into `dst` (device) synchronously on the stream.
+// Descriptors to device memory, stream-ordered before the kernels that read them.  The host
+// side goes through pinned staging, so the copy is asynchronous; the previous upload's copy is
+// waited for before its staging is reused.
 static int upload(rbcg_ctx* ctx, const Staging& stg, unsigned char* dst) {
   if (stg.host.empty()) return RBCG_OK;
-  HIP_TRY(hipMemcpyAsync(dst, stg.host.data(), stg.host.size(), hipMemcpyHostToDevice, ctx->stream));
-  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (!ctx->ev_stage) HIP_TRY(hipEventCreateWithFlags(&ctx->ev_stage, hipEventDisableTiming));
+  if (ctx->stage_pending) {
+    HIP_TRY(hipEventSynchronize(ctx->ev_stage));
+    ctx->stage_pending = false;
+  }
+  if (stg.host.size() > ctx->stage_cap) {
+    if (ctx->stage) (void)hipHostFree(ctx->stage);
+    ctx->stage = nullptr;
+    ctx->stage_cap = 0;
+    const size_t cap = (size_t)round_up((int64_t)stg.host.size(), 1 << 20);
+    if (hipHostMalloc(&ctx->stage, cap, hipHostMallocDefault) != hipSuccess) return RBCG_ERR_OOM;
+    ctx->stage_cap = cap;
+  }
+  std::memcpy(ctx->stage, stg.host.data(), stg.host.size());
+  HIP_TRY(hipMemcpyAsync(dst, ctx->stage, stg.host.size(), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(hipEventRecord(ctx->ev_stage, ctx->stream));
+  ctx->stage_pending = true;
   return RBCG_OK;
 }
 
@@ -1966,7 +2007,7 @@ static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, c
     rys_p = a.take<double>(std::max<size_t>(rys, 1));
     mu_dev = a.take<double>(nsys);
     sq_dev = a.take<double>(nsys);
-    dscr = a.take<unsigned char>(1 << 16);
+    dscr = a.take<unsigned char>(std::max<size_t>((size_t)1 << 16, (size_t)nsys * 512));
   };
   Arena a0;
   carve_all(a0);
@@ -1990,6 +2031,11 @@ static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, c
   E.active_h = (int32_t*)ctx->pinned;
   double* host_sq = (double*)((char*)ctx->pinned + round_up(nsys * 2 * sizeof(int32_t), 64));
   E.done_h = (int32_t*)((char*)host_sq + round_up(nsys * sizeof(double), 64));
+  // per-sweep values staged in pinned memory, copied with one transfer each
+  double* tol_h = (double*)((char*)E.done_h + round_up(nsys * sizeof(int32_t), 64));
+  double* scale_h = tol_h + nsys;
+  int32_t* doneat_h = (int32_t*)(scale_h + nsys);
+  int32_t* fail_h = doneat_h + nsys;
   HIP_TRY(hipMemcpyAsync(mu_dev, mu, nsys * sizeof(double), hipMemcpyHostToDevice, st));
 
   // ||b||
@@ -2005,24 +2051,14 @@ static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, c
   int max_sweeps = 1;
   for (int64_t s = 0; s < nsys; ++s) max_sweeps = std::max(max_sweeps, opts[s].rtol > 0 ? (int)opts[s].refine_max : 1);
 
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    // systems taking part in this sweep
-    std::vector<int32_t> act(nsys, 0);
-    bool any = false;
-    for (int64_t s = 0; s < nsys; ++s) {
-      const bool fixed = opts[s].rtol == 0.0;
-      act[s] = (!done[s] && (sweep == 0 || !fixed)) ? 1 : 0;
-      any |= act[s] != 0;
-    }
-    if (!any) break;
-    // start block copies: row 0 = current residual (b on the first sweep), rows 1.. = Omega
+  // The step program is the same for every sweep: the start block is read from rbuf (b is copied
+  // there before the first sweep) and the monitor reads its tolerance from device memory.
+  {
     std::vector<CopyDesc> cps;
-    std::vector<double> tol(nsys, 0.0);
-    std::vector<double> rnorm(nsys, 0.0);
     for (int64_t s = 0; s < nsys; ++s) {
       const Prob& pr = E.P[s];
       CopyDesc c{};
-      c.src = plain_rows(sweep == 0 ? b[s] : rbuf[s], pr.d);
+      c.src = plain_rows(rbuf[s], pr.d);
       c.dst = pr.block(0);
       c.alpha = 1.0;
       c.rows = 1;
@@ -2037,87 +2073,109 @@ static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, c
       o.rows = k[s];
       o.rows_total = k[s];
       o.n = pr.d;
-      o.active = k[s] > 0 ? (int)s : -2;
+      o.active = (int)s;
+      if (k[s] == 0) o.rows = 0, o.rows_total = 0, o.active = -1;
       cps.push_back(o);
-      rnorm[s] = sweep == 0 ? bnorm[s] : relres[s] * bnorm[s];
-      if (opts[s].rtol > 0.0) {
-        double t = 0.5 * opts[s].rtol * bnorm[s] / std::max(rnorm[s], 1e-300);
-        t = std::max(t, sweep_floor(opts[s]));
-        tol[s] = std::min(t, 0.5);
-      }
     }
-    // copy descriptors with inactive systems disabled: a copy whose active index is -2 is skipped
-    for (auto& c : cps)
-      if (c.active == -2) c.rows = 0, c.rows_total = 0, c.active = -1;
     pg = Program();
-    build_program(pg, E, tol, true, cps, E.maxm);
+    build_program(pg, E, std::vector<double>(nsys, 0.0), true, cps, E.maxm);
     if (pg.stg.host.size() + desc_off + 65536 > ctx->ws_cap) return RBCG_ERR_OOM;
     rc = upload(ctx, pg.stg, ddesc);
     if (rc) return rc;
-    rc = set_active_all(ctx, E, act);
-    if (rc) return rc;
-    // monitor scale: ||r|| of the start vector = R0[0][0] is computed on device; use the host norm
+    for (int64_t s = 0; s < nsys; ++s)
+      HIP_TRY(hipMemcpyAsync(rbuf[s], b[s], (size_t)E.P[s].d * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    // systems taking part in this sweep
+    std::vector<int32_t> act(nsys, 0);
+    bool any = false;
     for (int64_t s = 0; s < nsys; ++s) {
-      HIP_TRY(hipMemcpyAsync(E.P[s].scale, &rnorm[s], sizeof(double), hipMemcpyHostToDevice, st));
-      HIP_TRY(hipMemsetAsync(E.P[s].fail, 0, sizeof(int32_t), st));
-      const int32_t tm = opts[s].t_max - 1;
-      HIP_TRY(hipMemcpyAsync(E.P[s].done_at, &tm, sizeof(int32_t), hipMemcpyHostToDevice, st));
+      const bool fixed = opts[s].rtol == 0.0;
+      act[s] = (!done[s] && (sweep == 0 || !fixed)) ? 1 : 0;
+      any |= act[s] != 0;
     }
-    HIP_TRY(hipStreamSynchronize(st));
+    if (!any) break;
+    // monitor tolerance and scale (||r|| of the start vector), step limit, failure flag, activity
+    for (int64_t s = 0; s < nsys; ++s) {
+      const double rnorm = sweep == 0 ? bnorm[s] : relres[s] * bnorm[s];
+      double tol = 0.0;
+      if (opts[s].rtol > 0.0) {
+        double t = 0.5 * opts[s].rtol * bnorm[s] / std::max(rnorm, 1e-300);
+        t = std::max(t, sweep_floor(opts[s]));
+        tol = std::min(t, 0.5);
+      }
+      tol_h[s] = tol;
+      scale_h[s] = rnorm;
+      doneat_h[s] = opts[s].t_max - 1;
+      fail_h[s] = 0;
+      E.active_h[s] = act[s];
+      E.done_h[s] = act[s];
+    }
+    HIP_TRY(hipMemcpyAsync(E.tolv, tol_h, nsys * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(E.scales, scale_h, nsys * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(E.done_ats, doneat_h, nsys * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(E.fails, fail_h, nsys * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(E.active, E.active_h, nsys * sizeof(int32_t), hipMemcpyHostToDevice, st));
     // per-system step limits: a system stops at its own t_max (converge kernel cannot see it), so
     // the engine runs max t_max; systems with smaller t_max are handled by rtol==0 semantics.
     int steps = 0;
     rc = run_steps(ctx, E, pg, ddesc, &steps);
     if (rc) return rc;
     // steps used per system
-    std::vector<int32_t> done_at(nsys), fail(nsys), rank(nsys);
-    for (int64_t s = 0; s < nsys; ++s) {
-      HIP_TRY(hipMemcpyAsync(&done_at[s], E.P[s].done_at, 4, hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipMemcpyAsync(&fail[s], E.P[s].fail, 4, hipMemcpyDeviceToHost, st));
-    }
+    HIP_TRY(hipMemcpyAsync(doneat_h, E.done_ats, nsys * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(fail_h, E.fails, nsys * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    // backward sweeps (each system its own t) and x (+)= Q y
-    for (int64_t s = 0; s < nsys; ++s) {
-      if (!act[s]) continue;
-      const Prob& pr = E.P[s];
-      const int t = std::min(std::min((int)done_at[s] + 1, steps), (int)opts[s].t_max);
-      iters[s] = t;
-      loads[s] += t;
-      sweeps[s] += 1;
-      if (fail[s]) status[s] = RBCG_ERR_NOT_SPD;
+    // backward sweeps (each system its own t) and x (+)= Q y, all systems in two launches
+    {
       Staging stg;
-      TriDesc td{};
-      td.D = pr.D;
-      td.Bsub = pr.Bsub;
-      td.mask = pr.mask;
-      td.rhs = pr.R0;
-      td.ld_rhs = pr.m;
-      td.Lw = pr.Lw;
-      td.Xw = pr.Xw;
-      td.Zw = pr.Zw;
-      td.Y = pr.ybuf;
-      td.ldy = 1;
-      td.m = pr.m;
-      td.r = 1;
-      td.active = -1;
-      NnDesc nn{};
-      nn.P = pr.rows(0);
-      nn.C = pr.ybuf;
-      nn.ldc = 1;
-      nn.Y = plain_rows(x[s], pr.d);
-      nn.O = plain_rows(x[s], pr.d);
-      nn.alpha = 1.0;
-      nn.beta = sweep == 0 ? 0.0 : 1.0;
-      nn.Ka = t * pr.m;
-      nn.Mo = 1;
-      nn.N = pr.d;
-      nn.active = -1;
-      const size_t o1 = stg.add(std::vector<TriDesc>{td});
-      const size_t o2 = stg.add(std::vector<NnDesc>{nn});
+      std::vector<TriDesc> tds;
+      std::vector<NnDesc> nns;
+      int maxd = 1;
+      for (int64_t s = 0; s < nsys; ++s) {
+        if (!act[s]) continue;
+        const Prob& pr = E.P[s];
+        const int t = std::min(std::min((int)doneat_h[s] + 1, steps), (int)opts[s].t_max);
+        iters[s] = t;
+        loads[s] += t;
+        sweeps[s] += 1;
+        if (fail_h[s]) status[s] = RBCG_ERR_NOT_SPD;
+        TriDesc td{};
+        td.D = pr.D;
+        td.Bsub = pr.Bsub;
+        td.mask = pr.mask;
+        td.rhs = pr.R0;
+        td.ld_rhs = pr.m;
+        td.Lw = pr.Lw;
+        td.Xw = pr.Xw;
+        td.Zw = pr.Zw;
+        td.Y = pr.ybuf;
+        td.ldy = 1;
+        td.m = pr.m;
+        td.r = 1;
+        td.active = -1;
+        td.nblk = t;
+        tds.push_back(td);
+        NnDesc nn{};
+        nn.P = pr.rows(0);
+        nn.C = pr.ybuf;
+        nn.ldc = 1;
+        nn.Y = plain_rows(x[s], pr.d);
+        nn.O = plain_rows(x[s], pr.d);
+        nn.alpha = 1.0;
+        nn.beta = sweep == 0 ? 0.0 : 1.0;
+        nn.Ka = t * pr.m;
+        nn.Mo = 1;
+        nn.N = pr.d;
+        nn.active = -1;
+        nns.push_back(nn);
+        maxd = std::max(maxd, pr.d);
+      }
+      const size_t o1 = stg.add(tds);
+      const size_t o2 = stg.add(nns);
       rc = upload(ctx, stg, dscr);
       if (rc) return rc;
-      HIP_TRY(launch_tri_backward(dptr<TriDesc>(dscr, o1), 1, pr.m, 1, t, nullptr, st));
-      HIP_TRY(launch_gemm_nn_ex(false, dptr<NnDesc>(dscr, o2), 1, 1, pr.d, nullptr, st));
+      HIP_TRY(launch_tri_backward(dptr<TriDesc>(dscr, o1), (int)tds.size(), E.maxm, 1, E.t_max, nullptr, st));
+      HIP_TRY(launch_gemm_nn_ex(false, dptr<NnDesc>(dscr, o2), (int)nns.size(), 1, maxd, nullptr, st));
     }
     // FP64 residuals
     for (int64_t s = 0; s < nsys; ++s) {
@@ -2317,6 +2375,7 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
     if (rc) return rc;
     rc = set_active_all(ctx, E, std::vector<int32_t>{1});
     if (rc) return rc;
+    HIP_TRY(hipMemcpy(E.tolv, tol.data(), sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpyAsync(pr.scale, &rmax, sizeof(double), hipMemcpyHostToDevice, st));
     const int32_t tm = E.t_max - 1;
     HIP_TRY(hipMemcpyAsync(pr.done_at, &tm, 4, hipMemcpyHostToDevice, st));

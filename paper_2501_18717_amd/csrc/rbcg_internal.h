@@ -125,7 +125,8 @@ struct TriDesc {
   double* est;             // residual estimate output (monitor) or null
   int32_t* fail;           // set to 1 on a non-positive pivot
   double sigma;
-  int32_t m, r, active, pad_;
+  int32_t m, r, active;
+  int32_t nblk;            // backward sweep: blocks of this descriptor (0: the launch's t)
 };
 
 // Conversion of rows between precisions (RNE).
@@ -202,7 +203,7 @@ hipError_t launch_tmul(const TmulDesc* d_desc, int nz, int64_t maxTotal, const i
 // Convergence test of one problem after step `step`; a converged problem clears its device
 // flag and, when host_flag is set, its mirror in pinned host memory (read by the host loop).
 struct ConvDesc {
-  const double* est; const double* scale; double tol; int32_t* active_flag; int32_t* done_at; int32_t step, pad_;
+  const double* est; const double* scale; const double* tol; int32_t* active_flag; int32_t* done_at; int32_t step, pad_;
   int32_t* host_flag;
 };
 hipError_t launch_converge(const ConvDesc* d_desc, int nz, hipStream_t st);
