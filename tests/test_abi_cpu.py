@@ -33,6 +33,33 @@ def test_exports_every_declared_symbol(lib):
         assert hasattr(lib, n), n
 
 
+def _header_struct(name):
+    src = open(os.path.join(ROOT, "include", "rbcg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    m = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r"\s*;", src)
+    assert m, name
+    fields = []
+    for decl in m.group(1).split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        typ, names = decl.split(None, 1)
+        for n in names.split(","):
+            fields.append((n.strip(), typ))
+    return fields
+
+
+@pytest.mark.parametrize("cname,pyname", [("rbcg_opts", "Opts"), ("rbcg_info", "Info")])
+def test_binding_structs_mirror_header(cname, pyname):
+    """The ctypes structures of the binding have the header's fields, in order and width."""
+    from paper_2501_18717_amd import rbcg
+    width = {"int32_t": ctypes.c_int32, "double": ctypes.c_double, "int64_t": ctypes.c_int64}
+    want = [(n, width[t]) for n, t in _header_struct(cname)]
+    got = list(getattr(rbcg, pyname)._fields_)
+    assert [n for n, _ in got] == [n for n, _ in want]
+    assert [t for _, t in got] == [t for _, t in want]
+
+
 def test_status_strings_and_version(lib):
     from paper_2501_18717_amd import rbcg
     for code in range(-7, 1):

@@ -152,6 +152,50 @@ def test_mixed_f32_refinement_matches_oracle(R):
     assert info["relres"] <= 1e-10
 
 
+def test_repeated_solves_are_bitwise_identical(R):
+    """The first solve of a shape autotunes the block product's split count; later solves reuse
+    it, and the same inputs give the same iterate bit for bit (fixed summation orders)."""
+    import torch
+    rbcg, ctx = R
+    note("repeat solve d=3000 k=64 f64 and f32")
+    P = synth.dense_problem(7, 3000, 1.5, 64, 1e-4)
+    op = rbcg.DenseOperator(ctx, to_dev(P["A"]), lo="f32")
+    bd, omd = to_dev(P["b"]), to_dev(P["omega"])
+    for mv in ("f64", "f32"):
+        xs = []
+        for _ in range(3):
+            x = torch.zeros_like(bd)
+            rc, info = rbcg.solve(ctx, [op], [P["mu"]], [bd], [omd], [x],
+                                  [rbcg.opts(40, rtol=1e-10, matvec=mv, refine_max=6)], check=False)
+            assert rc == 0, info
+            xs.append(x.cpu().numpy())
+        assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[1], xs[2])
+
+
+@pytest.mark.parametrize("sweep_tol", [1e-6, 1e-4, 1e-2])
+def test_sweep_target_changes_schedule_not_answer(R, sweep_tol):
+    """The per-sweep target of low-precision refinement trades sweeps against products per
+    sweep; every setting reaches the requested FP64 residual."""
+    import torch
+    rbcg, ctx = R
+    note(f"sweep_tol {sweep_tol}")
+    g = np.random.default_rng(6)
+    d = 2048
+    A = synth.spd_from_spectrum(np.arange(1, d + 1, dtype=float) ** (-1.5), g)
+    b = g.standard_normal(d)
+    Om = g.standard_normal((64, d))
+    op = rbcg.DenseOperator(ctx, to_dev(A), lo="f32")
+    bd = to_dev(b)
+    x = torch.zeros_like(bd)
+    o = rbcg.opts(40, rtol=1e-10, matvec="f32", refine_max=12, sweep_tol=sweep_tol)
+    rc, info = rbcg.solve(ctx, [op], [1e-4], [bd], [to_dev(Om)], [x], [o], check=False)
+    assert rc == 0, info
+    note(f"  sweeps {info[0]['refine_sweeps']} loads {info[0]['matrix_loads']} relres {info[0]['relres']:.1e}")
+    assert info[0]["relres"] <= 1e-10
+    xt = ot.solve_dense(A, 1e-4, b)
+    assert a_err(A, 1e-4, x.cpu().numpy(), xt) < 1e-8
+
+
 def test_invalid_arguments_rejected_before_device_work(R):
     import torch
     rbcg, ctx = R
@@ -165,6 +209,10 @@ def test_invalid_arguments_rejected_before_device_work(R):
     rc, _ = rbcg.solve(ctx, [op], [-1.0], [b], [None], [x], [rbcg.opts(2)], check=False)
     assert rc == -1
     rc, _ = rbcg.solve(ctx, [op], [0.0], [b], [None], [x], [rbcg.opts(0)], check=False)
+    assert rc == -1
+    rc, _ = rbcg.solve(ctx, [op], [0.0], [b], [None], [x], [rbcg.opts(2, sweep_tol=-1.0)], check=False)
+    assert rc == -1
+    rc, _ = rbcg.solve(ctx, [op], [0.0], [b], [None], [x], [rbcg.opts(2, sweep_tol=1.0)], check=False)
     assert rc == -1
     # mixed precision without the low-precision copy is unsupported
     rc, _ = rbcg.solve(ctx, [op], [0.0], [b], [None], [x], [rbcg.opts(2, matvec="f32")], check=False)
