@@ -403,7 +403,8 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
       }
       __syncthreads();
       // prevB in LDS (behind the other arrays) when the launch reserved room, else 16-column panels
-      double* pb = (double*)(((uintptr_t)(kept + m) + 15) & ~(uintptr_t)15);
+      const size_t pb_off = ((size_t)((unsigned char*)(kept + m) - smem_raw) + 15) & ~(size_t)15;
+      double* pb = (double*)(smem_raw + pb_off);
       const bool whole = (int64_t)((unsigned char*)(pb + m * m) - smem_raw) <= lds_bytes;
       for (int e = tid; e < m * m; e += 1024) {
         const int a = e / m, cc = e - a * m;
@@ -459,87 +460,168 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
     }
   }
 
-  double v[NS];
-#pragma unroll
-  for (int q = 0; q < NS; ++q) {
-    const int a = stripe + stripes * q;
-    v[q] = (owner && a < m) ? d.G[(int64_t)a * d.ldg + c] : 0.0;
-  }
-  for (int e = tid; e < m * m; e += 1024) Rl[e] = 0.0;
-  for (int i = tid; i < m; i += 1024) {
-    const double g = d.G[(int64_t)i * d.ldg + i];
-    dref[i] = g;
-    diag[i] = g;
-    pre[i] = d.pre ? d.pre[(int64_t)i * d.pre_stride] : -1.0;
-    chosen[i] = 0;
-    kept[i] = 0;
-    perm[i] = i;
-  }
-  if (tid == 0) s_rank = 0;
-  __syncthreads();
-
-  int s = 0;
-  for (; s < m; ++s) {
-    int p = s;
-    if (d.pivot && !(d.force_first && s == 0)) {
-      if (wave == 0) {
-        double best = -2.0;
-        int bi = 0x7fffffff;
-        for (int cc = lane; cc < m; cc += 64) {
-          if (chosen[cc]) continue;
-          const double rel = dref[cc] > 0.0 ? diag[cc] / dref[cc] : -1.0;
-          if (rel > best || (rel == best && cc < bi)) { best = rel; bi = cc; }
-        }
-        wave_argmax(best, bi);
-        if (lane == 0) wi[0] = bi;
-      }
-      __syncthreads();
-      p = wi[0];
+  // ---- unpivoted attempt (the common case) with the inverse factor carried along: thread
+  //      (stripe, c) holds the Schur entries (a, c) and the entries E[a][c] of E = L^{-1}
+  //      (G = L D L^T, L unit lower triangular), i.e. the elimination's row operations applied to
+  //      the identity.  Rhat^{-1} = E^T D^{-1/2}, so no triangular inversion follows.  One barrier
+  //      per step (publication double-buffered), the row slot of the pivot a compile-time
+  //      constant.  A pivot failing any test ends the attempt and the general path below redoes
+  //      the factorization (pivoting where asked; a pivoted factorization attempts with the
+  //      stricter relative threshold max(tau, 1e-8)).
+  bool fast_ok = false;
+  double ev[NS];
+  if constexpr (NS <= 9) {   // (wider slot counts would spill the extra registers)
+    const double tau_a = d.pivot ? fmax(d.tau, 1e-8) : d.tau;
+    const gmem_t<const double> G = gmem(d.G);
+    double va[NS];
+    for (int i = tid; i < m; i += 1024) {
+      dref[i] = G[(int64_t)i * d.ldg + i];
+      pre[i] = d.pre ? gmem(d.pre)[(int64_t)i * d.pre_stride] : -1.0;
     }
-    const double piv2 = diag[p];
-    bool defl;
-    if (d.force_first && s == 0) defl = !(piv2 > 0.0);
-    else defl = !(dref[p] > 0.0) || !(piv2 > d.tau * dref[p]) || (pre[p] >= 0.0 && !(piv2 > d.eta2 * pre[p])) ||
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      const int a = stripe + stripes * q;
+      va[q] = (owner && a < m) ? G[(int64_t)a * d.ldg + c] : 0.0;
+      ev[q] = (owner && a == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    bool ok = true;
+    static_for<NS>([&](auto qc) {
+      constexpr int qs = decltype(qc)::value;
+      for (int ps = 0; ps < stripes; ++ps) {
+        const int s = qs * stripes + ps;
+        if (s >= m || !ok) break;   // uniform
+        double* rb = pan + (s & 1) * 2 * m;   // Schur row s (= column s)
+        double* eb = rb + m;                  // row s of E (final: last updated at step s - 1)
+        if (owner && stripe == ps) {
+          rb[c] = va[qs];
+          eb[c] = ev[qs];
+        }
+        __syncthreads();
+        const double piv2 = rb[s], drp = dref[s], prp = pre[s];
+        const double rcv = owner ? rb[c] : 0.0, ecv = owner ? eb[c] : 0.0;
+        double ra[NS];
+#pragma unroll
+        for (int q = qs; q < NS; ++q) {
+          const int a = stripe + stripes * q;
+          ra[q] = a < m ? rb[a] : 0.0;
+        }
+        bool bad;
+        if (d.force_first && s == 0) bad = !(piv2 > 0.0);
+        else
+          bad = !(drp > 0.0) | !(piv2 > tau_a * drp) | ((prp >= 0.0) & !(piv2 > d.eta2 * prp)) |
                 !(piv2 > d.floor2);
-    if (defl && d.pivot) break;   // every remaining column is at least as deficient
-    if (defl) {
-      __syncthreads();
-      if (tid == 0) { perm[s] = p; chosen[p] = 1; }
-      __syncthreads();
-      continue;
-    }
-    const double rp = sqrt(piv2);
-    const double irp = 1.0 / rp;
-    // publish row p of R: the owner of (p, c) for every column c
-    if (owner && stripe == p % stripes) {
-      const int qp = p / stripes;
-      double x = 0.0;
+        if (bad) {
+          ok = false;
+          break;
+        }
+        const bool fast = pos_in_range(piv2);
+        const double f = fast ? recip_pos(piv2) : 1.0 / piv2;
 #pragma unroll
-      for (int q = 0; q < NS; ++q)
-        if (q == qp) x = v[q];
-      rowb[c] = (c == p) ? rp : (chosen[c] ? 0.0 : x * irp);
-    }
+        for (int q = qs; q < NS; ++q) {
+          double li = ra[q] * f;
+          if (q == qs && stripe <= ps) li = 0.0;   // rows up to the pivot are final
+          va[q] = fma(-li, rcv, va[q]);
+          ev[q] = fma(-li, ecv, ev[q]);
+        }
+        const double irp = fast ? rsqrt_pos(piv2) : 1.0 / sqrt(piv2);
+        if (tid < m) Rl[s * m + tid] = tid >= s ? rcv * irp : 0.0;   // row s of R
+        if (tid == 0) diag[s] = irp;                                 // 1 / Rhat[s][s]
+      }
+    });
+    fast_ok = ok;
+  }
+
+  double v[NS];
+  if (!fast_ok) {
     __syncthreads();
-    // Schur update of owned elements; retired and chosen rows/columns see a zero factor
-    if (owner) {
-      const double rc = rowb[c];
 #pragma unroll
-      for (int q = 0; q < NS; ++q) {
-        const int a = stripe + stripes * q;
-        if (a < m) {
-          v[q] -= rowb[a] * rc;
-          if (a == c) diag[a] = v[q];
+    for (int q = 0; q < NS; ++q) {
+      const int a = stripe + stripes * q;
+      v[q] = (owner && a < m) ? d.G[(int64_t)a * d.ldg + c] : 0.0;
+    }
+    for (int e = tid; e < m * m; e += 1024) Rl[e] = 0.0;
+    for (int i = tid; i < m; i += 1024) {
+      const double g = d.G[(int64_t)i * d.ldg + i];
+      dref[i] = g;
+      diag[i] = g;
+      pre[i] = d.pre ? d.pre[(int64_t)i * d.pre_stride] : -1.0;
+      chosen[i] = 0;
+      kept[i] = 0;
+      perm[i] = i;
+    }
+    if (tid == 0) s_rank = 0;
+    __syncthreads();
+
+    int s = 0;
+    for (; s < m; ++s) {
+      int p = s;
+      if (d.pivot && !(d.force_first && s == 0)) {
+        if (wave == 0) {
+          double best = -2.0;
+          int bi = 0x7fffffff;
+          for (int cc = lane; cc < m; cc += 64) {
+            if (chosen[cc]) continue;
+            const double rel = dref[cc] > 0.0 ? diag[cc] / dref[cc] : -1.0;
+            if (rel > best || (rel == best && cc < bi)) { best = rel; bi = cc; }
+          }
+          wave_argmax(best, bi);
+          if (lane == 0) wi[0] = bi;
+        }
+        __syncthreads();
+        p = wi[0];
+      }
+      const double piv2 = diag[p];
+      bool defl;
+      if (d.force_first && s == 0) defl = !(piv2 > 0.0);
+      else defl = !(dref[p] > 0.0) || !(piv2 > d.tau * dref[p]) || (pre[p] >= 0.0 && !(piv2 > d.eta2 * pre[p])) ||
+                  !(piv2 > d.floor2);
+      if (defl && d.pivot) break;   // every remaining column is at least as deficient
+      if (defl) {
+        __syncthreads();
+        if (tid == 0) { perm[s] = p; chosen[p] = 1; }
+        __syncthreads();
+        continue;
+      }
+      const double rp = sqrt(piv2);
+      const double irp = 1.0 / rp;
+      // publish row p of R: the owner of (p, c) for every column c
+      if (owner && stripe == p % stripes) {
+        const int qp = p / stripes;
+        double x = 0.0;
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+          if (q == qp) x = v[q];
+        rowb[c] = (c == p) ? rp : (chosen[c] ? 0.0 : x * irp);
+      }
+      __syncthreads();
+      // Schur update of owned elements; retired and chosen rows/columns see a zero factor
+      if (owner) {
+        const double rc = rowb[c];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          const int a = stripe + stripes * q;
+          if (a < m) {
+            v[q] -= rowb[a] * rc;
+            if (a == c) diag[a] = v[q];
+          }
         }
       }
+      for (int i = tid; i < m; i += 1024) Rl[s * m + i] = rowb[i];
+      if (tid == 0) { perm[s] = p; chosen[p] = 1; kept[s] = 1; s_rank = s_rank + 1; }
+      __syncthreads();
     }
-    for (int i = tid; i < m; i += 1024) Rl[s * m + i] = rowb[i];
-    if (tid == 0) { perm[s] = p; chosen[p] = 1; kept[s] = 1; s_rank = s_rank + 1; }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    int pos = s;
-    for (int i = 0; i < m && pos < m; ++i)
-      if (!chosen[i]) { perm[pos++] = i; chosen[i] = 1; }
+    if (tid == 0) {
+      int pos = s;
+      for (int i = 0; i < m && pos < m; ++i)
+        if (!chosen[i]) { perm[pos++] = i; chosen[i] = 1; }
+    }
+  } else {
+    for (int i = tid; i < m; i += 1024) {
+      kept[i] = 1;
+      perm[i] = i;
+    }
+    if (tid == 0) s_rank = m;
   }
   __syncthreads();
   // ---- reported coefficient block Bout = R (times prevB, staged 16 columns at a time)
@@ -566,8 +648,18 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
   } else {
     for (int e = tid; e < m * m; e += 1024) d.Bout[e] = kept[e / m] ? Rl[e] : 0.0;
   }
-  for (int e = tid; e < m; e += 1024) d.mask[e] = kept[e] ? 0 : 1;
+  for (int i = tid; i < m; i += 1024) d.mask[i] = kept[i] ? 0 : 1;
   if (tid == 0 && d.rank_out) *d.rank_out = s_rank;
+  if (fast_ok) {   // Mout[c][a] = E[a][c] / sqrt(D[a]) (zero for c > a)
+    if (owner) {
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        const int a = stripe + stripes * q;
+        if (a < m) gmem(d.Mout)[(int64_t)c * m + a] = ev[q] * diag[a];
+      }
+    }
+    return;
+  }
   // ---- X = Rhat^{-1} in registers (pivot positions), Rhat[i][u] = R[i][perm[u]]:
   //      X = I; for q descending: X[q][:] /= Rhat[q][q]; X[i][:] -= Rhat[i][q] X[q][:], i < q.
   __syncthreads();

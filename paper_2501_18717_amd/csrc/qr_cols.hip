@@ -49,10 +49,18 @@ __device__ __forceinline__ unsigned pivot_key(bool chosen, double diag, double i
 //   wi    8 (+8)     per-wave argmax keys (double-buffered); s and rank after the loop
 //   perm  M, kept M  pivot position -> column of W; kept flag per pivot position
 //   rinv  M          1 / Rhat[s][s] of kept positions
-inline size_t qr_m_lds(int M) {
-  const int MP = (M + 1) & ~1;
-  return ((size_t)M * MP + 2 * ((size_t)MP + 2) + (size_t)M) * 8 + (16 + 2 * (size_t)M) * 4 + 32;
-}
+//   erow  2*MP       (unpivoted attempt) published row of the inverse factor, double-buffered
+template <int M>
+struct QrLds {   // byte offsets (compile-time, so every access stays an LDS access)
+  static constexpr size_t MP = (M + 1) & ~1;
+  static constexpr size_t prow = (size_t)M * MP * 8;
+  static constexpr size_t wi = prow + 2 * (MP + 2) * 8;
+  static constexpr size_t perm = wi + 16 * 4;
+  static constexpr size_t kept = perm + (size_t)M * 4;
+  static constexpr size_t rinv = (kept + (size_t)M * 4 + 15) & ~(size_t)15;
+  static constexpr size_t erow = rinv + MP * 8;
+  static constexpr size_t bytes = erow + 2 * MP * 8;
+};
 
 // Outputs of a factorization whose R rows (by pivot position, columns in W's order) are in Rl:
 // Bout, mask, rank, and Mout = the columns of Rhat^{-1} placed by perm.  One lane per column.
@@ -68,7 +76,7 @@ __device__ __forceinline__ void qr_epilogue(const QrDesc& d, double* Rl, const i
     if (d.prevB) {
       double pb[MP];
 #pragma unroll
-      for (int u = 0; u < MP; ++u) pb[u] = u < M ? d.prevB[u * M + c] : 0.0;
+      for (int u = 0; u < MP; ++u) pb[u] = u < M ? gmem(d.prevB)[u * M + c] : 0.0;
       for (int s0 = 0; s0 < M; ++s0) {
         const double* Rs = Rl + s0 * MP;
         double a0 = 0.0, a1 = 0.0;
@@ -78,14 +86,14 @@ __device__ __forceinline__ void qr_epilogue(const QrDesc& d, double* Rl, const i
           a0 = fma(r2.x, pb[u], a0);
           a1 = fma(r2.y, pb[u + 1], a1);
         }
-        d.Bout[s0 * M + c] = kept[s0] ? a0 + a1 : 0.0;
+        gmem(d.Bout)[s0 * M + c] = kept[s0] ? a0 + a1 : 0.0;
       }
     } else {
-      for (int s0 = 0; s0 < M; ++s0) d.Bout[s0 * M + c] = kept[s0] ? Rl[s0 * MP + c] : 0.0;
+      for (int s0 = 0; s0 < M; ++s0) gmem(d.Bout)[s0 * M + c] = kept[s0] ? Rl[s0 * MP + c] : 0.0;
     }
-    d.mask[c] = kept[c] ? 0 : 1;
+    gmem(d.mask)[c] = kept[c] ? 0 : 1;
   }
-  if (tid == 0 && d.rank_out) *d.rank_out = rank;
+  if (tid == 0 && d.rank_out) *gmem(d.rank_out) = rank;
 
   // ---- transpose of Rhat into Rl: row u = column u of Rhat = column perm[u] of R
   double col[MP];
@@ -125,7 +133,7 @@ __device__ __forceinline__ void qr_epilogue(const QrDesc& d, double* Rl, const i
     // Mout[perm[a]][c] = X[a][c] for kept a <= c (Q column c = sum_a W column a * Mout[a][c])
     const bool kc = kept[c];
 #pragma unroll
-    for (int a = 0; a < M; ++a) d.Mout[perm[a] * M + c] = (kc && kept[a] && a <= c) ? x[a] : 0.0;
+    for (int a = 0; a < M; ++a) gmem(d.Mout)[perm[a] * M + c] = (kc && kept[a] && a <= c) ? x[a] : 0.0;
   }
 }
 
@@ -146,13 +154,14 @@ __device__ __forceinline__ void qr_pivoted(const QrDesc& d) {
   constexpr int NCH = (M + 63) / 64;               // 64-bit words of the chosen-column mask
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  using L = QrLds<M>;
   double* Rl = (double*)smem_raw;
-  double* prow = Rl + M * MP;
-  int* wi = (int*)(prow + 2 * PB);
-  int* perm = wi + 16;
-  int* kept = perm + M;
-  double* rinv = (double*)(((uintptr_t)(kept + M) + 15) & ~(uintptr_t)15);   // 1 / Rhat[s][s]
-  const double* __restrict__ G = d.G;
+  double* prow = (double*)(smem_raw + L::prow);
+  int* wi = (int*)(smem_raw + L::wi);
+  int* perm = (int*)(smem_raw + L::perm);
+  int* kept = (int*)(smem_raw + L::kept);
+  double* rinv = (double*)(smem_raw + L::rinv);   // 1 / Rhat[s][s]
+  const gmem_t<const double> G = gmem(d.G);
   const int64_t ldg = d.ldg;
 
   for (int e = tid; e < M * MP; e += NT) Rl[e] = 0.0;
@@ -179,7 +188,7 @@ __device__ __forceinline__ void qr_pivoted(const QrDesc& d) {
       const int a = rl + GR * i;
       dref[i] = (dl && a < M) ? v[i][i] : 0.0;
       idref[i] = dref[i] > 0.0 ? 1.0 / dref[i] : 0.0;
-      pre[i] = (dl && a < M && d.pre) ? d.pre[(int64_t)a * d.pre_stride] : -1.0;
+      pre[i] = (dl && a < M && d.pre) ? gmem(d.pre)[(int64_t)a * d.pre_stride] : -1.0;
     }
     uint64_t ch[NCH];
 #pragma unroll
@@ -314,10 +323,16 @@ __device__ __forceinline__ void qr_pivoted(const QrDesc& d) {
 }
 
 // Unpivoted attempt at the same factorization, for the common case of a well-conditioned block:
-// the pivot of step s is column s, so the loop over s is unrolled and the pivot column's register
-// slot is a compile-time constant (no argmax, no slot selection).  Any relative Schur pivot below
-// max(tau, 1e-8), or any deflation test that fires, aborts the attempt, and the same workgroup
-// redoes the factorization with pivoting.
+// the pivot of step s is column s, so the loop over s runs by register-slot column and the pivot
+// column's slot is a compile-time constant (no argmax, no slot selection).  The inverse factor is
+// carried in the same lane grid: the row operations that reduce G = L D L^T (L unit lower
+// triangular) to upper triangular form turn the identity into E = L^{-1}, and Rhat^{-1} =
+// E^T D^{-1/2}, so Mout leaves the registers without a separate triangular inversion.  Slots
+// that no later step reads (Schur entries left of or above the pivot block, E entries right of
+// it) are never touched, E slot columns start as identity columns when their block begins, and
+// finished E slot rows are written out at the end of their block.  Any relative Schur pivot
+// below max(tau, 1e-8), or any deflation test that fires, aborts the attempt, and the same
+// workgroup redoes the factorization with pivoting (whose outputs overwrite the attempt's).
 template <int M, int GR, int NWF>
 __global__ __launch_bounds__(64 * ((M + 63) / 64 > NWF ? (M + 63) / 64 : NWF))
 void k_qr_np(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) {
@@ -334,27 +349,25 @@ void k_qr_np(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) 
   if (NWF == NT / 64 && d.dg.D) diag_block(d.dg, threadIdx.x, NT);
   const int tid = threadIdx.x, wave = tid >> 6;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  using L = QrLds<M>;
   double* Rl = (double*)smem_raw;
-  double* prow = Rl + M * MP;
-  int* wi = (int*)(prow + 2 * PB);
-  int* perm = wi + 16;
-  int* kept = perm + M;
-  double* rinv = (double*)(((uintptr_t)(kept + M) + 15) & ~(uintptr_t)15);
-  const double* __restrict__ G = d.G;
+  double* prow = (double*)(smem_raw + L::prow);
+  int* wi = (int*)(smem_raw + L::wi);
+  double* erow = (double*)(smem_raw + L::erow);   // 2 x MP: published row of E (double-buffered)
+  const gmem_t<const double> G = gmem(d.G);
   const int64_t ldg = d.ldg;
   const double tau = fmax(d.tau, 1e-8);
-
-  for (int e = tid; e < M * MP; e += NT) Rl[e] = 0.0;
-  for (int i = tid; i < M; i += NT) {
-    perm[i] = i;
-    kept[i] = 1;
+  // with a previous factor the rows of R are kept for Bout = R prevB, else written out directly
+  const bool keepR = d.prevB != nullptr;
+  if (keepR) {
+    for (int e = tid; e < M * MP; e += NT) Rl[e] = 0.0;
+    __syncthreads();
   }
-  __syncthreads();
 
   if (wave < NWF) {
     const int rl = tid % GR, cl = tid / GR;
     const bool dl = rl == cl;
-    double v[S][S];
+    double v[S][S], e[S][S];
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
@@ -362,25 +375,29 @@ void k_qr_np(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) 
         const int a = rl + GR * i, c = cl + GR * j;
         v[i][j] = (a < M && c < M) ? G[(int64_t)a * ldg + c] : 0.0;
       }
-    double dref[S], pre[S];
+    double dref[S], pre[S], rv[S];
 #pragma unroll
     for (int i = 0; i < S; ++i) {
       const int a = rl + GR * i;
       dref[i] = (dl && a < M) ? v[i][i] : 0.0;
-      pre[i] = (dl && a < M && d.pre) ? d.pre[(int64_t)a * d.pre_stride] : -1.0;
+      pre[i] = (dl && a < M && d.pre) ? gmem(d.pre)[(int64_t)a * d.pre_stride] : -1.0;
+      rv[i] = 0.0;
     }
     bool ok = true;
-    // pivots s = GR js + r: the slot column js is a compile-time constant, r runs at run time
     static_for<S>([&](auto jc) {
       constexpr int js = decltype(jc)::value;
+      // E slot column js enters as identity columns
+#pragma unroll
+      for (int i = js; i < S; ++i) e[i][js] = (rl + GR * i == cl + GR * js) ? 1.0 : 0.0;
 #pragma nounroll
       for (int r = 0; r < GR; ++r) {
         const int s = GR * js + r;
         if (s >= M || !ok) break;   // uniform
         double* pr = prow + (s & 1) * PB;
-        if (cl == r) {
+        double* pq = erow + (s & 1) * MP;
+        if (cl == r) {   // Schur column s (rows of later pivots; earlier rows are never read)
 #pragma unroll
-          for (int i = 0; i < S; ++i) {
+          for (int i = js; i < S; ++i) {
             const int a = rl + GR * i;
             if (a < M) pr[a] = v[i][js];
           }
@@ -389,41 +406,77 @@ void k_qr_np(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) 
             pr[MP + 1] = pre[js];
           }
         }
+        if (rl == r) {   // row s of E (final: its last update was step s - 1)
+#pragma unroll
+          for (int j = 0; j <= js; ++j) {
+            const int c = cl + GR * j;
+            if (c < M) pq[c] = e[js][j];
+          }
+        }
         if constexpr (NWF > 1) __syncthreads();
         else __builtin_amdgcn_wave_barrier();
+        // every value this step needs, read at once
         const double piv2 = pr[s];
         const double drp = pr[MP], prp = pr[MP + 1];
+        double ra[S], rc[S], re[S];
+#pragma unroll
+        for (int i = js; i < S; ++i) {
+          const int a = rl + GR * i, c = cl + GR * i;
+          ra[i] = a < M ? pr[a] : 0.0;
+          rc[i] = c < M ? pr[c] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j <= js; ++j) {
+          const int c = cl + GR * j;
+          re[j] = c < M ? pq[c] : 0.0;
+        }
         bool bad;
         if (d.force_first && s == 0) bad = !(piv2 > 0.0);
-        else
-          bad = !(drp > 0.0) || !(piv2 > tau * drp) || (prp >= 0.0 && !(piv2 > d.eta2 * prp)) ||
+        else   // all terms evaluated (no short circuit: no extra round trips)
+          bad = !(drp > 0.0) | !(piv2 > tau * drp) | ((prp >= 0.0) & !(piv2 > d.eta2 * prp)) |
                 !(piv2 > d.floor2);
         if (bad) {
           ok = false;
           break;
         }
-        double ra[S], rc[S];
+        const bool fast = pos_in_range(piv2);
+        const double f = fast ? recip_pos(piv2) : 1.0 / piv2;
 #pragma unroll
-        for (int i = 0; i < S; ++i) {
-          const int a = rl + GR * i, c = cl + GR * i;
-          ra[i] = a < M ? pr[a] : 0.0;
-          rc[i] = c < M ? pr[c] : 0.0;
+        for (int i = js; i < S; ++i) {
+          const double li = ra[i] * f;
+#pragma unroll
+          for (int j = js; j < S; ++j) v[i][j] = fma(-li, rc[j], v[i][j]);
         }
-        const double irp = 1.0 / sqrt(piv2);
-        const double f = irp * irp;
-        if (tid == 0) rinv[s] = irp;
-        if (rl == 0) {
+#pragma unroll
+        for (int i = js; i < S; ++i) {
+          double li = ra[i] * f;
+          if (i == js && rl <= r) li = 0.0;   // rows up to the pivot are final
+#pragma unroll
+          for (int j = 0; j <= js; ++j) e[i][j] = fma(-li, re[j], e[i][j]);
+        }
+        const double irp = fast ? rsqrt_pos(piv2) : 1.0 / sqrt(piv2);
+        if (rl == r) rv[js] = irp;
+        if (rl == 0) {   // row s of R: zero left of the pivot
 #pragma unroll
           for (int j = 0; j < S; ++j) {
             const int c = cl + GR * j;
-            if (c < M) Rl[s * MP + c] = c < s ? 0.0 : rc[j] * irp;
+            if (c < M) {
+              const double x = (j >= js && c >= s) ? rc[j] * irp : 0.0;
+              if (keepR) Rl[s * MP + c] = x;
+              else gmem(d.Bout)[(int64_t)s * M + c] = x;
+            }
           }
         }
+      }
+      // E slot row js is final: Mout[b][a] = E[a][b] / sqrt(D[a]) (zero for b > a)
+      if (ok) {
+        const int a = rl + GR * js;
+        if (a < M) {
 #pragma unroll
-        for (int i = 0; i < S; ++i) {
-          const double ri = ra[i] * f;
-#pragma unroll
-          for (int j = 0; j < S; ++j) v[i][j] = fma(-ri, rc[j], v[i][j]);
+          for (int j = 0; j < S; ++j) {
+            const int b = cl + GR * j;
+            if (b < M) gmem(d.Mout)[(int64_t)b * M + a] = j <= js ? e[js][j] * rv[js] : 0.0;
+          }
         }
       }
     });
@@ -437,12 +490,32 @@ void k_qr_np(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) 
     qr_pivoted<M, GR, NWF>(d);
     return;
   }
-  qr_epilogue<M>(d, Rl, perm, kept, rinv, M, tid);
+  for (int c = tid; c < M; c += NT) gmem(d.mask)[c] = 0;
+  if (tid == 0 && d.rank_out) *gmem(d.rank_out) = M;
+  if (keepR) {   // Bout = R prevB, one lane per column
+    const int c = tid;
+    if (c < M) {
+      double pb[MP];
+#pragma unroll
+      for (int u = 0; u < MP; ++u) pb[u] = u < M ? gmem(d.prevB)[u * M + c] : 0.0;
+      for (int s0 = 0; s0 < M; ++s0) {
+        const double* Rs = Rl + s0 * MP;
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int u = 0; u < MP; u += 2) {
+          const double2 r2 = *(const double2*)(Rs + u);
+          a0 = fma(r2.x, pb[u], a0);
+          a1 = fma(r2.y, pb[u + 1], a1);
+        }
+        gmem(d.Bout)[s0 * M + c] = a0 + a1;
+      }
+    }
+  }
 }
 
 template <int M, int GR, int NWF>
 static hipError_t launch_qr_m_t(const QrDesc* dd, int nz, const int32_t* act, hipStream_t st) {
-  const size_t lds = qr_m_lds(M);
+  constexpr size_t lds = QrLds<M>::bytes;
   if (lds > kLdsCap) return hipErrorInvalidValue;
   const void* kern = (const void*)k_qr_np<M, GR, NWF>;
   static const hipError_t attr = [&] {   // once per process, thread-safe
@@ -466,7 +539,7 @@ hipError_t launch_qr_m(const QrDesc* dd, int nz, int m, const int32_t* act, hipS
     case 9: return launch_qr_m_t<9, 8, 1>(dd, nz, act, st);
     case 17: return launch_qr_m_t<17, 8, 1>(dd, nz, act, st);
     case 33: return launch_qr_m_t<33, 8, 1>(dd, nz, act, st);
-    case 65: return launch_qr_m_t<65, 8, 1>(dd, nz, act, st);
+    case 65: return launch_qr_m_t<65, 16, 4>(dd, nz, act, st);
     case 129: return launch_qr_m_t<129, 16, 4>(dd, nz, act, st);
     default: return hipErrorInvalidValue;
   }

@@ -113,15 +113,6 @@ __device__ __forceinline__ void panel_gemm_nt(int tid, const double* Pg, bool p_
   }
 }
 
-// 1 / x for x > 0 to full double precision: hardware reciprocal estimate and two Newton steps.
-__device__ __forceinline__ double recip_pos(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
-
 template <int M, int GR, int NWF>
 __global__ __launch_bounds__(256) void k_tri_exact(const TriDesc* __restrict__ descs, int j0, int j1,
                                                    const int32_t* __restrict__ act) {
