@@ -50,7 +50,7 @@ static hipError_t set_big_lds(const void* k) {
 //   FIN_TRANS / FIN_RESID: part[s][c][i] -> row c of O, element i
 // ---------------------------------------------------------------------------------------------
 // sum_s p[s * stride] in split order; the loads of four splits are issued together.
-__device__ __forceinline__ double split_sum(const double* __restrict__ p, int64_t stride, int splits) {
+__device__ __forceinline__ double split_sum(gmem_t<const double> p, int64_t stride, int splits) {
   double v = 0.0;
   int s = 0;
   for (; s + 4 <= splits; s += 4) {
@@ -73,8 +73,8 @@ __global__ __launch_bounds__(256) void k_finish(const FinDesc* __restrict__ desc
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
       const int c = (int)(e / f.M), i = (int)(e % f.M);
-      const double v = split_sum(f.part + e, total, f.splits);
-      f.out[(int64_t)i * f.ldo + c] = f.alpha * v;
+      const double v = split_sum(gmem(f.part) + e, total, f.splits);
+      gmem(f.out)[(int64_t)i * f.ldo + c] = f.alpha * v;
     }
     return;
   }
@@ -82,19 +82,19 @@ __global__ __launch_bounds__(256) void k_finish(const FinDesc* __restrict__ desc
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
     const int o = (int)(e / cols), in = (int)(e % cols);
-    double v = split_sum(f.part + e, total, f.splits) * f.alpha;
+    double v = split_sum(gmem(f.part) + e, total, f.splits) * f.alpha;
     if (rowmajor) {
-      f.out[(int64_t)o * f.ldo + in] = v;
+      gmem(f.out)[(int64_t)o * f.ldo + in] = v;
     } else if (f.mode == FIN_TRANS) {
-      ((double*)f.O.p)[row_off(f.O, o) + in] = v;
+      gmem((double*)f.O.p)[row_off(f.O, o) + in] = v;
     } else if (f.mode == FIN_AXPBY) {
       double y = v;
-      if (f.beta != 0.0) y += f.beta * ((const double*)f.rhs.p)[row_off(f.rhs, o) + in];
-      ((double*)f.O.p)[row_off(f.O, o) + in] = y;
+      if (f.beta != 0.0) y += f.beta * gmem((const double*)f.rhs.p)[row_off(f.rhs, o) + in];
+      gmem((double*)f.O.p)[row_off(f.O, o) + in] = y;
     } else {
-      const double rv = ((const double*)f.rhs.p)[row_off(f.rhs, o) + in];
-      const double xv = ((const double*)f.xin.p)[row_off(f.xin, o) + in];
-      ((double*)f.O.p)[row_off(f.O, o) + in] = rv - v - f.mu[o] * xv;
+      const double rv = gmem((const double*)f.rhs.p)[row_off(f.rhs, o) + in];
+      const double xv = gmem((const double*)f.xin.p)[row_off(f.xin, o) + in];
+      gmem((double*)f.O.p)[row_off(f.O, o) + in] = rv - v - gmem(f.mu)[o] * xv;
     }
   }
 }
@@ -131,11 +131,11 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const NnDesc* __restrict__ desc
     for (int e = 0; e < 4; ++e) {
       const int a = ac + 4 * e + q;
       const bool aval = a < d.Ka;
-      const double pv = (aval && ival) ? (double)((const PT*)d.P.p)[row_off(d.P, a) + i] : 0.0;
+      const double pv = (aval && ival) ? (double)gmem((const PT*)d.P.p)[row_off(d.P, a) + i] : 0.0;
 #pragma unroll
       for (int tb = 0; tb < TB; ++tb) {
         const int b = 16 * tb + r16;
-        const double cv = (aval && b < d.Mo) ? d.C[(int64_t)a * d.ldc + b] : 0.0;
+        const double cv = (aval && b < d.Mo) ? gmem(d.C)[(int64_t)a * d.ldc + b] : 0.0;
         acc[tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(cv, pv, acc[tb], 0, 0, 0);
       }
     }
@@ -160,8 +160,8 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const NnDesc* __restrict__ desc
 #pragma unroll
       for (int w = 0; w < 3; ++w) v += red[((w * TB + tb) * 4 + r) * 64 + lane];
       double out = d.alpha * v;
-      if (d.beta != 0.0) out += d.beta * ((const double*)d.Y.p)[row_off(d.Y, b) + i];
-      ((double*)d.O.p)[row_off(d.O, b) + i] = out;
+      if (d.beta != 0.0) out += d.beta * gmem((const double*)d.Y.p)[row_off(d.Y, b) + i];
+      gmem((double*)d.O.p)[row_off(d.O, b) + i] = out;
     }
   }
 }
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(256) void k_nn_tall(const NnDesc* __restrict__ desc
   const int ab = s * per, ae = min(d.Ka, ab + per);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* cs = (double*)smem_raw;        // [2][16][CS]
-  const PT* __restrict__ P = (const PT*)d.P.p;
+  const gmem_t<const PT> P = gmem((const PT*)d.P.p);
   auto load_p = [&](int a0, double* pv) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(256) void k_nn_tall(const NnDesc* __restrict__ desc
     for (int e = tid; e < 16 * BW; e += 256) {
       const int r = e / BW, b = e - r * BW;
       const int a = a0 + r;
-      dst[r * CS + b] = (a < ae && b < d.Mo) ? d.C[(int64_t)a * d.ldc + b] : 0.0;
+      dst[r * CS + b] = (a < ae && b < d.Mo) ? gmem(d.C)[(int64_t)a * d.ldc + b] : 0.0;
     }
   };
   v4d acc[TB];
@@ -282,11 +282,11 @@ __global__ __launch_bounds__(256) void k_nn_tall(const NnDesc* __restrict__ desc
       if (b >= d.Mo) continue;
       const double v = acc[tb][r];
       if (splits > 1) {
-        d.part[((int64_t)s * d.Mo + b) * d.N + i] = v;
+        gmem(d.part)[((int64_t)s * d.Mo + b) * d.N + i] = v;
       } else {
         double out = d.alpha * v;
-        if (d.beta != 0.0) out += d.beta * ((const double*)d.Y.p)[row_off(d.Y, b) + i];
-        ((double*)d.O.p)[row_off(d.O, b) + i] = out;
+        if (d.beta != 0.0) out += d.beta * gmem((const double*)d.Y.p)[row_off(d.Y, b) + i];
+        gmem((double*)d.O.p)[row_off(d.O, b) + i] = out;
       }
     }
   }
@@ -376,13 +376,13 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
   if (!d.pivot && d.prevB) {
     __shared__ int s_small;
     __shared__ double s_wmax[16];
-    for (int i = tid; i < m; i += 1024) dref[i] = d.G[(int64_t)i * d.ldg + i];
+    for (int i = tid; i < m; i += 1024) dref[i] = gmem(d.G)[(int64_t)i * d.ldg + i];
     __syncthreads();
     double emax = 0.0;
     for (int e = tid; e < m * m; e += 1024) {
       const int a = e / m, cc = e - a * m;
       if (dref[a] == 0.0 || dref[cc] == 0.0) continue;   // deflated (zero) columns
-      const double g = d.G[(int64_t)a * d.ldg + cc];
+      const double g = gmem(d.G)[(int64_t)a * d.ldg + cc];
       emax = fmax(emax, fabs(g - (a == cc ? 1.0 : 0.0)));
     }
 #pragma unroll
@@ -399,7 +399,7 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
       // kept[i] = column i non-zero; F in Rl (upper), Bout = (I + F) prevB, Mout = I - F
       for (int i = tid; i < m; i += 1024) {
         kept[i] = dref[i] != 0.0;
-        d.mask[i] = kept[i] ? 0 : 1;
+        gmem(d.mask)[i] = kept[i] ? 0 : 1;
       }
       __syncthreads();
       // prevB in LDS (behind the other arrays) when the launch reserved room, else 16-column panels
@@ -410,17 +410,17 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
         const int a = e / m, cc = e - a * m;
         double f = 0.0;
         if (kept[a] && kept[cc] && cc >= a) {
-          const double g = d.G[(int64_t)a * d.ldg + cc];
+          const double g = gmem(d.G)[(int64_t)a * d.ldg + cc];
           f = (a == cc) ? 0.5 * (g - 1.0) : g;
         }
         Rl[e] = f;
-        d.Mout[e] = (kept[a] && kept[cc]) ? ((a == cc ? 1.0 : 0.0) - f) : 0.0;
-        if (whole) pb[e] = d.prevB[e];
+        gmem(d.Mout)[e] = (kept[a] && kept[cc]) ? ((a == cc ? 1.0 : 0.0) - f) : 0.0;
+        if (whole) pb[e] = gmem(d.prevB)[e];
       }
       if (tid == 0 && d.rank_out) {
         int rk = 0;
         for (int i = 0; i < m; ++i) rk += kept[i];
-        *d.rank_out = rk;
+        *gmem(d.rank_out) = rk;
       }
       __syncthreads();
       if (whole) {
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
             const double* Fs = Rl + s0 * m;
             for (int u = s0; u < m; ++u) acc += Fs[u] * pb[u * m + cc];
           }
-          d.Bout[s0 * m + cc] = acc;
+          gmem(d.Bout)[s0 * m + cc] = acc;
         }
         return;
       }
@@ -440,7 +440,7 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
         const int nc = min(16, m - c0);
         for (int e = tid; e < m * 16; e += 1024) {
           const int u = e >> 4, cc = e & 15;
-          pan[e] = cc < nc ? d.prevB[u * m + c0 + cc] : 0.0;
+          pan[e] = cc < nc ? gmem(d.prevB)[u * m + c0 + cc] : 0.0;
         }
         __syncthreads();
         for (int e = tid; e < m * 16; e += 1024) {
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
             const double* Fs = Rl + s0 * m;
             for (int u = s0; u < m; ++u) acc += Fs[u] * pan[u * 16 + cc];
           }
-          d.Bout[s0 * m + c0 + cc] = acc;
+          gmem(d.Bout)[s0 * m + c0 + cc] = acc;
         }
         __syncthreads();
       }
@@ -538,14 +538,14 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
       const int a = stripe + stripes * q;
-      v[q] = (owner && a < m) ? d.G[(int64_t)a * d.ldg + c] : 0.0;
+      v[q] = (owner && a < m) ? gmem(d.G)[(int64_t)a * d.ldg + c] : 0.0;
     }
     for (int e = tid; e < m * m; e += 1024) Rl[e] = 0.0;
     for (int i = tid; i < m; i += 1024) {
-      const double g = d.G[(int64_t)i * d.ldg + i];
+      const double g = gmem(d.G)[(int64_t)i * d.ldg + i];
       dref[i] = g;
       diag[i] = g;
-      pre[i] = d.pre ? d.pre[(int64_t)i * d.pre_stride] : -1.0;
+      pre[i] = d.pre ? gmem(d.pre)[(int64_t)i * d.pre_stride] : -1.0;
       chosen[i] = 0;
       kept[i] = 0;
       perm[i] = i;
@@ -630,7 +630,7 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
       const int nc = min(16, m - c0);
       for (int e = tid; e < m * 16; e += 1024) {
         const int u = e >> 4, cc = e & 15;
-        pan[e] = cc < nc ? d.prevB[u * m + c0 + cc] : 0.0;
+        pan[e] = cc < nc ? gmem(d.prevB)[u * m + c0 + cc] : 0.0;
       }
       __syncthreads();
       for (int e = tid; e < m * 16; e += 1024) {
@@ -641,15 +641,15 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
           const double* Rs = Rl + s0 * m;
           for (int u = 0; u < m; ++u) acc += Rs[u] * pan[u * 16 + cc];
         }
-        d.Bout[s0 * m + c0 + cc] = acc;
+        gmem(d.Bout)[s0 * m + c0 + cc] = acc;
       }
       __syncthreads();
     }
   } else {
-    for (int e = tid; e < m * m; e += 1024) d.Bout[e] = kept[e / m] ? Rl[e] : 0.0;
+    for (int e = tid; e < m * m; e += 1024) gmem(d.Bout)[e] = kept[e / m] ? Rl[e] : 0.0;
   }
-  for (int i = tid; i < m; i += 1024) d.mask[i] = kept[i] ? 0 : 1;
-  if (tid == 0 && d.rank_out) *d.rank_out = s_rank;
+  for (int i = tid; i < m; i += 1024) gmem(d.mask)[i] = kept[i] ? 0 : 1;
+  if (tid == 0 && d.rank_out) *gmem(d.rank_out) = s_rank;
   if (fast_ok) {   // Mout[c][a] = E[a][c] / sqrt(D[a]) (zero for c > a)
     if (owner) {
 #pragma unroll
@@ -700,7 +700,7 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
       const int a = stripe + stripes * q;
       if (a >= m) continue;
       const double x = (kept[a] && kept[c] && a <= c) ? v[q] : 0.0;
-      d.Mout[perm[a] * m + c] = x;
+      gmem(d.Mout)[perm[a] * m + c] = x;
     }
   }
 }
@@ -1064,23 +1064,23 @@ __global__ __launch_bounds__(256) void k_convert(const CvtDesc* __restrict__ des
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
     const int rr = (int)(e / d.cols), c = (int)(e % d.cols);
-    double v = d.src_t == DT_F64 ? ((const double*)d.src.p)[row_off(d.src, rr) + c]
-                                 : (double)((const float*)d.src.p)[row_off(d.src, rr) + c];
+    double v = d.src_t == DT_F64 ? gmem((const double*)d.src.p)[row_off(d.src, rr) + c]
+                                 : (double)gmem((const float*)d.src.p)[row_off(d.src, rr) + c];
     if (d.dst_t == DT_F32) {
-      ((float*)d.dst.p)[row_off(d.dst, rr) + c] = (float)v;
+      gmem((float*)d.dst.p)[row_off(d.dst, rr) + c] = (float)v;
     } else if (d.dst_t == DT_F64) {
-      ((double*)d.dst.p)[row_off(d.dst, rr) + c] = v;
+      gmem((double*)d.dst.p)[row_off(d.dst, rr) + c] = v;
     } else if (!d.split_lo) {
-      ((unsigned short*)d.dst.p)[row_off(d.dst, rr) + c] = f32_to_bf16((float)v);
+      gmem((unsigned short*)d.dst.p)[row_off(d.dst, rr) + c] = f32_to_bf16((float)v);
     } else {
       // three BF16 parts of the FP64 value (about 24 significant bits)
       const unsigned short hi = f32_to_bf16((float)v);
       const double r1 = v - (double)bf16_to_f32(hi);
       const unsigned short mid = f32_to_bf16((float)r1);
       const unsigned short lo = f32_to_bf16((float)(r1 - (double)bf16_to_f32(mid)));
-      ((unsigned short*)d.dst.p)[row_off(d.dst, 3 * rr) + c] = hi;
-      ((unsigned short*)d.dst.p)[row_off(d.dst, 3 * rr + 1) + c] = mid;
-      ((unsigned short*)d.dst.p)[row_off(d.dst, 3 * rr + 2) + c] = lo;
+      gmem((unsigned short*)d.dst.p)[row_off(d.dst, 3 * rr) + c] = hi;
+      gmem((unsigned short*)d.dst.p)[row_off(d.dst, 3 * rr + 1) + c] = mid;
+      gmem((unsigned short*)d.dst.p)[row_off(d.dst, 3 * rr + 2) + c] = lo;
     }
   }
 }
@@ -1150,8 +1150,8 @@ __global__ __launch_bounds__(256) void k_copy(const CopyDesc* __restrict__ descs
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
     const int rr = (int)(e / d.n), c = (int)(e % d.n);
-    const double v = rr < d.rows ? d.alpha * ((const double*)d.src.p)[row_off(d.src, rr) + c] : 0.0;
-    ((double*)d.dst.p)[row_off(d.dst, rr) + c] = v;
+    const double v = rr < d.rows ? d.alpha * gmem((const double*)d.src.p)[row_off(d.src, rr) + c] : 0.0;
+    gmem((double*)d.dst.p)[row_off(d.dst, rr) + c] = v;
   }
 }
 
@@ -1171,7 +1171,7 @@ __global__ __launch_bounds__(256) void k_fill(const FillDesc* __restrict__ descs
   int j = 0;
   for (int s = 0; s < d.m && j < d.src_avail; ++s) {
     if (!d.mask[s]) continue;
-    ((double*)d.dst.p)[row_off(d.dst, s) + i] = ((const double*)d.src.p)[row_off(d.src, d.src_first + j) + i];
+    gmem((double*)d.dst.p)[row_off(d.dst, s) + i] = gmem((const double*)d.src.p)[row_off(d.src, d.src_first + j) + i];
     ++j;
   }
 }

@@ -38,31 +38,29 @@ __global__ __launch_bounds__(64 * W) void k_mv_wide(const NtDesc* __restrict__ d
   const int N = d.N;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float* xs = (float*)smem_raw;              // [2][NC][XS]
-  __shared__ const float* xrow_ptr[NC];
-  for (int r = tid; r < NC; r += NT) xrow_ptr[r] = r < N ? (const float*)d.X.p + row_off(d.X, r) : nullptr;
+  __shared__ gmem_t<const float> xrow_ptr[NC];
+  for (int r = tid; r < NC; r += NT) xrow_ptr[r] = r < N ? gmem((const float*)d.X.p) + row_off(d.X, r) : nullptr;
   __syncthreads();
 
   const int row = i0 + wave * 32 + rr;
   const bool rval = row < d.M;
-  const float* pp = (const float*)d.P.p + (rval ? row_off(d.P, row) : 0);
+  const gmem_t<const float> pp = gmem((const float*)d.P.p) + (rval ? row_off(d.P, row) : 0);
 
-  float4 xreg[XP];
+  v4f xreg[XP];
   auto load_x = [&](int kc) {
     const bool full = kc + BK <= ke;
 #pragma unroll
     for (int p = 0; p < XP; ++p) {
       const int e = tid + NT * p;
       const int r = e / VPR, k = kc + 4 * (e % VPR);
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      const float* src = r < NC ? xrow_ptr[r] : nullptr;
+      v4f v = (v4f)(0.f);
+      const gmem_t<const float> src = r < NC ? xrow_ptr[r] : nullptr;
       if (src) {
         if (full) {
-          v = *(const float4*)(src + k);
+          v = *(gmem_t<const v4f>)(src + k);
         } else {
-          v.x = k < ke ? src[k] : 0.f;
-          v.y = k + 1 < ke ? src[k + 1] : 0.f;
-          v.z = k + 2 < ke ? src[k + 2] : 0.f;
-          v.w = k + 3 < ke ? src[k + 3] : 0.f;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) v[t] = k + t < ke ? src[k + t] : 0.f;
         }
       }
       xreg[p] = v;
@@ -74,21 +72,19 @@ __global__ __launch_bounds__(64 * W) void k_mv_wide(const NtDesc* __restrict__ d
     for (int p = 0; p < XP; ++p) {
       const int e = tid + NT * p;
       const int r = e / VPR;
-      if (r < NC) *(float4*)(dst + r * XS + 4 * (e % VPR)) = xreg[p];
+      if (r < NC) *(v4f*)(dst + r * XS + 4 * (e % VPR)) = xreg[p];
     }
   };
   float ar[32];
   auto load_a = [&](int kc) {
     const int k = kc + 32 * h;
     if (rval && k + 32 <= ke) {
-      const float4* src = (const float4*)(pp + k);
+      const gmem_t<const v4f> src = (gmem_t<const v4f>)(pp + k);
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
-        const float4 u = src[t];
-        ar[4 * t] = u.x;
-        ar[4 * t + 1] = u.y;
-        ar[4 * t + 2] = u.z;
-        ar[4 * t + 3] = u.w;
+        const v4f u = src[t];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ar[4 * t + e] = u[e];
       }
     } else {
 #pragma unroll
@@ -154,7 +150,7 @@ __global__ __launch_bounds__(64 * W) void k_mv_wide(const NtDesc* __restrict__ d
       const int c = 32 * t + 8 * (r >> 2) + 4 * h + (r & 3);
       if (!iv || c >= N) continue;
       const double v = (double)a[r];
-      if (splits > 1) d.part[((int64_t)s * N + c) * d.M + i] = v;
+      if (splits > 1) gmem(d.part)[((int64_t)s * N + c) * d.M + i] = v;
       else store_out(d, d.out_t, i, c, v);
     }
   });
@@ -162,7 +158,7 @@ __global__ __launch_bounds__(64 * W) void k_mv_wide(const NtDesc* __restrict__ d
     const float tot = ex + __shfl_xor(ex, 32);
     const int c = 32 * T2;
     if (h == 0 && iv && c < N) {
-      if (splits > 1) d.part[((int64_t)s * N + c) * d.M + i] = (double)tot;
+      if (splits > 1) gmem(d.part)[((int64_t)s * N + c) * d.M + i] = (double)tot;
       else store_out(d, d.out_t, i, c, (double)tot);
     }
   }
