@@ -112,8 +112,8 @@ hipError_t launch_finish(const FinDesc* dd, int nz, int maxM, int maxN, const in
 //   One workgroup = 16 columns i, all Mo rows b (TB tiles), the 4 waves split the a range.
 //   MFMA A operand = C^T (b x a), B operand = P (a x i); D rows = b, columns = i.
 // ---------------------------------------------------------------------------------------------
-template <typename PT, int TB>
-__global__ __launch_bounds__(256) void k_gemm_nn(const NnDesc* __restrict__ descs, const int32_t* __restrict__ act) {
+template <typename PT, int TB, int NW>
+__global__ __launch_bounds__(64 * NW) void k_gemm_nn(const NnDesc* __restrict__ descs, const int32_t* __restrict__ act) {
   const NnDesc d = descs[blockIdx.z];
   if (!is_active(act, d.active)) return;
   const int i0 = blockIdx.x * 16;
@@ -125,23 +125,49 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const NnDesc* __restrict__ desc
   v4d acc[TB];
 #pragma unroll
   for (int tb = 0; tb < TB; ++tb) acc[tb] = v4d{0, 0, 0, 0};
-  // wave w takes a-chunks of 16 starting at 16 w, stepping 64
-  for (int ac = 16 * wave; ac < d.Ka; ac += 64) {
+  // wave w takes a-chunks of 16 starting at 16 w, stepping 16 NW; with up to nine row tiles the
+  // operands of the next two chunks are in flight while this chunk's MFMAs run (three register
+  // stages; wider tiles would spill them)
+  const gmem_t<const PT> P = gmem((const PT*)d.P.p);
+  const gmem_t<const double> C = gmem(d.C);
+  constexpr int STEP = 16 * NW;
+  constexpr int NSTG = TB <= 9 ? 3 : 1;
+  double pv[NSTG][4], cv[NSTG][4][TB];
+  auto load = [&](int ac, double* pb, double (*cb)[TB]) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int a = ac + 4 * e + q;
       const bool aval = a < d.Ka;
-      const double pv = (aval && ival) ? (double)gmem((const PT*)d.P.p)[row_off(d.P, a) + i] : 0.0;
+      pb[e] = (aval && ival) ? (double)P[row_off(d.P, a) + i] : 0.0;
 #pragma unroll
       for (int tb = 0; tb < TB; ++tb) {
         const int b = 16 * tb + r16;
-        const double cv = (aval && b < d.Mo) ? gmem(d.C)[(int64_t)a * d.ldc + b] : 0.0;
-        acc[tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(cv, pv, acc[tb], 0, 0, 0);
+        cb[e][tb] = (aval && b < d.Mo) ? C[(int64_t)a * d.ldc + b] : 0.0;
       }
     }
+  };
+  int ac = 16 * wave;
+#pragma unroll
+  for (int st = 0; st + 1 < NSTG; ++st)
+    if (ac + st * STEP < d.Ka) load(ac + st * STEP, pv[st], cv[st]);
+  bool go = ac < d.Ka;
+  while (go) {
+    static_for<NSTG>([&](auto stc) {
+      constexpr int st = decltype(stc)::value;
+      if (!go) return;
+      constexpr int ld = (st + NSTG - 1) % NSTG;
+      if (ac + (NSTG - 1) * STEP < d.Ka) load(ac + (NSTG - 1) * STEP, pv[ld], cv[ld]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int tb = 0; tb < TB; ++tb)
+          acc[tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(cv[st][e][tb], pv[st][e], acc[tb], 0, 0, 0);
+      ac += STEP;
+      go = ac < d.Ka;
+    });
   }
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* red = (double*)smem_raw;   // [3][TB][4][64]
+  double* red = (double*)smem_raw;   // [NW - 1][TB][4][64]
   if (wave > 0) {
 #pragma unroll
     for (int tb = 0; tb < TB; ++tb)
@@ -158,7 +184,7 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const NnDesc* __restrict__ desc
       if (b >= d.Mo) continue;
       double v = acc[tb][r];
 #pragma unroll
-      for (int w = 0; w < 3; ++w) v += red[((w * TB + tb) * 4 + r) * 64 + lane];
+      for (int w = 0; w < NW - 1; ++w) v += red[((w * TB + tb) * 4 + r) * 64 + lane];
       double out = d.alpha * v;
       if (d.beta != 0.0) out += d.beta * gmem((const double*)d.Y.p)[row_off(d.Y, b) + i];
       gmem((double*)d.O.p)[row_off(d.O, b) + i] = out;
@@ -166,17 +192,22 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const NnDesc* __restrict__ desc
   }
 }
 
-template <typename PT, int TB>
-static hipError_t launch_nn_t(const NnDesc* dd, int nz, int maxN, const int32_t* act, hipStream_t st) {
-  const size_t lds = (size_t)3 * TB * 4 * 64 * 8;
-  auto kern = k_gemm_nn<PT, TB>;
+template <typename PT, int TB, int NW>
+static hipError_t launch_nn_w(const NnDesc* dd, int nz, int maxN, const int32_t* act, hipStream_t st) {
+  const size_t lds = (size_t)(NW - 1) * TB * 4 * 64 * 8;
+  auto kern = k_gemm_nn<PT, TB, NW>;
   // raised once per process; function-local static initialisation is thread-safe
   static const hipError_t attr =
       lds > 64 * 1024 ? hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
                       : hipSuccess;
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(kern, dim3((maxN + 15) / 16, 1, nz), dim3(256), lds, st, dd, act);
+  hipLaunchKernelGGL(kern, dim3((maxN + 15) / 16, 1, nz), dim3(64 * NW), lds, st, dd, act);
   return hipGetLastError();
+}
+
+template <typename PT, int TB>
+static hipError_t launch_nn_t(const NnDesc* dd, int nz, int maxN, const int32_t* act, hipStream_t st) {
+  return launch_nn_w<PT, TB, 4>(dd, nz, maxN, act, st);
 }
 
 template <typename PT>

@@ -374,10 +374,12 @@ static int nn_splits(int N, int Ka, int nz) {
 }
 
 // Splits of the projection products [Q_0..Q_j W]^T W on the tall kernel (64-row tiles):
-// about 1024 workgroups, at least 128 values of k per split.
+// about 256 workgroups, at least 128 values of k per split.  More splits fill more of the chip
+// but every split writes a whole partial output that the reduction reads back; measured on the
+// dense d = 8192, m = 65 workload, 256 beats 512 and 1024.
 static int proj_splits(int M, int nz, int K) {
   const int tiles = (M + 63) / 64;
-  const int want = std::max(1, 1024 / std::max(1, tiles * nz));
+  const int want = std::max(1, 256 / std::max(1, tiles * nz));
   const int cap = std::max(1, K / 128);
   return std::max(1, std::min(want, std::min(cap, 64)));
 }
@@ -573,17 +575,15 @@ static void add_proj(Program& pg, std::vector<Launch>& out, Engine& E, int j, bo
   }
 }
 
-// W -= Q_{0..j} C  (rows [0, (j+1)m) of the basis)
+// W -= Q_{0..j} C  (rows [0, (j+1)m) of the basis): one launch, the workgroup's waves split the
+// reduction over the basis and combine on chip (no split partials in HBM)
 static void add_update(Program& pg, std::vector<Launch>& out, Engine& E, int j, double** C) {
   std::vector<NnDesc> nn;
-  std::vector<FinDesc> fin;
-  int maxMo = 0, maxN = 0, maxKa = 0;
+  int maxMo = 0, maxN = 0;
   for (auto& pr : E.P) {
     maxMo = std::max(maxMo, pr.m);
     maxN = std::max(maxN, pr.d);
-    maxKa = std::max(maxKa, (j + 1) * pr.m);
   }
-  const int splits = nn_splits(maxN, maxKa, (int)E.P.size());
   for (size_t p = 0; p < E.P.size(); ++p) {
     const Prob& pr = E.P[p];
     NnDesc d{};
@@ -598,37 +598,15 @@ static void add_update(Program& pg, std::vector<Launch>& out, Engine& E, int j, 
     d.Mo = pr.m;
     d.N = pr.d;
     d.active = (int)p;
-    d.part = pr.part;
     nn.push_back(d);
-    FinDesc f{};
-    f.part = pr.part;
-    f.M = pr.d;
-    f.N = pr.m;
-    f.splits = splits;
-    f.mode = FIN_AXPBY;
-    f.O = pr.block(j + 1);
-    f.rhs = pr.block(j + 1);
-    f.alpha = -1.0;
-    f.beta = 1.0;
-    f.active = (int)p;
-    fin.push_back(f);
   }
   Launch L{Launch::NN};
   L.off = pg.stg.add(nn);
   L.nz = (int)nn.size();
-  L.a0 = 1 << 9;   // tall variant
+  L.a0 = 0;
   L.a1 = maxMo;
   L.a2 = maxN;
-  L.a3 = splits;
   out.push_back(L);
-  if (splits > 1) {
-    Launch F{Launch::FIN};
-    F.off = pg.stg.add(fin);
-    F.nz = (int)fin.size();
-    F.a1 = maxN;
-    F.a2 = maxMo;
-    out.push_back(F);
-  }
 }
 
 // G = W^T W for the W in block slot `slot`
@@ -1321,8 +1299,6 @@ static void size_partials(Engine& E, const rbcg_ctx* ctx) {
     for (auto& pr : E.P) maxM = std::max(maxM, (j + 2) * pr.m);
     const int s = proj_splits(maxM, nz, K);
     if (s > 1) need = std::max(need, (size_t)s * maxM * E.maxm);
-    const int su = nn_splits(K, (j + 1) * E.maxm, nz);
-    if (su > 1) need = std::max(need, (size_t)su * E.maxm * K);
   }
   const int sg = proj_splits(E.maxm, nz, K);
   if (sg > 1) need = std::max(need, (size_t)sg * E.maxm * E.maxm);
