@@ -125,46 +125,28 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_nn(const NnDesc* __restrict__ 
   v4d acc[TB];
 #pragma unroll
   for (int tb = 0; tb < TB; ++tb) acc[tb] = v4d{0, 0, 0, 0};
-  // wave w takes a-chunks of 16 starting at 16 w, stepping 16 NW; with up to nine row tiles the
-  // operands of the next two chunks are in flight while this chunk's MFMAs run (three register
-  // stages; wider tiles would spill them)
+  // wave w takes a-chunks of 16 starting at 16 w, stepping 16 NW (deeper register pipelining of
+  // the operands measured slower: it costs occupancy)
   const gmem_t<const PT> P = gmem((const PT*)d.P.p);
   const gmem_t<const double> C = gmem(d.C);
-  constexpr int STEP = 16 * NW;
-  constexpr int NSTG = TB <= 9 ? 3 : 1;
-  double pv[NSTG][4], cv[NSTG][4][TB];
-  auto load = [&](int ac, double* pb, double (*cb)[TB]) {
+  for (int ac = 16 * wave; ac < d.Ka; ac += 16 * NW) {
+    double pv[4], cv[4][TB];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int a = ac + 4 * e + q;
       const bool aval = a < d.Ka;
-      pb[e] = (aval && ival) ? (double)P[row_off(d.P, a) + i] : 0.0;
+      pv[e] = (aval && ival) ? (double)P[row_off(d.P, a) + i] : 0.0;
 #pragma unroll
       for (int tb = 0; tb < TB; ++tb) {
         const int b = 16 * tb + r16;
-        cb[e][tb] = (aval && b < d.Mo) ? C[(int64_t)a * d.ldc + b] : 0.0;
+        cv[e][tb] = (aval && b < d.Mo) ? C[(int64_t)a * d.ldc + b] : 0.0;
       }
     }
-  };
-  int ac = 16 * wave;
 #pragma unroll
-  for (int st = 0; st + 1 < NSTG; ++st)
-    if (ac + st * STEP < d.Ka) load(ac + st * STEP, pv[st], cv[st]);
-  bool go = ac < d.Ka;
-  while (go) {
-    static_for<NSTG>([&](auto stc) {
-      constexpr int st = decltype(stc)::value;
-      if (!go) return;
-      constexpr int ld = (st + NSTG - 1) % NSTG;
-      if (ac + (NSTG - 1) * STEP < d.Ka) load(ac + (NSTG - 1) * STEP, pv[ld], cv[ld]);
+    for (int e = 0; e < 4; ++e)
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-#pragma unroll
-        for (int tb = 0; tb < TB; ++tb)
-          acc[tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(cv[st][e][tb], pv[st][e], acc[tb], 0, 0, 0);
-      ac += STEP;
-      go = ac < d.Ka;
-    });
+      for (int tb = 0; tb < TB; ++tb)
+        acc[tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(cv[e][tb], pv[e], acc[tb], 0, 0, 0);
   }
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* red = (double*)smem_raw;   // [NW - 1][TB][4][64]

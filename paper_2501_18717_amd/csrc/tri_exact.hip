@@ -19,7 +19,7 @@
 namespace rbcg {
 
 __device__ __forceinline__ double ld_agent(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(gmem(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Panels: 16 values of u in the Schur product (P and Q panels, placed in the region of S when
@@ -59,8 +59,8 @@ __device__ __forceinline__ void panel_gemm_nt(int tid, const double* Pg, bool p_
       const int e = tid + 256 * t;
       const int a = e / KP, u = u0 + e % KP;
       const bool in = e < MT * 16 * KP && a < M && u < M;
-      rp[t] = in ? (p_agent ? ld_agent(Pg + a * M + u) : Pg[a * M + u]) : 0.0;
-      rq[t] = (in && stage_q) ? Qg[a * M + u] : 0.0;
+      rp[t] = in ? (p_agent ? ld_agent(Pg + a * M + u) : gmem(Pg)[a * M + u]) : 0.0;
+      rq[t] = (in && stage_q) ? gmem(Qg)[a * M + u] : 0.0;
     }
   };
   auto put = [&]() {
@@ -147,11 +147,11 @@ __global__ __launch_bounds__(256) void k_tri_exact(const TriDesc* __restrict__ d
       }
       __syncthreads();
     }
-    for (int e = tid; e < M * r; e += 256) d.Zw[(int64_t)j * M * r + e] = zb[e];
+    for (int e = tid; e < M * r; e += 256) gmem(d.Zw)[(int64_t)j * M * r + e] = zb[e];
 
     // S_j = D_j - U_{j-1} B_{j-1}^T  (the shift and the symmetrisation come with the sweep load)
     if (j == 0) {
-      for (int e = tid; e < M * M; e += 256) S[(e / M) * MP + (e % M)] = Dj[e];
+      for (int e = tid; e < M * M; e += 256) S[(e / M) * MP + (e % M)] = gmem(Dj)[e];
     } else {
       const double* U = d.Xw + (j - 1) * mm;
       const double* B = d.Bsub + (j - 1) * mm;
@@ -162,12 +162,12 @@ __global__ __launch_bounds__(256) void k_tri_exact(const TriDesc* __restrict__ d
         // every tile of a wave stays in registers until the last panel: S may share its region
         // with the panels, as it is written only after them
         panel_gemm_nt<M, kPanelA, NTW>(tid, U, true, B, nullptr, panA, panB,
-                                       [&](int a, int b, double v) { S[a * MP + b] = Dj[a * M + b] - v; });
+                                       [&](int a, int b, double v) { S[a * MP + b] = gmem(Dj)[a * M + b] - v; });
       } else {
         // tiles in groups of 8: results go to Lw[j] (overwritten by Sinv_j later), then to S
         double* Lj = d.Lw + j * mm;
         panel_gemm_nt<M, kPanelA, 8>(tid, U, true, B, nullptr, panA, panB,
-                                     [&](int a, int b, double v) { Lj[a * M + b] = Dj[a * M + b] - v; });
+                                     [&](int a, int b, double v) { gmem(Lj)[a * M + b] = gmem(Dj)[a * M + b] - v; });
         __threadfence();
         __syncthreads();
         for (int e = tid; e < M * M; e += 256) S[(e / M) * MP + (e % M)] = ld_agent(Lj + e);
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) void k_tri_exact(const TriDesc* __restrict__ d
           double x = 0.0;
           if (a < M && c < M) {
             x = a == c ? S[a * MP + a] + d.sigma : 0.5 * (S[a * MP + c] + S[c * MP + a]);
-            if (mk[a] || mk[c]) x = a == c ? 1.0 : 0.0;
+            if (gmem(mk)[a] || gmem(mk)[c]) x = a == c ? 1.0 : 0.0;
           }
           v[i][k] = x;
         }
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256) void k_tri_exact(const TriDesc* __restrict__ d
           const int a = rl + GR * i, c = cl + GR * k;
           if (a < M && c < M) {
             S[a * MP + c] = -v[i][k];
-            Lj[a * M + c] = -v[i][k];
+            gmem(Lj)[a * M + c] = -v[i][k];
           }
         }
     }
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(256) void k_tri_exact(const TriDesc* __restrict__ d
     {
       double* Uj = d.Xw + j * mm;
       panel_gemm_nt<M, kPanelC, 8>(tid, Bj, false, nullptr, S, pan, nullptr,
-                                [&](int a, int b, double v) { Uj[a * M + b] = v; });
+                                [&](int a, int b, double v) { gmem(Uj)[a * M + b] = v; });
     }
     // y = Sinv_j rhs'_j
     for (int e = tid; e < M * r; e += 256) {
@@ -269,9 +269,9 @@ __global__ __launch_bounds__(256) void k_tri_exact(const TriDesc* __restrict__ d
     for (int e = tid; e < M * r; e += 256) {
       const int a = e / r, c = e % r;
       double acc = 0.0;
-      for (int u = 0; u < M; ++u) acc += Bj[a * M + u] * zy[u * r + c];
+      for (int u = 0; u < M; ++u) acc += gmem(Bj)[a * M + u] * zy[u * r + c];
       zb[e] = -acc;
-      d.Zw[(int64_t)(j + 1) * M * r + e] = -acc;
+      gmem(d.Zw)[(int64_t)(j + 1) * M * r + e] = -acc;
       sq += acc * acc;
     }
 #pragma unroll
