@@ -49,20 +49,27 @@ static hipError_t set_big_lds(const void* k) {
 //   FIN_ROWMAJOR: part[s][i][c] -> out[i*ldo + c]
 //   FIN_TRANS / FIN_RESID: part[s][c][i] -> row c of O, element i
 // ---------------------------------------------------------------------------------------------
-// sum_s p[s * stride] in split order; the loads of four splits are issued together.
-__device__ __forceinline__ double split_sum(gmem_t<const double> p, int64_t stride, int splits) {
+// sum over s = first, first + step, ... < splits of p[s * stride], in that order; the loads of
+// four splits are issued together.
+__device__ __forceinline__ double split_sum(gmem_t<const double> p, int64_t stride, int splits, int first = 0,
+                                            int step = 1) {
   double v = 0.0;
-  int s = 0;
-  for (; s + 4 <= splits; s += 4) {
-    const double a = p[(int64_t)s * stride], b = p[(int64_t)(s + 1) * stride];
-    const double c = p[(int64_t)(s + 2) * stride], d = p[(int64_t)(s + 3) * stride];
+  int s = first;
+  for (; s + 3 * step < splits; s += 4 * step) {
+    const double a = p[(int64_t)s * stride], b = p[(int64_t)(s + step) * stride];
+    const double c = p[(int64_t)(s + 2 * step) * stride], d = p[(int64_t)(s + 3 * step) * stride];
     v = (((v + a) + b) + c) + d;
   }
-  for (; s < splits; ++s) v += p[(int64_t)s * stride];
+  for (; s < splits; s += step) v += p[(int64_t)s * stride];
   return v;
 }
 
-__global__ __launch_bounds__(256) void k_finish(const FinDesc* __restrict__ descs, const int32_t* __restrict__ act) {
+// tpo (a power of two up to 64, FIN_T2R only): lanes per output; lane u of a group sums splits
+// u, u + tpo, ... and the group combines by a fixed butterfly, so the result does not depend on
+// the launch shape beyond tpo.  Small outputs with many splits (the Gram and projection
+// reductions) get the extra parallelism.
+__global__ __launch_bounds__(256) void k_finish(const FinDesc* __restrict__ descs, const int32_t* __restrict__ act,
+                                                int tpo) {
   const FinDesc f = descs[blockIdx.z];
   if (!is_active(act, f.active)) return;
   const bool rowmajor = f.mode == FIN_ROWMAJOR;
@@ -70,11 +77,17 @@ __global__ __launch_bounds__(256) void k_finish(const FinDesc* __restrict__ desc
   const int cols = rowmajor ? f.N : f.M;
   if (f.mode == FIN_T2R) {
     const int64_t total = (int64_t)f.N * f.M;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
-      const int c = (int)(e / f.M), i = (int)(e % f.M);
-      const double v = split_sum(gmem(f.part) + e, total, f.splits);
-      gmem(f.out)[(int64_t)i * f.ldo + c] = f.alpha * v;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int sub = (int)(gid & (tpo - 1));
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x / tpo;
+    // every lane of a group sees the same e, so whole groups enter and leave the loop together
+    for (int64_t e = gid / tpo; e < total; e += stride) {
+      double v = split_sum(gmem(f.part) + e, total, f.splits, sub, tpo);
+      for (int off = 1; off < tpo; off <<= 1) v += __shfl_xor(v, off, 64);
+      if (sub == 0) {
+        const int c = (int)(e / f.M), i = (int)(e % f.M);
+        gmem(f.out)[(int64_t)i * f.ldo + c] = f.alpha * v;
+      }
     }
     return;
   }
@@ -99,11 +112,13 @@ __global__ __launch_bounds__(256) void k_finish(const FinDesc* __restrict__ desc
   }
 }
 
-hipError_t launch_finish(const FinDesc* dd, int nz, int maxM, int maxN, const int32_t* act, hipStream_t st) {
-  const int64_t tot = (int64_t)maxM * maxN;
+hipError_t launch_finish(const FinDesc* dd, int nz, int maxM, int maxN, const int32_t* act, hipStream_t st,
+                         int tpo) {
+  if (tpo < 1 || tpo > 64 || (tpo & (tpo - 1))) return hipErrorInvalidValue;
+  const int64_t tot = (int64_t)maxM * maxN * tpo;
   int blocks = (int)std::min<int64_t>((tot + 255) / 256, 2048);
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_finish, dim3(blocks, 1, nz), dim3(256), 0, st, dd, act);
+  hipLaunchKernelGGL(k_finish, dim3(blocks, 1, nz), dim3(256), 0, st, dd, act, tpo);
   return hipGetLastError();
 }
 

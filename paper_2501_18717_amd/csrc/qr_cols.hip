@@ -486,6 +486,9 @@ void k_qr_np(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) 
   }
   __syncthreads();
   if (wi[8] < 0) {   // uniform: redo the factorization with pivoting
+    // the attempt already stored rows of Bout and Mout; those stores must be complete before
+    // the redo stores the same addresses from other lanes
+    __threadfence();
     __syncthreads();
     qr_pivoted<M, GR, NWF>(d);
     return;

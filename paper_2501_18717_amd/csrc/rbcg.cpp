@@ -384,6 +384,14 @@ static int proj_splits(int M, int nz, int K) {
   return std::max(1, std::min(want, std::min(cap, 64)));
 }
 
+// Lanes per output of a transposing split-K reduction: a power of two, about four splits per
+// lane, at most 16 (1 below 8 splits).
+static int fin_lanes(int splits) {
+  int t = 1;
+  while (t < 16 && 4 * (2 * t) <= splits) t *= 2;
+  return t;
+}
+
 // Widths served by the FP32 32x32x2 product kernel: N = 32 t2 + ne (ne = 1: the last column on
 // the vector ALU).
 static bool wide_shape(int N, int* t2, int* ne) {
@@ -488,7 +496,7 @@ static hipError_t enqueue(const Launch& L, unsigned char* dbase, const int32_t* 
       }
       return launch_gemm_nt_ex(L.a0 & 0xff, (L.a0 >> 8) & 1, L.flag, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a2,
                                L.a3, act, st);
-    case Launch::FIN: return launch_finish(dptr<FinDesc>(dbase, L.off), L.nz, L.a1, L.a2, act, st);
+    case Launch::FIN: return launch_finish(dptr<FinDesc>(dbase, L.off), L.nz, L.a1, L.a2, act, st, std::max(1, L.a3));
     case Launch::NN:
       if (L.a0 & (1 << 9))
         return launch_nn_tall(L.flag, dptr<NnDesc>(dbase, L.off), L.nz, L.a1, L.a2, L.a3, act, st);
@@ -571,6 +579,7 @@ static void add_proj(Program& pg, std::vector<Launch>& out, Engine& E, int j, bo
     F.nz = (int)fin.size();
     F.a1 = maxM;
     F.a2 = maxN;
+    F.a3 = fin_lanes(splits);
     out.push_back(F);
   }
 }
@@ -655,6 +664,7 @@ static void add_gram(Program& pg, std::vector<Launch>& out, Engine& E, int slot)
     F.nz = (int)fin.size();
     F.a1 = maxm;
     F.a2 = maxm;
+    F.a3 = fin_lanes(splits);
     out.push_back(F);
   }
 }

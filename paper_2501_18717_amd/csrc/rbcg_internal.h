@@ -146,7 +146,7 @@ struct CvtDesc {
 hipError_t launch_gemm_nt_ex(int dtype, int out_t, bool xsplit, const NtDesc* d_desc, int nz, int maxM,
                              int maxN, int splits, const int32_t* active, hipStream_t st);
 hipError_t launch_finish(const FinDesc* d_desc, int nz, int maxM, int maxN, const int32_t* active,
-                         hipStream_t st);
+                         hipStream_t st, int lanes_per_output = 1);
 hipError_t launch_gemm_nn_ex(bool p_f32, const NnDesc* d_desc, int nz, int maxMo, int maxN,
                              const int32_t* active, hipStream_t st);
 // Same product, 64 output columns per workgroup with the C chunk staged in LDS and P streamed
