@@ -740,7 +740,6 @@ static void add_cholqr(Program& pg, std::vector<Launch>& out, Engine& E, int slo
       d.active = (int)p;
       d.eta2 = E.eta2;
       d.tau = E.tau;
-      if (dg) d.dg = dg[p];   // the diagonal block of T of the previous basis block
       qr.push_back(d);
     }
     Launch L{Launch::QR};
@@ -776,6 +775,9 @@ static void add_cholqr(Program& pg, std::vector<Launch>& out, Engine& E, int slo
       // first-pass column whose true new part is at rounding level can be kept; its scaled
       // column then has a norm far from one.  Such columns are dropped here.
       d.floor2 = 0.25;
+      // the diagonal block of T of the previous basis block, formed by this launch's 1024 threads
+      // (C1 and C2 stay intact until the next step's projections)
+      if (dg) d.dg = dg[p];
       qr.push_back(d);
     }
     Launch L{Launch::QR};
@@ -1266,7 +1268,7 @@ static void build_program(Program& pg, Engine& E, const std::vector<double>& tol
     // Cholesky QR pass (the second update changes W only at rounding level)
     add_proj(pg, out, E, j, true, c2.data());
     add_update(pg, out, E, j, c2.data());
-    // D_j = sym(C1 + C2) block j, formed by the first Cholesky-QR pass' workgroups
+    // D_j = sym(C1 + C2) block j, formed by the second Cholesky-QR pass' workgroups
     std::vector<DiagDesc> dd;
     for (size_t p = 0; p < E.P.size(); ++p) {
       const Prob& pr = E.P[p];
