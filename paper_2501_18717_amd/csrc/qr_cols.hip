@@ -357,12 +357,11 @@ void k_qr_np(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) 
   const gmem_t<const double> G = gmem(d.G);
   const int64_t ldg = d.ldg;
   const double tau = fmax(d.tau, 1e-8);
-  // with a previous factor the rows of R are kept for Bout = R prevB, else written out directly
+  // rows of R go to LDS as they are formed (Bout leaves after the loop, or as R prevB); the pad
+  // column is read by the R prevB product
   const bool keepR = d.prevB != nullptr;
-  if (keepR) {
-    for (int e = tid; e < M * MP; e += NT) Rl[e] = 0.0;
-    __syncthreads();
-  }
+  if (keepR && (M & 1))
+    for (int e = tid; e < M; e += NT) Rl[e * MP + M] = 0.0;
 
   if (wave < NWF) {
     const int rl = tid % GR, cl = tid / GR;
@@ -375,12 +374,20 @@ void k_qr_np(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) 
         const int a = rl + GR * i, c = cl + GR * j;
         v[i][j] = (a < M && c < M) ? G[(int64_t)a * ldg + c] : 0.0;
       }
-    double dref[S], pre[S], rv[S];
+    // per column the bound its Schur pivot must exceed (every deflation test in one number):
+    // max(tau dref, eta2 pre (when known), floor2), +inf when the column has no norm; only 0 for
+    // a forced first column
+    double thr[S], rv[S];
 #pragma unroll
     for (int i = 0; i < S; ++i) {
       const int a = rl + GR * i;
-      dref[i] = (dl && a < M) ? v[i][i] : 0.0;
-      pre[i] = (dl && a < M && d.pre) ? gmem(d.pre)[(int64_t)a * d.pre_stride] : -1.0;
+      const double dref = (dl && a < M) ? v[i][i] : 0.0;
+      const double pre = (dl && a < M && d.pre) ? gmem(d.pre)[(int64_t)a * d.pre_stride] : -1.0;
+      double t = fmax(tau * dref, d.floor2);
+      if (pre >= 0.0) t = fmax(t, d.eta2 * pre);
+      if (!(dref > 0.0)) t = INFINITY;
+      if (d.force_first && a == 0) t = 0.0;
+      thr[i] = t;
       rv[i] = 0.0;
     }
     bool ok = true;
@@ -401,10 +408,7 @@ void k_qr_np(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) 
             const int a = rl + GR * i;
             if (a < M) pr[a] = v[i][js];
           }
-          if (dl) {
-            pr[MP] = dref[js];
-            pr[MP + 1] = pre[js];
-          }
+          if (dl) pr[MP] = thr[js];
         }
         if (rl == r) {   // row s of E (final: its last update was step s - 1)
 #pragma unroll
@@ -417,7 +421,7 @@ void k_qr_np(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) 
         else __builtin_amdgcn_wave_barrier();
         // every value this step needs, read at once
         const double piv2 = pr[s];
-        const double drp = pr[MP], prp = pr[MP + 1];
+        const double thp = pr[MP];
         double ra[S], rc[S], re[S];
 #pragma unroll
         for (int i = js; i < S; ++i) {
@@ -430,12 +434,7 @@ void k_qr_np(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) 
           const int c = cl + GR * j;
           re[j] = c < M ? pq[c] : 0.0;
         }
-        bool bad;
-        if (d.force_first && s == 0) bad = !(piv2 > 0.0);
-        else   // all terms evaluated (no short circuit: no extra round trips)
-          bad = !(drp > 0.0) | !(piv2 > tau * drp) | ((prp >= 0.0) & !(piv2 > d.eta2 * prp)) |
-                !(piv2 > d.floor2);
-        if (bad) {
+        if (!(piv2 > thp)) {
           ok = false;
           break;
         }
@@ -460,11 +459,7 @@ void k_qr_np(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) 
 #pragma unroll
           for (int j = 0; j < S; ++j) {
             const int c = cl + GR * j;
-            if (c < M) {
-              const double x = (j >= js && c >= s) ? rc[j] * irp : 0.0;
-              if (keepR) Rl[s * MP + c] = x;
-              else gmem(d.Bout)[(int64_t)s * M + c] = x;
-            }
+            if (c < M) Rl[s * MP + c] = (j >= js && c >= s) ? rc[j] * irp : 0.0;
           }
         }
       }
@@ -486,8 +481,8 @@ void k_qr_np(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) 
   }
   __syncthreads();
   if (wi[8] < 0) {   // uniform: redo the factorization with pivoting
-    // the attempt already stored rows of Bout and Mout; those stores must be complete before
-    // the redo stores the same addresses from other lanes
+    // the attempt already stored rows of Mout; those stores must be complete before the redo
+    // stores the same addresses from other lanes
     __threadfence();
     __syncthreads();
     qr_pivoted<M, GR, NWF>(d);
@@ -495,6 +490,8 @@ void k_qr_np(const QrDesc* __restrict__ descs, const int32_t* __restrict__ act) 
   }
   for (int c = tid; c < M; c += NT) gmem(d.mask)[c] = 0;
   if (tid == 0 && d.rank_out) *gmem(d.rank_out) = M;
+  if (!keepR)
+    for (int e = tid; e < M * M; e += NT) gmem(d.Bout)[e] = Rl[(e / M) * MP + e % M];
   if (keepR) {   // Bout = R prevB, one lane per column
     const int c = tid;
     if (c < M) {
