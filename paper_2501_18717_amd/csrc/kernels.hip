@@ -378,7 +378,6 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
                                                     int lds_bytes) {
   const QrDesc d = descs[blockIdx.z];
   if (!is_active(act, d.active)) return;
-  if (d.dg.D) diag_block(d.dg, threadIdx.x, 1024);
   const int m = d.m;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int stripes = 1024 / m;
@@ -402,54 +401,70 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
   //      max |E| <= 1e-8 gives R = I + F (F = upper part of E, halved diagonal) and
   //      R^{-1} = I - F, both exact to O(|E|^2) = rounding level; no sequential factorization.
   if (!d.pivot && d.prevB) {
-    __shared__ int s_small;
+    __shared__ int s_small, s_kept;
     __shared__ double s_wmax[16];
-    for (int i = tid; i < m; i += 1024) dref[i] = gmem(d.G)[(int64_t)i * d.ldg + i];
+    __shared__ int s_wcnt[16];
+    // G into LDS (Rl) and prevB behind the other arrays when the launch reserved room: one pass
+    // over global memory, everything after it reads LDS
+    const size_t pb_off = ((size_t)((unsigned char*)(kept + m) - smem_raw) + 15) & ~(size_t)15;
+    double* pb = (double*)(smem_raw + pb_off);
+    const bool whole = (int64_t)((unsigned char*)(pb + m * m) - smem_raw) <= lds_bytes;
+    {
+      const gmem_t<const double> G = gmem(d.G), PB = gmem(d.prevB);
+      for (int e = tid; e < m * m; e += 1024) {
+        const int a = e / m, cc = e - a * m;
+        Rl[e] = G[(int64_t)a * d.ldg + cc];
+        if (whole) pb[e] = PB[e];
+      }
+    }
+    if (d.dg.D) diag_block(d.dg, threadIdx.x, 1024);   // independent work while the loads land
     __syncthreads();
     double emax = 0.0;
     for (int e = tid; e < m * m; e += 1024) {
       const int a = e / m, cc = e - a * m;
-      if (dref[a] == 0.0 || dref[cc] == 0.0) continue;   // deflated (zero) columns
-      const double g = gmem(d.G)[(int64_t)a * d.ldg + cc];
-      emax = fmax(emax, fabs(g - (a == cc ? 1.0 : 0.0)));
+      if (Rl[a * m + a] == 0.0 || Rl[cc * m + cc] == 0.0) continue;   // deflated (zero) columns
+      emax = fmax(emax, fabs(Rl[e] - (a == cc ? 1.0 : 0.0)));
     }
+    int cnt = (tid < m && Rl[tid * m + tid] != 0.0) ? 1 : 0;   // m <= 1024
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) emax = fmax(emax, __shfl_xor(emax, off, 64));
-    if (lane == 0) s_wmax[wave] = emax;
+    for (int off = 32; off > 0; off >>= 1) {
+      emax = fmax(emax, __shfl_xor(emax, off, 64));
+      cnt += __shfl_xor(cnt, off, 64);
+    }
+    if (lane == 0) {
+      s_wmax[wave] = emax;
+      s_wcnt[wave] = cnt;
+    }
     __syncthreads();
     if (tid == 0) {
       double mx = 0.0;
-      for (int w = 0; w < 16; ++w) mx = fmax(mx, s_wmax[w]);
+      int kc = 0;
+      for (int w = 0; w < 16; ++w) {
+        mx = fmax(mx, s_wmax[w]);
+        kc += s_wcnt[w];
+      }
       s_small = mx <= 1e-8;
+      s_kept = kc;
     }
     __syncthreads();
     if (s_small) {
       // kept[i] = column i non-zero; F in Rl (upper), Bout = (I + F) prevB, Mout = I - F
       for (int i = tid; i < m; i += 1024) {
-        kept[i] = dref[i] != 0.0;
+        kept[i] = Rl[i * m + i] != 0.0;
         gmem(d.mask)[i] = kept[i] ? 0 : 1;
       }
       __syncthreads();
-      // prevB in LDS (behind the other arrays) when the launch reserved room, else 16-column panels
-      const size_t pb_off = ((size_t)((unsigned char*)(kept + m) - smem_raw) + 15) & ~(size_t)15;
-      double* pb = (double*)(smem_raw + pb_off);
-      const bool whole = (int64_t)((unsigned char*)(pb + m * m) - smem_raw) <= lds_bytes;
-      for (int e = tid; e < m * m; e += 1024) {
+      for (int e = tid; e < m * m; e += 1024) {   // in place: each element read and written by one thread
         const int a = e / m, cc = e - a * m;
         double f = 0.0;
         if (kept[a] && kept[cc] && cc >= a) {
-          const double g = gmem(d.G)[(int64_t)a * d.ldg + cc];
+          const double g = Rl[e];
           f = (a == cc) ? 0.5 * (g - 1.0) : g;
         }
         Rl[e] = f;
         gmem(d.Mout)[e] = (kept[a] && kept[cc]) ? ((a == cc ? 1.0 : 0.0) - f) : 0.0;
-        if (whole) pb[e] = gmem(d.prevB)[e];
       }
-      if (tid == 0 && d.rank_out) {
-        int rk = 0;
-        for (int i = 0; i < m; ++i) rk += kept[i];
-        *gmem(d.rank_out) = rk;
-      }
+      if (tid == 0 && d.rank_out) *gmem(d.rank_out) = s_kept;
       __syncthreads();
       if (whole) {
         for (int e = tid; e < m * m; e += 1024) {
@@ -486,6 +501,9 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
       }
       return;
     }
+    __syncthreads();   // Rl is reused below
+  } else if (d.dg.D) {
+    diag_block(d.dg, threadIdx.x, 1024);
   }
 
   // ---- unpivoted attempt (the common case) with the inverse factor carried along: thread
