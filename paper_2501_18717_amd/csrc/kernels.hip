@@ -467,15 +467,25 @@ __global__ __launch_bounds__(1024) void k_qr_factor(const QrDesc* __restrict__ d
       if (tid == 0 && d.rank_out) *gmem(d.rank_out) = s_kept;
       __syncthreads();
       if (whole) {
-        for (int e = tid; e < m * m; e += 1024) {
-          const int s0 = e / m, cc = e - s0 * m;
-          double acc = 0.0;
-          if (kept[s0]) {
-            acc = pb[s0 * m + cc];
-            const double* Fs = Rl + s0 * m;
-            for (int u = s0; u < m; ++u) acc += Fs[u] * pb[u * m + cc];
+        // F prevB on the FP64 16x16x4 MFMA from LDS: 16 x 16 output tiles dealt to the 16
+        // waves; F is upper triangular, so tile row ti starts its reduction at u = 16 ti
+        const int MT = (m + 15) / 16;
+        const int r16 = lane & 15, kq = lane >> 4;
+        for (int tile = wave; tile < MT * MT; tile += 16) {
+          const int ti = tile / MT, tj = tile - ti * MT;
+          const int s0 = 16 * ti + r16, cc = 16 * tj + r16;
+          v4d acc = {0.0, 0.0, 0.0, 0.0};
+          for (int u0 = 16 * ti; u0 < m; u0 += 4) {
+            const int u = u0 + kq;
+            const double a = (s0 < m && u < m) ? Rl[s0 * m + u] : 0.0;
+            const double b = (u < m && cc < m) ? pb[u * m + cc] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
           }
-          gmem(d.Bout)[s0 * m + cc] = acc;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * ti + kq + 4 * r, col = 16 * tj + r16;
+            if (row < m && col < m) gmem(d.Bout)[row * m + col] = kept[row] ? pb[row * m + col] + acc[r] : 0.0;
+          }
         }
         return;
       }
