@@ -142,7 +142,10 @@ def main():
         solve(x_64, o_64)
     torch.cuda.synchronize()
 
-    # ---- timed: mixed precision (the reported value)
+    # ---- timed: mixed precision (the reported value).  Every block product is timed with a
+    # pair of HIP events (the markers cost the solve about 13 us per product; timing only every
+    # fourth launch measured launch durations 10-15% below the rocprofv3 trace of the same
+    # launches, so all of them are timed).
     ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

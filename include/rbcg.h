@@ -185,13 +185,16 @@ int rbcg_op_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t N, const double* X, 
 /* Bytes of device memory currently held by the context's workspace. */
 int64_t rbcg_workspace_bytes(const rbcg_ctx* ctx);
 
-/* Measurement hook.  rbcg_profile(ctx, 1) clears the counters and starts
- * timing every block-product GEMM launch (the A X or Z^T (Z X) products that
- * the paper counts as matrix-loads, Sec. 1.2) with HIP events on the context's
- * stream; rbcg_profile(ctx, 0) stops.  rbcg_profile_read reports the number of
- * timed launches, their summed GPU time in milliseconds, and their summed
- * algorithmic flops (2 * rows * cols * block width per GEMM) and HBM bytes
- * (one read of the operator per GEMM).  All pointers are host pointers. */
+/* Measurement hook.  rbcg_profile(ctx, n) with n >= 1 clears the counters and
+ * starts timing every n-th block-product GEMM launch (the A X or Z^T (Z X)
+ * products that the paper counts as matrix-loads, Sec. 1.2; n = 1: all of
+ * them) with a pair of HIP events on the context's stream; each pair adds a
+ * marker to the stream, which n > 1 keeps off most launches.  rbcg_profile(ctx,
+ * 0) stops; n < 0 is RBCG_ERR_INVALID_ARG.  rbcg_profile_read reports the
+ * number of timed launches, their summed GPU time in milliseconds, and their
+ * summed algorithmic flops (2 * rows * cols * block width per GEMM) and HBM
+ * bytes (one read of the operator per GEMM).  All pointers are host
+ * pointers. */
 int rbcg_profile(rbcg_ctx* ctx, int enable);
 int rbcg_profile_read(const rbcg_ctx* ctx, int64_t* launches, double* ms_total, double* flops_total,
                       double* bytes_total);

@@ -54,6 +54,9 @@ struct rbcg_ctx {
   hipEvent_t ev_mon = nullptr;
   // block-product timing (rbcg_profile): event pairs around each block-product GEMM launch
   bool prof = false;
+  int prof_every = 1;          // time every prof_every-th block-product launch
+  int64_t prof_seen = 0;       // block-product launches since rbcg_profile
+  bool prof_open = false;      // a begin event is recorded and waits for its end
   std::vector<hipEvent_t> prof_pool;
   size_t prof_used = 0;
   std::vector<double> prof_flops, prof_bytes;
@@ -168,8 +171,11 @@ extern "C" int rbcg_destroy(rbcg_ctx* c) {
 extern "C" int64_t rbcg_workspace_bytes(const rbcg_ctx* c) { return c ? (int64_t)c->ws_cap : 0; }
 
 extern "C" int rbcg_profile(rbcg_ctx* c, int enable) {
-  if (!c) return RBCG_ERR_INVALID_ARG;
+  if (!c || enable < 0) return RBCG_ERR_INVALID_ARG;
   c->prof = enable != 0;
+  c->prof_every = enable > 0 ? enable : 1;
+  c->prof_seen = 0;
+  c->prof_open = false;
   c->prof_used = 0;
   c->prof_flops.clear();
   c->prof_bytes.clear();
@@ -443,6 +449,9 @@ struct Launch {
 // Event pair around a profiled launch; elapsed times are collected after the call's final sync.
 static hipError_t prof_begin(rbcg_ctx* c, const Launch& L, hipStream_t st) {
   if (!c->prof || !L.prof) return hipSuccess;
+  // every event pair costs a marker on the stream: sample the launches
+  if (c->prof_seen++ % c->prof_every != 0) return hipSuccess;
+  c->prof_open = true;
   if (c->prof_used + 2 > c->prof_pool.size()) {
     for (int i = 0; i < 64; ++i) {
       hipEvent_t e;
@@ -456,7 +465,8 @@ static hipError_t prof_begin(rbcg_ctx* c, const Launch& L, hipStream_t st) {
   return hipEventRecord(c->prof_pool[c->prof_used], st);
 }
 static hipError_t prof_end(rbcg_ctx* c, const Launch& L, hipStream_t st) {
-  if (!c->prof || !L.prof) return hipSuccess;
+  if (!c->prof || !L.prof || !c->prof_open) return hipSuccess;
+  c->prof_open = false;
   hipError_t e = hipEventRecord(c->prof_pool[c->prof_used + 1], st);
   c->prof_used += 2;
   return e;
@@ -1489,9 +1499,16 @@ static int run_steps(rbcg_ctx* ctx, Engine& E, Program& pg, unsigned char* dbase
   // block product of step j + 1 has been issued, so that it overlaps the small kernels of that
   // step rather than holding a compute unit the product's workgroups wait for.
   int pending = -1;
-  auto start_monitor = [&](int jm) -> hipError_t {
-    hipError_t e = hipEventRecord(ctx->ev_mon, st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->side, ctx->ev_mon, 0);
+  // one event marks each step's progress on the stream (a marker costs several microseconds of
+  // idle time between dependent kernels): recorded once the step's block product is issued, it
+  // releases the previous step's monitor on the side stream and paces the host
+  auto start_monitor = [&](int jm, hipEvent_t after) -> hipError_t {
+    hipError_t e = hipSuccess;
+    if (!after) {
+      after = ctx->ev_mon;
+      e = hipEventRecord(after, st);
+    }
+    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->side, after, 0);
     for (const auto& L : pg.mon[jm])
       if (e == hipSuccess) e = enqueue(L, dbase, E.active, ctx->side);
     return e;
@@ -1500,22 +1517,27 @@ static int run_steps(rbcg_ctx* ctx, Engine& E, Program& pg, unsigned char* dbase
   for (; j < E.t_max; ++j) {
     const auto& steps = pg.steps[j + 1];
     const int pe = (int)pg.prod_end.size() > j + 1 ? pg.prod_end[j + 1] : 0;
+    bool marked = false;
     for (int i = 0; i < (int)steps.size(); ++i) {
       HIP_TRY(run(steps[i]));
-      if (i + 1 == pe && pending >= 0) {
-        HIP_TRY(start_monitor(pending));
-        pending = -1;
+      if (i + 1 == pe && E.done_h) {
+        HIP_TRY(hipEventRecord(ctx->ev[j & 1], st));
+        marked = true;
+        if (pending >= 0) {
+          HIP_TRY(start_monitor(pending, ctx->ev[j & 1]));
+          pending = -1;
+        }
       }
     }
     if (pending >= 0) {
-      HIP_TRY(start_monitor(pending));
+      HIP_TRY(start_monitor(pending, nullptr));
       pending = -1;
     }
     if (!pg.mon[j].empty()) pending = j;
-    HIP_TRY(hipEventRecord(ctx->ev[j & 1], st));
     if (E.done_h) {
+      if (!marked) HIP_TRY(hipEventRecord(ctx->ev[j & 1], st));
       // the convergence kernels clear the pinned mirror themselves: no copy on the stream; the
-      // host runs at most one step ahead of the device
+      // host waits for the previous step's block product, so it runs about one step ahead
       if (j >= 1) {
         HIP_TRY(hipEventSynchronize(ctx->ev[(j - 1) & 1]));
         bool any = false;
@@ -1536,7 +1558,7 @@ static int run_steps(rbcg_ctx* ctx, Engine& E, Program& pg, unsigned char* dbase
       if (!any) { ++j; break; }
     }
   }
-  if (pending >= 0) HIP_TRY(start_monitor(pending));
+  if (pending >= 0) HIP_TRY(start_monitor(pending, nullptr));
   HIP_TRY(hipStreamSynchronize(st));
   HIP_TRY(hipStreamSynchronize(ctx->side));
   prof_collect(ctx);

@@ -141,9 +141,11 @@ class Context:
     def workspace_bytes(self) -> int:
         return int(_ws_bytes(self._h))
 
-    def profile(self, enable: bool):
-        """Start (clearing counters) or stop event timing of the block-product GEMMs."""
-        _check(_profile(self._h, 1 if enable else 0), "rbcg_profile")
+    def profile(self, enable: bool, every: int = 1):
+        """Start (clearing counters) or stop event timing of every `every`-th block-product GEMM."""
+        if enable and every < 1:
+            raise ValueError("every must be >= 1")
+        _check(_profile(self._h, int(every) if enable else 0), "rbcg_profile")
 
     def profile_read(self) -> dict:
         n = _i64()
