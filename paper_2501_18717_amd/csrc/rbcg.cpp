@@ -2201,6 +2201,24 @@ static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, c
       if (opts[s].rtol == 0.0 || relres[s] <= opts[s].rtol) done[s] = 1;
     }
   }
+  // directions dropped in each system's last Krylov space: the deflation masks of its blocks
+  // 0 .. iters - 1 (one copy per system, one synchronisation)
+  {
+    std::vector<std::vector<int32_t>> mh(nsys);
+    for (int64_t s = 0; s < nsys; ++s) {
+      const Prob& pr = E.P[s];
+      const int t = std::min(iters[s], E.t_max);
+      if (t <= 0) continue;
+      mh[s].resize((size_t)t * pr.m);
+      HIP_TRY(hipMemcpyAsync(mh[s].data(), pr.mask, mh[s].size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int64_t s = 0; s < nsys; ++s) {
+      int n = 0;
+      for (int32_t f : mh[s]) n += f != 0;
+      deflated[s] = n;
+    }
+  }
   int ret = RBCG_OK;
   for (int64_t s = 0; s < nsys; ++s) {
     if (status[s] == RBCG_OK && opts[s].rtol > 0.0 && !(relres[s] <= opts[s].rtol)) status[s] = RBCG_ERR_NO_CONVERGENCE;

@@ -88,6 +88,26 @@ def test_ragged_shapes(R, d, k, t, p, mu):
     assert a_err(A, mu, x, X[0]) < max(1e-12, 1e-15 * kappa)
 
 
+@pytest.mark.parametrize("d,k,t", [(200, 128, 2), (150, 64, 3)])
+def test_deflation_late_in_a_block(R, d, k, t):
+    """The Krylov space reaches dimension d partway through the last block (129 + 71 = 200,
+    2 * 65 + 20 = 150): that block's factorization starts unpivoted, completes several rows of
+    its output, then meets a deflated column and is redone with pivoting by the same
+    workgroup.  Exact termination: the answer is the dense solution."""
+    note(f"late deflation d={d} k={k} t={t}")
+    g = np.random.default_rng(7 * d + k)
+    lam = np.arange(1, d + 1, dtype=float) ** (-1.0)
+    A = synth.spd_from_spectrum(lam, g)
+    b = g.standard_normal(d)
+    Om = g.standard_normal((k, d))
+    mu = 1e-2
+    rc, info, x = _solve_one(R, A, mu, b, Om, t)
+    assert rc == 0, info
+    assert info["deflated"] > 0, info
+    xt = ot.solve_dense(A, mu, b)
+    assert a_err(A, mu, x, xt) < 1e-11
+
+
 def test_batched_uneven_systems_match_one_at_a_time(R):
     """Several systems of uneven d and k in one call equal separate calls and
     the oracle (batching must not change results)."""
