@@ -1567,6 +1567,17 @@ static int run_steps(rbcg_ctx* ctx, Engine& E, Program& pg, unsigned char* dbase
 }
 
 // --------------------------------------------------------------------------- helpers
+// Directions dropped in blocks 0 .. t - 1 of a problem's Krylov space (its deflation masks).
+static int count_deflated(const Prob& pr, int t, hipStream_t st, int* out) {
+  *out = 0;
+  if (t <= 0) return RBCG_OK;
+  std::vector<int32_t> mh((size_t)t * pr.m);
+  HIP_TRY(hipMemcpyAsync(mh.data(), pr.mask, mh.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int32_t f : mh) *out += f != 0;
+  return RBCG_OK;
+}
+
 static int set_active_all(rbcg_ctx* ctx, Engine& E, const std::vector<int32_t>& vals) {
   std::memcpy(E.active_h, vals.data(), vals.size() * sizeof(int32_t));
   if (E.done_h) std::memcpy(E.done_h, vals.data(), vals.size() * sizeof(int32_t));
@@ -2476,6 +2487,9 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
     }
     if (!refine || all) break;
   }
+  int ndefl = 0;
+  rc = count_deflated(pr, std::min(iters, E.t_max), st, &ndefl);
+  if (rc) return rc;
   int ret = RBCG_OK;
   for (int64_t l = 0; l < L; ++l) {
     if (status[l] == RBCG_OK && refine && !(relres[l] <= opts->rtol)) status[l] = RBCG_ERR_NO_CONVERGENCE;
@@ -2483,7 +2497,7 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
     info[l].iters = iters;
     info[l].matrix_loads = loads;
     info[l].refine_sweeps = sweeps;
-    info[l].deflated = 0;
+    info[l].deflated = ndefl;
     info[l].precision_used = opts->matvec;
     info[l].relres = relres[l];
     if (ret == RBCG_OK && status[l] != RBCG_OK) ret = status[l];
@@ -2762,6 +2776,11 @@ extern "C" int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, con
     std::vector<int32_t> fh((size_t)ngroups * nq);
     HIP_TRY(hipMemcpyAsync(fh.data(), failN, fh.size() * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    std::vector<int> ndefl(ngroups, 0);
+    for (int g = 0; g < ngroups; ++g) {
+      rc = count_deflated(E.P[g], std::min(steps, E.t_max), st, &ndefl[g]);
+      if (rc) return rc;
+    }
     int ret = RBCG_OK;
     for (int64_t i = 0; i < ms; ++i) {
       const int g = (int)(i / m);
@@ -2771,7 +2790,7 @@ extern "C" int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, con
       info[i].iters = steps;
       info[i].matrix_loads = steps;
       info[i].refine_sweeps = 1;
-      info[i].deflated = 0;
+      info[i].deflated = ndefl[g];
       info[i].precision_used = opts->matvec;
       info[i].relres = -1.0;
       if (f && ret == RBCG_OK) ret = RBCG_ERR_NOT_SPD;
