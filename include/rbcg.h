@@ -53,7 +53,9 @@ extern "C" {
 typedef enum {
   RBCG_OK = 0,
   RBCG_ERR_INVALID_ARG = -1,    /* bad size, pointer, tolerance or option */
-  RBCG_ERR_NOT_SPD = -2,        /* a non-positive pivot in T_t + mu I or in a start block */
+  RBCG_ERR_NOT_SPD = -2,        /* a non-positive pivot in T_t + mu I or in a start block; with
+                                   refinement (rtol > 0) only when the final FP64 residual also
+                                   misses rtol (a later sweep can repair a spoiled one) */
   RBCG_ERR_BREAKDOWN = -3,      /* the whole block deflated before convergence */
   RBCG_ERR_NO_CONVERGENCE = -4, /* budget exhausted; best iterate written, info.relres set */
   RBCG_ERR_HIP = -5,            /* a HIP runtime call failed */

@@ -2068,6 +2068,7 @@ static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, c
     if (!(bnorm[s] > 0.0) || !std::isfinite(bnorm[s])) return RBCG_ERR_INVALID_ARG;
   }
   std::vector<int> status(nsys, RBCG_OK), loads(nsys, 0), sweeps(nsys, 0), iters(nsys, 0), deflated(nsys, 0);
+  std::vector<char> spd_fail(nsys, 0);
   std::vector<char> done(nsys, 0);
   int max_sweeps = 1;
   for (int64_t s = 0; s < nsys; ++s) max_sweeps = std::max(max_sweeps, opts[s].rtol > 0 ? (int)opts[s].refine_max : 1);
@@ -2159,7 +2160,12 @@ static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, c
         iters[s] = t;
         loads[s] += t;
         sweeps[s] += 1;
-        if (fail_h[s]) status[s] = RBCG_ERR_NOT_SPD;
+        // a non-positive pivot spoils this sweep's correction; with refinement the FP64 residual
+        // decides (a later sweep can repair it), so it is reported only if that residual fails
+        if (fail_h[s]) {
+          if (opts[s].rtol > 0.0) spd_fail[s] = 1;
+          else status[s] = RBCG_ERR_NOT_SPD;
+        }
         TriDesc td{};
         td.D = pr.D;
         td.Bsub = pr.Bsub;
@@ -2232,7 +2238,8 @@ static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, c
   }
   int ret = RBCG_OK;
   for (int64_t s = 0; s < nsys; ++s) {
-    if (status[s] == RBCG_OK && opts[s].rtol > 0.0 && !(relres[s] <= opts[s].rtol)) status[s] = RBCG_ERR_NO_CONVERGENCE;
+    if (status[s] == RBCG_OK && opts[s].rtol > 0.0 && !(relres[s] <= opts[s].rtol))
+      status[s] = spd_fail[s] ? RBCG_ERR_NOT_SPD : RBCG_ERR_NO_CONVERGENCE;
     info[s].status = status[s];
     info[s].iters = iters[s];
     info[s].matrix_loads = loads[s];
@@ -2340,6 +2347,7 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
   if (!(bnorm > 0.0) || !std::isfinite(bnorm)) return RBCG_ERR_INVALID_ARG;
   std::vector<double> relres(L, -1.0);
   std::vector<int> status(L, RBCG_OK);
+  std::vector<char> spd_fail(L, 0);
   int loads = 0, sweeps = 0, iters = 0;
   const int max_sweeps = refine ? opts->refine_max : 1;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
@@ -2482,7 +2490,10 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
     bool all = true;
     for (int64_t l = 0; l < L; ++l) {
       relres[l] = std::sqrt(host_sq[l]) / bnorm;
-      if (fh[l]) status[l] = RBCG_ERR_NOT_SPD;
+      if (fh[l]) {   // as in the solve: with refinement the FP64 residual decides
+        if (refine) spd_fail[l] = 1;
+        else status[l] = RBCG_ERR_NOT_SPD;
+      }
       if (refine && !(relres[l] <= opts->rtol)) all = false;
     }
     if (!refine || all) break;
@@ -2492,7 +2503,8 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
   if (rc) return rc;
   int ret = RBCG_OK;
   for (int64_t l = 0; l < L; ++l) {
-    if (status[l] == RBCG_OK && refine && !(relres[l] <= opts->rtol)) status[l] = RBCG_ERR_NO_CONVERGENCE;
+    if (status[l] == RBCG_OK && refine && !(relres[l] <= opts->rtol))
+      status[l] = spd_fail[l] ? RBCG_ERR_NOT_SPD : RBCG_ERR_NO_CONVERGENCE;
     info[l].status = status[l];
     info[l].iters = iters;
     info[l].matrix_loads = loads;
