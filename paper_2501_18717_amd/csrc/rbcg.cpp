@@ -1520,11 +1520,13 @@ static int run_steps(rbcg_ctx* ctx, Engine& E, Program& pg, unsigned char* dbase
     bool marked = false;
     for (int i = 0; i < (int)steps.size(); ++i) {
       HIP_TRY(run(steps[i]));
-      if (i + 1 == pe && E.done_h) {
-        HIP_TRY(hipEventRecord(ctx->ev[j & 1], st));
-        marked = true;
+      if (i + 1 == pe) {
+        if (E.done_h) {
+          HIP_TRY(hipEventRecord(ctx->ev[j & 1], st));
+          marked = true;
+        }
         if (pending >= 0) {
-          HIP_TRY(start_monitor(pending, ctx->ev[j & 1]));
+          HIP_TRY(start_monitor(pending, marked ? ctx->ev[j & 1] : nullptr));
           pending = -1;
         }
       }
