@@ -185,6 +185,7 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_nn(const NnDesc* __restrict__ 
       double out = d.alpha * v;
       if (d.beta != 0.0) out += d.beta * gmem((const double*)d.Y.p)[row_off(d.Y, b) + i];
       gmem((double*)d.O.p)[row_off(d.O, b) + i] = out;
+      if (d.O32.p) gmem((float*)d.O32.p)[row_off(d.O32, b) + i] = (float)out;   // RNE, as k_convert
     }
   }
 }

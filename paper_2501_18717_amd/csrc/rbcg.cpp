@@ -680,6 +680,13 @@ static void add_gram(Program& pg, std::vector<Launch>& out, Engine& E, int slot)
 }
 
 // W <- W * M (in place) for block slot `slot`
+// A single dense system with FP32 block products: the second factor application of every block
+// also writes the FP32 copy the next block product reads (no separate conversion launch).
+static bool fused_q32(const Engine& E) {
+  return E.Gs.size() == 1 && E.P.size() == 1 && E.Gs[0].count == 1 && E.Gs[0].op->kind == RBCG_OP_DENSE &&
+         E.Gs[0].mv_t == RBCG_F32 && E.Gs[0].xlo != nullptr;
+}
+
 static void add_rmul(Program& pg, std::vector<Launch>& out, Engine& E, int slot, bool second) {
   std::vector<NnDesc> nn;
   int maxm = 0, maxN = 0;
@@ -697,6 +704,7 @@ static void add_rmul(Program& pg, std::vector<Launch>& out, Engine& E, int slot,
     d.Mo = pr.m;
     d.N = pr.d;
     d.active = (int)p;
+    if (second && fused_q32(E)) d.O32 = plain_rows(E.Gs[0].xlo, E.Gs[0].ld_xlo);
     nn.push_back(d);
     maxm = std::max(maxm, pr.m);
     maxN = std::max(maxN, pr.d);
@@ -915,20 +923,22 @@ static void add_matvec(Program& pg, std::vector<Launch>& out, Engine& E, int j) 
       nd.out_t = DT_F64;
       int dtype = DT_F64;
       if (G.mv_t == RBCG_F32) {
-        CvtDesc c{};
-        c.src = Xb;
-        c.dst = plain_rows(G.xlo, G.ld_xlo);
-        c.rows = G.N;
-        c.cols = d;
-        c.src_t = DT_F64;
-        c.dst_t = DT_F32;
-        c.active = act_idx;
-        Launch C{Launch::CVT};
-        C.off = pg.stg.add(std::vector<CvtDesc>{c});
-        C.nz = 1;
-        C.a1 = G.N;
-        C.a2 = d;
-        out.push_back(C);
+        if (!fused_q32(E)) {   // (else the block's last factor application wrote the copy)
+          CvtDesc c{};
+          c.src = Xb;
+          c.dst = plain_rows(G.xlo, G.ld_xlo);
+          c.rows = G.N;
+          c.cols = d;
+          c.src_t = DT_F64;
+          c.dst_t = DT_F32;
+          c.active = act_idx;
+          Launch C{Launch::CVT};
+          C.off = pg.stg.add(std::vector<CvtDesc>{c});
+          C.nz = 1;
+          C.a1 = G.N;
+          C.a2 = d;
+          out.push_back(C);
+        }
         nd.P = plain_rows(op->lo, op->ld_lo);
         nd.X = plain_rows(G.xlo, G.ld_xlo);
         dtype = DT_F32;

@@ -69,6 +69,7 @@ struct NnDesc {
   double alpha, beta;
   int32_t Ka, Mo, N, active;
   double* part;            // split partials of the tall variant ([s][b][i]) when splits > 1
+  RowOp O32;               // k_gemm_nn: FP32 copy of the output rows as well (p == null: none)
 };
 
 // Symmetrised diagonal block of T from the two projection passes.
