@@ -1112,6 +1112,84 @@ hipError_t launch_tri_backward(const TriDesc* dd, int nz, int maxm, int maxr, in
 }
 
 // ---------------------------------------------------------------------------------------------
+// Gram matrix G = W^T W of one block of m <= 16 MT rows (W's rows are the block's vectors):
+// workgroup s takes one range of k, stages it for all m rows in LDS in chunks of 32 and
+// accumulates the whole m x m result on the FP64 16x16x4 MFMA (16 x 16 tiles dealt to the 4
+// waves); partials part[s][c][i] = sum over the range of W[i][k] W[c][k] (reduced by k_finish,
+// FIN_T2R).  Both operands of a tile come from the same LDS rows, so every value of W is read
+// from memory once per launch.
+// ---------------------------------------------------------------------------------------------
+template <int MT>
+__global__ __launch_bounds__(256) void k_gram(const NtDesc* __restrict__ descs, int splits,
+                                              const int32_t* __restrict__ act) {
+  constexpr int KC = 32, WS = KC + 1;
+  constexpr int NTL = MT * MT, TPW = (NTL + 3) / 4;
+  const NtDesc d = descs[blockIdx.z];
+  if (!is_active(act, d.active)) return;
+  const int m = d.M, s = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const int kper = ((d.K + splits - 1) / splits + KC - 1) / KC * KC;
+  const int kb = s * kper, ke = min(d.K, kb + kper);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* ws = (double*)smem_raw;   // [16 MT][WS]
+  const gmem_t<const double> W = gmem((const double*)d.P.p);
+  v4d acc[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int kc = kb; kc < ke; kc += KC) {
+    for (int e = tid; e < 16 * MT * KC; e += 256) {
+      const int a = e / KC, kk = e - a * KC;
+      ws[a * WS + kk] = (a < m && kc + kk < ke) ? W[row_off(d.P, a) + kc + kk] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < KC; k4 += 4) {
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        const int tile = wave + 4 * t;
+        if (tile < NTL) {
+          const int ti = tile / MT, tj = tile - ti * MT;
+          const double x = ws[(16 * ti + r16) * WS + k4 + kq];
+          const double y = ws[(16 * tj + r16) * WS + k4 + kq];
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[t], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const gmem_t<double> part = gmem(d.part);
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int tile = wave + 4 * t;
+    if (tile >= NTL) continue;
+    const int ti = tile / MT, tj = tile - ti * MT;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * ti + kq + 4 * r, c = 16 * tj + r16;
+      if (i < m && c < m) part[((int64_t)s * m + c) * m + i] = acc[t][r];
+    }
+  }
+}
+
+bool gram_supported(int m) { return m >= 1 && m <= 80; }
+
+hipError_t launch_gram(const NtDesc* dd, int nz, int maxm, int splits, const int32_t* act, hipStream_t st) {
+  const int mt = (maxm + 15) / 16;
+  if (maxm < 1 || mt > 5 || splits < 1) return hipErrorInvalidValue;
+  const size_t lds = (size_t)16 * mt * (32 + 1) * 8;
+  const dim3 grid(splits, 1, nz);
+  switch (mt) {
+    case 1: hipLaunchKernelGGL(k_gram<1>, grid, dim3(256), lds, st, dd, splits, act); break;
+    case 2: hipLaunchKernelGGL(k_gram<2>, grid, dim3(256), lds, st, dd, splits, act); break;
+    case 3: hipLaunchKernelGGL(k_gram<3>, grid, dim3(256), lds, st, dd, splits, act); break;
+    case 4: hipLaunchKernelGGL(k_gram<4>, grid, dim3(256), lds, st, dd, splits, act); break;
+    default: hipLaunchKernelGGL(k_gram<5>, grid, dim3(256), lds, st, dd, splits, act); break;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
 // Precision conversion of rows (RNE), optional BF16 hi/lo split.
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_convert(const CvtDesc* __restrict__ descs, const int32_t* __restrict__ act) {

@@ -490,6 +490,7 @@ static void prof_collect(rbcg_ctx* c) {
 static hipError_t enqueue(const Launch& L, unsigned char* dbase, const int32_t* act, hipStream_t st) {
   switch (L.kind) {
     case Launch::NT:
+      if (L.a0 & (1 << 12)) return launch_gram(dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a3, act, st);
       if (L.a0 & (1 << 11)) {   // FP32 product on the 32x32x2 kernel
         int t2 = 0, ne = 0;
         if (!wide_shape(L.a2, &t2, &ne)) return hipErrorInvalidValue;
@@ -629,12 +630,25 @@ static void add_update(Program& pg, std::vector<Launch>& out, Engine& E, int j, 
 }
 
 // G = W^T W for the W in block slot `slot`
+// Splits of the dedicated Gram kernel (one 32-value chunk of k or more per workgroup): about
+// 256 workgroups.
+static int gram_splits(int nz, int K) {
+  return std::max(1, std::min(std::max(1, 256 / std::max(1, nz)), std::max(1, K / 32)));
+}
+
+static bool uniform_width(const Engine& E);
+
+// The Gram of a block goes to the dedicated kernel when every problem has the same width (at
+// most 80), else to the tall product kernel.
+static bool gram_kernel(const Engine& E) { return uniform_width(E) && gram_supported(E.maxm); }
+
 static void add_gram(Program& pg, std::vector<Launch>& out, Engine& E, int slot) {
   std::vector<NtDesc> nt;
   std::vector<FinDesc> fin;
   int maxm = 0, K = 0;
   for (auto& pr : E.P) { maxm = std::max(maxm, pr.m); K = std::max(K, pr.d); }
-  const int splits = proj_splits(maxm, (int)E.P.size(), K);
+  const bool gk = gram_kernel(E);
+  const int splits = gk ? gram_splits((int)E.P.size(), K) : proj_splits(maxm, (int)E.P.size(), K);
   for (size_t p = 0; p < E.P.size(); ++p) {
     const Prob& pr = E.P[p];
     NtDesc d{};
@@ -663,12 +677,13 @@ static void add_gram(Program& pg, std::vector<Launch>& out, Engine& E, int slot)
   Launch L{Launch::NT};
   L.off = pg.stg.add(nt);
   L.nz = (int)nt.size();
-  L.a0 = DT_F64 | (1 << 9) | (1 << 10);   // tall kernel; basis rows are 16-byte aligned
+  // dedicated Gram kernel, or the tall kernel (basis rows are 16-byte aligned)
+  L.a0 = gk ? (1 << 12) : (DT_F64 | (1 << 9) | (1 << 10));
   L.a1 = maxm;
   L.a2 = maxm;
   L.a3 = splits;
   out.push_back(L);
-  if (splits > 1) {
+  if (splits > 1 || gk) {   // (the Gram kernel always writes partials)
     Launch F{Launch::FIN};
     F.off = pg.stg.add(fin);
     F.nz = (int)fin.size();
@@ -1332,8 +1347,8 @@ static void size_partials(Engine& E, const rbcg_ctx* ctx) {
     const int s = proj_splits(maxM, nz, K);
     if (s > 1) need = std::max(need, (size_t)s * maxM * E.maxm);
   }
-  const int sg = proj_splits(E.maxm, nz, K);
-  if (sg > 1) need = std::max(need, (size_t)sg * E.maxm * E.maxm);
+  const int sg = gram_kernel(E) ? gram_splits(nz, K) : proj_splits(E.maxm, nz, K);
+  need = std::max(need, (size_t)sg * E.maxm * E.maxm);
   for (auto& pr : E.P) pr.part_elems = need;
   for (auto& G : E.Gs) {
     const int d = (int)G.op->d;

@@ -146,6 +146,10 @@ struct CvtDesc {
 // 1 = transposed (row c); xsplit: X rows hold BF16 hi/lo pairs.
 hipError_t launch_gemm_nt_ex(int dtype, int out_t, bool xsplit, const NtDesc* d_desc, int nz, int maxM,
                              int maxN, int splits, const int32_t* active, hipStream_t st);
+// Gram matrix W^T W of one block per descriptor (P = the block, M = N = m <= 80, K = d), split
+// over k into part (splits x m x m, FIN_T2R order).
+bool gram_supported(int m);
+hipError_t launch_gram(const NtDesc* d_desc, int nz, int maxm, int splits, const int32_t* active, hipStream_t st);
 hipError_t launch_finish(const FinDesc* d_desc, int nz, int maxM, int maxN, const int32_t* active,
                          hipStream_t st, int lanes_per_output = 1);
 hipError_t launch_gemm_nn_ex(bool p_f32, const NnDesc* d_desc, int nz, int maxMo, int maxN,
