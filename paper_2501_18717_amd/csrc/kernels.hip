@@ -51,16 +51,17 @@ static hipError_t set_big_lds(const void* k) {
 // ---------------------------------------------------------------------------------------------
 // sum over s = first, first + step, ... < splits of p[s * stride], in that order; the loads of
 // four splits are issued together.
-__device__ __forceinline__ double split_sum(gmem_t<const double> p, int64_t stride, int splits, int first = 0,
+template <typename T>
+__device__ __forceinline__ double split_sum(gmem_t<const T> p, int64_t stride, int splits, int first = 0,
                                             int step = 1) {
   double v = 0.0;
   int s = first;
   for (; s + 3 * step < splits; s += 4 * step) {
-    const double a = p[(int64_t)s * stride], b = p[(int64_t)(s + step) * stride];
-    const double c = p[(int64_t)(s + 2 * step) * stride], d = p[(int64_t)(s + 3 * step) * stride];
+    const double a = (double)p[(int64_t)s * stride], b = (double)p[(int64_t)(s + step) * stride];
+    const double c = (double)p[(int64_t)(s + 2 * step) * stride], d = (double)p[(int64_t)(s + 3 * step) * stride];
     v = (((v + a) + b) + c) + d;
   }
-  for (; s < splits; s += step) v += p[(int64_t)s * stride];
+  for (; s < splits; s += step) v += (double)p[(int64_t)s * stride];
   return v;
 }
 
@@ -95,7 +96,8 @@ __global__ __launch_bounds__(256) void k_finish(const FinDesc* __restrict__ desc
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
     const int o = (int)(e / cols), in = (int)(e % cols);
-    double v = split_sum(gmem(f.part) + e, total, f.splits) * f.alpha;
+    double v = (f.part_f32 ? split_sum(gmem((const float*)f.part) + e, total, f.splits)
+                           : split_sum(gmem(f.part) + e, total, f.splits)) * f.alpha;
     if (rowmajor) {
       gmem(f.out)[(int64_t)o * f.ldo + in] = v;
     } else if (f.mode == FIN_TRANS) {

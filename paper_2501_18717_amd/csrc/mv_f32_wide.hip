@@ -9,7 +9,9 @@
 // this chunk computes) and each lane streams 32 consecutive values of its own row of P straight
 // into registers.  Inside a chunk the k index is relabelled identically for both operands: lane
 // half h (lane / 32) takes the run kc + 32 h + [0, 32), and MFMA step s pairs the two halves'
-// values s.  D rows = c (X side), D columns = i (P side), so stores run along i.
+// values s.  D rows = c (X side), D columns = i (P side), so stores run along i.  Split-K
+// partials are stored as FP32, the precision they were accumulated in (half the bytes of FP64;
+// the reduction converts each exactly before adding in FP64).
 #include "device_common.inc"
 
 namespace rbcg {
@@ -149,16 +151,15 @@ __global__ __launch_bounds__(64 * W) void k_mv_wide(const NtDesc* __restrict__ d
     for (int r = 0; r < 16; ++r) {
       const int c = 32 * t + 8 * (r >> 2) + 4 * h + (r & 3);
       if (!iv || c >= N) continue;
-      const double v = (double)a[r];
-      if (splits > 1) gmem(d.part)[((int64_t)s * N + c) * d.M + i] = v;
-      else store_out(d, d.out_t, i, c, v);
+      if (splits > 1) gmem((float*)d.part)[((int64_t)s * N + c) * d.M + i] = a[r];   // FP32 partials
+      else store_out(d, d.out_t, i, c, (double)a[r]);
     }
   });
   if constexpr (NE) {
     const float tot = ex + __shfl_xor(ex, 32);
     const int c = 32 * T2;
     if (h == 0 && iv && c < N) {
-      if (splits > 1) gmem(d.part)[((int64_t)s * N + c) * d.M + i] = (double)tot;
+      if (splits > 1) gmem((float*)d.part)[((int64_t)s * N + c) * d.M + i] = tot;
       else store_out(d, d.out_t, i, c, (double)tot);
     }
   }

@@ -986,6 +986,7 @@ static void add_matvec(Program& pg, std::vector<Launch>& out, Engine& E, int j) 
         f.O = Wb;
         f.alpha = 1.0;
         f.active = act_idx;
+        f.part_f32 = wide ? 1 : 0;   // the 32x32x2 kernel stores FP32 partials
         Launch F{Launch::FIN};
         F.off = pg.stg.add(std::vector<FinDesc>{f});
         F.nz = 1;

@@ -29,7 +29,8 @@ struct NtDesc {
   RowOp P;
   RowOp X;
   int32_t M, N, K, active;   // active: index into the active-flag array, -1 = always
-  double* part;              // split-K partials (when splits > 1), in output orientation
+  double* part;              // split-K partials (when splits > 1), in output orientation; the FP32
+                             // 32x32x2 product stores them as FP32 (its accumulators' precision)
   RowOp O;                   // direct transposed output: row c, element i (when out == null)
   double* out;               // direct row-major output out[i * ldo + c]
   int64_t ldo;
@@ -54,7 +55,8 @@ struct FinDesc {
   RowOp xin;              // FIN_RESID: current iterates
   const double* mu;       // FIN_RESID: shift of each row c
   double alpha;
-  int32_t active, pad_;
+  int32_t active;
+  int32_t part_f32;       // partials stored as FP32 (the FP32 32x32x2 product's accumulators)
   double beta;            // FIN_AXPBY
 };
 
