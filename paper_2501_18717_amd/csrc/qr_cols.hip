@@ -1,5 +1,5 @@
-// Pivoted Cholesky QR factor of a small Gram matrix, one lane per column, for the block
-// widths m = k + 1 with k a power of two (9, 17, 33, 65, 129), compiled for that exact m.
+// Pivoted Cholesky QR factor of a small Gram matrix for the block widths m = k + 1 with k a
+// power of two (9, 17, 33, 65, 129), compiled for that exact m.
 //
 // Contract (QrDesc): G = W^T W (m x m).  Outputs Mout (Q = W Mout), Bout (W = Q Bout, times
 // prevB when given), the deflation mask per pivot position and the rank.  Pivot rule: the
@@ -7,10 +7,11 @@
 // revealing); a column is deflated when that ratio falls below tau, when its remaining norm is
 // below sqrt(eta2) of its pre-projection norm, or when its Schur pivot is below floor2.
 //
-// The factorization runs in a 2D block-cyclic register layout (one wave for m <= 72, four
-// waves for m = 129), the pivot column published through double-buffered LDS; the triangular
-// inverse and the outputs run one lane per column.  With m fixed at compile time every loop
-// over rows is unrolled.
+// The factorization runs in a 2D block-cyclic register layout (one wave for m <= 33, four
+// waves for m = 65 and 129), the pivot column published through double-buffered LDS.  The
+// common case is an unpivoted attempt that carries the inverse factor along (k_qr_np); the
+// pivoted redo forms the triangular inverse and the outputs one lane per column.  With m fixed
+// at compile time every loop over rows is unrolled.
 #include "device_common.inc"
 
 
