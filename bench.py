@@ -407,7 +407,8 @@ def run_ridge(args):
 def run_sqrt(args):
     """Gaussian sampling A^(1/2) B: RBF kernel on 16384 points in [0,1]^3 (length scale 0.1, nugget
     1e-6), 256 samples in groups of 32, 32 quadrature nodes, t = 64 block products.  One step = all
-    256 samples, with FP64 products and with FP32 products."""
+    256 samples, with FP64 products and with FP32 products; then the inverse square root A^(-1/2) B
+    (FP64 products) on the same samples."""
     import torch
 
     import synth
@@ -429,6 +430,11 @@ def run_sqrt(args):
     t64, (rc64, _) = _timed(lambda: rbcg.sqrt_apply(ctx, op, Bd, Y, o64, check=False), args.steps)
     t32, (rc32, _) = _timed(lambda: rbcg.sqrt_apply(ctx, op, Bd, Y, o32, check=False), args.steps)
     log(f"sqrt: fp64 {t64 / args.steps:.3f}s, fp32 {t32 / args.steps:.3f}s per 256 samples")
+    # the inverse square root (whitening) runs the same spaces and rule without the leading A
+    for _ in range(args.warmup):
+        rbcg.invsqrt_apply(ctx, op, Bd, Y, o64, check=False)
+    ti, (rci, _) = _timed(lambda: rbcg.invsqrt_apply(ctx, op, Bd, Y, o64, check=False), args.steps)
+    log(f"inverse sqrt: fp64 {ti / args.steps:.3f}s per 256 samples")
     out = {
         "metric": "solves/s at 1e-8 rel A-norm err: mixed+batched vs plain FP64; HBM/MFMA % peak",
         "value": 256 * args.steps / t64, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
@@ -438,6 +444,8 @@ def run_sqrt(args):
                                "products", "d": 16384, "samples": 256, "nodes": 32, "t": 64},
         "fp32_products": {"value": 256 * args.steps / t32, "unit": "samples/s", "ms_per_step": 1e3 * t32 / args.steps,
                           "status": rc32, "note": "about 6e-3 from the FP64 result (no refinement for sampling)"},
+        "inverse_sqrt": {"value": 256 * args.steps / ti, "unit": "samples/s", "ms_per_step": 1e3 * ti / args.steps,
+                         "status": rci, "note": "A^(-1/2) B, FP64 products, same spaces and rule"},
         "status": rc64,
     }
     print(json.dumps(out), flush=True)

@@ -17,7 +17,9 @@
  *                    eq. ridge_regression; Sec. 3.2, eq. bcg_alg)
  *   rbcg_sqrt_apply  Gaussian sampling A^{1/2} B by the block-Lanczos square
  *                    root with a quadrature over the shifts z^2 (Sec. 1,
- *                    eq. sqrt_rational; Sec. 5, def. blansq)
+ *                    eq. sqrt_rational; Sec. 5, def. blansq); rbcg_invsqrt_apply
+ *                    is the inverse square root A^{-1/2} B (whitening) from the
+ *                    same Lanczos data and rule (Sec. 5.1, def. blanisq)
  *
  * Conventions for every call
  *   - Memory: every matrix or vector argument documented as "device" is a
@@ -175,6 +177,16 @@ int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, const double* o
  * opts.rtol is ignored; exactly opts.t_max products are run. */
 int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t m_s, const double* B, double* Y,
                     const rbcg_opts* opts, rbcg_info* info);
+
+/* Block-Lanczos inverse square root Y ~ A^{-1/2} B (def. blanisq): the same
+ * groups, Krylov spaces, Ritz-value interval and quadrature rule as
+ * rbcg_sqrt_apply, with the leading A dropped from the integrand:
+ * A^{-1/2} = (2/pi) int_0^inf (A + z^2 I)^{-1} dz, so Y = Q_t sum_i w_i
+ * (T_t + s_i I)^{-1} Q_t^T B (t blocks of the basis, where the square root
+ * uses t + 1).  Arguments, layout, ownership and errors as rbcg_sqrt_apply;
+ * RBCG_ERR_NOT_SPD when a shifted block-tridiagonal factorization fails. */
+int rbcg_invsqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t m_s, const double* B, double* Y,
+                       const rbcg_opts* opts, rbcg_info* info);
 
 /* The block product the solvers use (one matrix-load, Sec. 1.2):
  * W = A X for N vectors (rows of X, N x d row-major FP64, device), written to W

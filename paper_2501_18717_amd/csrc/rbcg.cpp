@@ -2546,8 +2546,13 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
 }
 
 // ------------------------------------------------------------------------------- sqrt
-extern "C" int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, const double* B, double* Y,
-                               const rbcg_opts* opts, rbcg_info* info) {
+// Shared by the square root (def. blansq) and the inverse square root (def. blanisq): both
+// weight the same shifted block-tridiagonal solves Y_i = (T_t + s_i I)^{-1} E_1 R_0 by the same
+// rule.  The square root then applies A through the Lanczos relation (the extended block
+// tridiagonal, one more basis block); the inverse square root maps the weighted sum back
+// with Q_t alone.
+static int sqrt_driver(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, const double* B, double* Y,
+                       const rbcg_opts* opts, rbcg_info* info, bool inverse) {
   if (!ctx || !op || !B || !Y || !opts || !info || ms < 1 || !valid_opts(opts)) return RBCG_ERR_INVALID_ARG;
   if (!op_supports(op, opts->matvec)) return RBCG_ERR_UNSUPPORTED;
   if (op->device != ctx->device) return RBCG_ERR_INVALID_ARG;
@@ -2788,13 +2793,13 @@ extern "C" int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, con
       tms.push_back(tm);
       NnDesc nn{};
       nn.P = E.P[g].rows(0);
-      nn.C = Cq + (size_t)g * (T + 1) * mm;
+      nn.C = inverse ? Ybar + (size_t)g * T * mm : Cq + (size_t)g * (T + 1) * mm;
       nn.ldc = m;
       nn.Y = plain_rows(Y + (int64_t)g * m * d, d);
       nn.O = plain_rows(Y + (int64_t)g * m * d, d);
       nn.alpha = 1.0;
       nn.beta = 0.0;
-      nn.Ka = (t + 1) * m;
+      nn.Ka = (inverse ? t : t + 1) * m;
       nn.Mo = (int)std::min<int64_t>(m, ms - (int64_t)g * m);
       nn.N = d;
       nn.active = -1;
@@ -2811,7 +2816,7 @@ extern "C" int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, con
     HIP_TRY(tri_forward_any(dptr<TriDesc>(dscr, o1), ngroups * nq, m, m, 0, t, st));
     HIP_TRY(launch_tri_backward(dptr<TriDesc>(dscr, o1), ngroups * nq, m, m, t, nullptr, st));
     HIP_TRY(launch_wsum(dptr<WsumDesc>(dscr, o2), ngroups, (int64_t)t * m * m, nullptr, st));
-    HIP_TRY(launch_tmul(dptr<TmulDesc>(dscr, o3), ngroups, (int64_t)(t + 1) * m * m, nullptr, st));
+    if (!inverse) HIP_TRY(launch_tmul(dptr<TmulDesc>(dscr, o3), ngroups, (int64_t)(t + 1) * m * m, nullptr, st));
     HIP_TRY(launch_gemm_nn_ex(false, dptr<NnDesc>(dscr, o4), ngroups, m, d, nullptr, st));
     std::vector<int32_t> fh((size_t)ngroups * nq);
     HIP_TRY(hipMemcpyAsync(fh.data(), failN, fh.size() * 4, hipMemcpyDeviceToHost, st));
@@ -2837,6 +2842,16 @@ extern "C" int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, con
     }
     return ret;
   }
+}
+
+extern "C" int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, const double* B, double* Y,
+                               const rbcg_opts* opts, rbcg_info* info) {
+  return sqrt_driver(ctx, op, ms, B, Y, opts, info, false);
+}
+
+extern "C" int rbcg_invsqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, const double* B, double* Y,
+                                  const rbcg_opts* opts, rbcg_info* info) {
+  return sqrt_driver(ctx, op, ms, B, Y, opts, info, true);
 }
 
 // Host-only: the quadrature rule used by rbcg_sqrt_apply (exported for testing without a GPU).

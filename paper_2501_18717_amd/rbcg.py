@@ -66,6 +66,7 @@ _solve = _sig("rbcg_solve", ctypes.c_int, [_vp, _i64, ctypes.POINTER(_vp), _dp, 
 _path = _sig("rbcg_path", ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i64, _dp, _vp, ctypes.POINTER(Opts),
                                           ctypes.POINTER(Info)])
 _sqrt = _sig("rbcg_sqrt_apply", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)])
+_invsqrt = _sig("rbcg_invsqrt_apply", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)])
 _ws_bytes = _sig("rbcg_workspace_bytes", _i64, [_vp])
 _op_apply = _sig("rbcg_op_apply", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, ctypes.c_int])
 _sqrt_rule = _sig("rbcg_sqrt_rule", ctypes.c_int, [ctypes.c_double, ctypes.c_double, _i32, _dp, _dp])
@@ -286,15 +287,24 @@ def path(ctx: Context, op, b, omega, mus: Sequence[float], X, options: Opts, che
     return rc, infos
 
 
-def sqrt_apply(ctx: Context, op, B, Y, options: Opts, check: bool = True):
-    """rbcg_sqrt_apply: Y (m_s x d) ~ rows of A^(1/2) B^T, written in place."""
+def _sqrt_call(fn, name, ctx, op, B, Y, options, check):
     import torch
     ms, d = B.shape
     _need(B, torch.float64, (ms, op.d), "B")
     _need(Y, torch.float64, (ms, op.d), "Y")
     info = (Info * ms)()
-    rc = _sqrt(ctx.handle, op.handle, ms, _ptr(B), _ptr(Y), ctypes.byref(options), info)
+    rc = fn(ctx.handle, op.handle, ms, _ptr(B), _ptr(Y), ctypes.byref(options), info)
     infos = [i.as_dict() for i in info]
     if check and rc != 0:
-        raise RbcgError(rc, "rbcg_sqrt_apply")
+        raise RbcgError(rc, name)
     return rc, infos
+
+
+def sqrt_apply(ctx: Context, op, B, Y, options: Opts, check: bool = True):
+    """rbcg_sqrt_apply: Y (m_s x d) ~ rows of A^(1/2) B^T, written in place."""
+    return _sqrt_call(_sqrt, "rbcg_sqrt_apply", ctx, op, B, Y, options, check)
+
+
+def invsqrt_apply(ctx: Context, op, B, Y, options: Opts, check: bool = True):
+    """rbcg_invsqrt_apply: Y (m_s x d) ~ rows of A^(-1/2) B^T, written in place."""
+    return _sqrt_call(_invsqrt, "rbcg_invsqrt_apply", ctx, op, B, Y, options, check)

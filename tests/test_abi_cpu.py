@@ -76,6 +76,7 @@ def test_null_context_rejected(lib):
     o = rbcg.opts(3)
     assert rbcg._path(None, None, None, None, 0, 1, None, None, ctypes.byref(o), info) == -1
     assert rbcg._sqrt(None, None, 1, None, None, ctypes.byref(o), info) == -1
+    assert rbcg._invsqrt(None, None, 1, None, None, ctypes.byref(o), info) == -1
     assert rbcg._solve(None, 1, None, None, None, None, None, None, None, None) == -1
 
 

@@ -12,7 +12,10 @@ benchmark uses (same library calls, same sizes).
   products are reported, not held to parity: sampling has no residual to
   refine, and FP32 products (the block rounded to FP32, FP32 accumulation)
   carry errors of about 6e-8 ||A|| per product, far above lambda_min ~ 1e-6
-  of this kernel matrix; measured deviation 6e-3, bounded here at 2e-2.
+  of this kernel matrix; measured deviation 6e-3, bounded here at 2e-2.  The
+  inverse square root (FP64 products) of the same samples against the
+  oracle's Q T^{-1/2} Q^T B, to max(1e-8, 1e-13 kappa(T)): T^{-1/2} amplifies
+  the rounding differences of the two Lanczos runs by up to kappa(T).
 """
 import numpy as np
 import pytest
@@ -133,3 +136,17 @@ def test_rbf_sampling_full_first_group(R):
     note(f"RBF: FP64 products vs oracle {r64:.2e}; FP32 products vs oracle {r32:.2e}")
     assert r64 < 1e-8
     assert r32 < 2e-2
+    note("RBF: GPU inverse sqrt (FP64 products)")
+    Yi = torch.zeros_like(Bd)
+    rc, _ = rbcg.invsqrt_apply(ctx, op, Bd, Yi, rbcg.opts(t, nquad=32, group=32))
+    assert rc == 0
+    Yi = Yi[:32].cpu().numpy()
+    note("RBF: oracle inverse square root, group 0")
+    Yio, lz = ob.inv_sqrt_apply_exact(A, B[:32], t)
+    ri = (np.linalg.norm(Yi - Yio, axis=1) / np.linalg.norm(Yio, axis=1)).max()
+    # rounding in the two FP64 Lanczos runs perturbs T by a few ulps of ||T||, which T^{-1/2}
+    # amplifies by up to kappa(T) (about 7e7 here); the quadrature itself is below 1e-10
+    w = np.linalg.eigvalsh(lz["T"])
+    bound = max(1e-8, 1e-13 * w[-1] / w[0])
+    note(f"RBF: inverse sqrt vs oracle {ri:.2e} (kappa(T) {w[-1] / w[0]:.1e}, bound {bound:.1e})")
+    assert ri < bound

@@ -8,7 +8,12 @@ products with FP64 refinement vs the dense ridge solution to 1e-8.  The
 square root is compared with the oracle's closed form A Q T^{-1/2} Q^T B; the
 GPU integrates with a 32-node conformal-map rule on its own Ritz interval,
 whose error is below 1e-10 for these spectra, so the bound is 1e-9 relative
-per sample.
+per sample.  The inverse square root (rbcg_invsqrt_apply) uses the same rule,
+whose relative error per Ritz value is the same for l^{-1/2} as for l^{1/2}
+(the two sums differ by the factor l), and is compared with the oracle's
+Q T^{-1/2} Q^T B to the same bound; its spectra are kept at kappa <= 1e4 so
+that rounding in the two Lanczos runs, which the inverse amplifies at the
+small end of the spectrum, stays well below it.
 """
 import numpy as np
 import pytest
@@ -120,12 +125,13 @@ def test_gram_path_bf16_refined_reaches_fp64_answer(R, ridge_small):
     assert all(inf["precision_used"] == 2 for inf in info)
 
 
-def _sqrt(R, op, B, t, nquad=32, group=32, matvec="f64"):
+def _sqrt(R, op, B, t, nquad=32, group=32, matvec="f64", inverse=False):
     import torch
     rbcg, ctx = R
     Bd = to_dev(B)
     Y = torch.zeros_like(Bd)
-    rc, info = rbcg.sqrt_apply(ctx, op, Bd, Y, rbcg.opts(t, nquad=nquad, group=group, matvec=matvec), check=False)
+    fn = rbcg.invsqrt_apply if inverse else rbcg.sqrt_apply
+    rc, info = fn(ctx, op, Bd, Y, rbcg.opts(t, nquad=nquad, group=group, matvec=matvec), check=False)
     torch.cuda.synchronize()
     return rc, info, Y.cpu().numpy()
 
@@ -186,4 +192,62 @@ def test_sqrt_full_space_equals_eigh(R):
     assert rc == 0, info
     Yt = ot.sqrt_eig(A, B)
     rel = np.linalg.norm(Y - Yt, axis=1) / np.linalg.norm(Yt, axis=1)
+    assert rel.max() < 1e-9, rel.max()
+
+
+def test_invsqrt_matches_oracle_closed_form(R):
+    """Inverse square root (def. blanisq), two groups of 32 samples sharing each
+    pass over A: each group equals the oracle's Q T^{-1/2} Q^T B of its block."""
+    rbcg, ctx = R
+    note("invsqrt rbf d=1024 t=8")
+    P = synth.rbf_problem(4, 1024, 64, ell=0.2, nugget=1e-2)
+    A, B = P["A"], P["B"]
+    op = rbcg.DenseOperator(ctx, to_dev(A))
+    t = 8
+    rc, info, Y = _sqrt(R, op, B, t, inverse=True)
+    assert rc == 0, info
+    for g in range(2):
+        Yo, _ = ob.inv_sqrt_apply_exact(A, B[32 * g:32 * (g + 1)], t)
+        Yg = Y[32 * g:32 * (g + 1)]
+        rel = np.linalg.norm(Yg - Yo, axis=1) / np.linalg.norm(Yo, axis=1)
+        assert rel.max() < 1e-9, rel.max()
+
+
+def test_invsqrt_ragged_last_group(R):
+    """40 samples in groups of 16 (the last group padded to 16, the padding
+    deflates): every group equals the oracle's inverse square root."""
+    rbcg, ctx = R
+    note("invsqrt ragged groups")
+    g = np.random.default_rng(79)
+    d = 200
+    A = synth.spd_from_spectrum(np.linspace(1.0, 50.0, d) ** 2, g)
+    B = g.standard_normal((40, d))
+    op = rbcg.DenseOperator(ctx, to_dev(A))
+    t = 5
+    rc, info, Y = _sqrt(R, op, B, t, group=16, inverse=True)
+    assert rc == 0, info
+    for g0, g1 in [(0, 16), (16, 32), (32, 40)]:
+        Yo, _ = ob.inv_sqrt_apply_exact(A, B[g0:g1], t)
+        rel = np.linalg.norm(Y[g0:g1] - Yo, axis=1) / np.linalg.norm(Yo, axis=1)
+        assert rel.max() < 1e-9, (g0, rel.max())
+
+
+def test_invsqrt_full_space_equals_eigh(R):
+    """m t >= d: the block-Lanczos inverse square root is A^{-1/2} B exactly,
+    and applying the square root to it gives B back."""
+    rbcg, ctx = R
+    note("invsqrt full space")
+    g = np.random.default_rng(80)
+    d = 96
+    A = synth.spd_from_spectrum(np.linspace(1.0, 50.0, d), g)
+    B = g.standard_normal((48, d))
+    op = rbcg.DenseOperator(ctx, to_dev(A))
+    rc, info, Y = _sqrt(R, op, B, 7, group=16, inverse=True)
+    assert rc == 0, info
+    Yt = ot.inv_sqrt_eig(A, B)
+    rel = np.linalg.norm(Y - Yt, axis=1) / np.linalg.norm(Yt, axis=1)
+    assert rel.max() < 1e-9, rel.max()
+    rc, info, Z = _sqrt(R, op, Y, 7, group=16)
+    assert rc == 0, info
+    rel = np.linalg.norm(Z - B, axis=1) / np.linalg.norm(B, axis=1)
     assert rel.max() < 1e-9, rel.max()
