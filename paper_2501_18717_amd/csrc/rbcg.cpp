@@ -119,7 +119,7 @@ extern "C" const char* rbcg_status_string(int s) {
   }
 }
 
-extern "C" int rbcg_version(void) { return 10000; }
+extern "C" int rbcg_version(void) { return 10100; }
 
 extern "C" int rbcg_create(rbcg_ctx** out, void* stream) {
   if (!out) return RBCG_ERR_INVALID_ARG;
