@@ -174,7 +174,9 @@ int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, const double* o
  *   B   device, m_s x d row-major (FP64)
  *   Y   device, m_s x d row-major (FP64), written
  *   info host[m_s]; relres holds -1 (no residual is defined)
- * opts.rtol is ignored; exactly opts.t_max products are run. */
+ * opts.rtol is ignored; exactly opts.t_max products are run.  All groups share
+ * one block product, so ceil(m_s / g) * g <= 256 with g = min(opts.group, m_s),
+ * else RBCG_ERR_UNSUPPORTED before any device work. */
 int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t m_s, const double* B, double* Y,
                     const rbcg_opts* opts, rbcg_info* info);
 

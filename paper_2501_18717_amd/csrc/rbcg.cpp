@@ -2562,10 +2562,9 @@ static int sqrt_driver(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, const doubl
   const int m = (int)std::min<int64_t>(gs, ms);
   if (tri_forward_lds(m, m) > kLdsCap || tri_backward_lds(m, m) > kLdsCap) return RBCG_ERR_INVALID_ARG;
   const int ngroups = (int)((ms + m - 1) / m);
-  if (ngroups * m > 16 * 16 * 4 && ngroups * m > 256) {
-    // block products of all groups are fused into one product with N = ngroups * m <= 256
-    return RBCG_ERR_UNSUPPORTED;
-  }
+  // the block products of all groups are fused into one product of N = ngroups * m vectors,
+  // and the general NT product kernel takes at most 16 column tiles of 16
+  if (ngroups * m > 256) return RBCG_ERR_UNSUPPORTED;
   hipStream_t st = ctx->stream;
   const int d = (int)op->d;
   Engine E;

@@ -238,3 +238,12 @@ def test_invalid_arguments_rejected_before_device_work(R):
     rc, _ = rbcg.solve(ctx, [op], [0.0], [b], [None], [x], [rbcg.opts(2, matvec="f32")], check=False)
     assert rc == -7
     assert float(x.abs().sum()) == 0.0
+    # sampling: all groups share one block product of at most 256 vectors (9 groups of 32 = 288)
+    A64 = to_dev(np.eye(64))
+    op64 = rbcg.DenseOperator(ctx, A64)
+    Bs = to_dev(np.ones((260, 64)))
+    Ys = torch.zeros_like(Bs)
+    for fn in (rbcg.sqrt_apply, rbcg.invsqrt_apply):
+        rc, _ = fn(ctx, op64, Bs, Ys, rbcg.opts(2, group=32), check=False)
+        assert rc == -7
+    assert float(Ys.abs().sum()) == 0.0
