@@ -186,7 +186,10 @@ int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t m_s, const double*
  * A^{-1/2} = (2/pi) int_0^inf (A + z^2 I)^{-1} dz, so Y = Q_t sum_i w_i
  * (T_t + s_i I)^{-1} Q_t^T B (t blocks of the basis, where the square root
  * uses t + 1).  Arguments, layout, ownership and errors as rbcg_sqrt_apply;
- * RBCG_ERR_NOT_SPD when a shifted block-tridiagonal factorization fails. */
+ * RBCG_ERR_NOT_SPD when a shifted block-tridiagonal factorization fails.
+ * A must be positive definite: for a singular A the Ritz values approach 0,
+ * the quadrature interval's lower end falls to rounding level and the result
+ * is not meaningful (the square root has no such restriction). */
 int rbcg_invsqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t m_s, const double* B, double* Y,
                        const rbcg_opts* opts, rbcg_info* info);
 
