@@ -927,16 +927,8 @@ static void add_matvec(Program& pg, std::vector<Launch>& out, Engine& E, int j) 
       continue;
     }
     if (op->kind == RBCG_OP_DENSE) {
-      NtDesc nd{};
-      nd.M = d;
-      nd.N = G.N;
-      nd.K = d;
-      nd.active = act_idx;
-      nd.part = G.part;
-      nd.O = Wb;
-      nd.out = nullptr;
-      nd.out_t = DT_F64;
       int dtype = DT_F64;
+      RowOp Pm = plain_rows(op->data, op->ld), Xm = Xb;
       if (G.mv_t == RBCG_F32) {
         if (!fused_q32(E)) {   // (else the block's last factor application wrote the copy)
           CvtDesc c{};
@@ -954,45 +946,65 @@ static void add_matvec(Program& pg, std::vector<Launch>& out, Engine& E, int j) 
           C.a2 = d;
           out.push_back(C);
         }
-        nd.P = plain_rows(op->lo, op->ld_lo);
-        nd.X = plain_rows(G.xlo, G.ld_xlo);
+        Pm = plain_rows(op->lo, op->ld_lo);
+        Xm = plain_rows(G.xlo, G.ld_xlo);
         dtype = DT_F32;
-      } else {
-        nd.P = plain_rows(op->data, op->ld);
-        nd.X = Xb;
       }
       const int splits = G.splits2;
-      Launch L{Launch::NT};
-      L.off = pg.stg.add(std::vector<NtDesc>{nd});
-      L.nz = 1;
       const bool pvec = dtype == DT_F32 || (op->ld % 2 == 0 && ((uintptr_t)op->data % 16) == 0);
-      int t2 = 0, ne = 0;
-      const bool wide = dtype == DT_F32 && wide_shape(G.N, &t2, &ne);
-      L.a0 = dtype | (1 << 8) | (G.N <= 144 ? (1 << 9) : 0) | (pvec ? (1 << 10) : 0) | (wide ? (1 << 11) : 0);
-      L.a1 = d;
-      L.a2 = G.N;
-      L.a3 = splits;
-      L.prof = true;
-      L.flops = 2.0 * d * (double)d * G.N;
-      L.bytes = (double)d * d * (dtype == DT_F32 ? 4.0 : 8.0);
-      out.push_back(L);
-      if (splits > 1) {
-        FinDesc f{};
-        f.part = G.part;
-        f.M = d;
-        f.N = G.N;
-        f.splits = splits;
-        f.mode = FIN_TRANS;
-        f.O = Wb;
-        f.alpha = 1.0;
-        f.active = act_idx;
-        f.part_f32 = wide ? 1 : 0;   // the 32x32x2 kernel stores FP32 partials
-        Launch F{Launch::FIN};
-        F.off = pg.stg.add(std::vector<FinDesc>{f});
-        F.nz = 1;
-        F.a1 = d;
-        F.a2 = G.N;
-        out.push_back(F);
+      const size_t xsz = dtype == DT_F32 ? sizeof(float) : sizeof(double);
+      // More than 144 vectors (wide sampling groups): equal column chunks of at most 144, each a
+      // tall-kernel launch with its own reduction (one more pass over A per chunk; the general
+      // NT kernel runs such widths at a fraction of the tall kernel's rate).  The chunks reuse
+      // the partial buffer one after another in stream order.
+      const int nch = (G.N + 143) / 144;
+      const int cw = (G.N + nch - 1) / nch;
+      for (int c0 = 0; c0 < G.N; c0 += cw) {
+        const int nc = std::min(cw, G.N - c0);
+        NtDesc nd{};
+        nd.M = d;
+        nd.N = nc;
+        nd.K = d;
+        nd.active = act_idx;
+        nd.part = G.part;
+        nd.P = Pm;
+        nd.X = Xm;
+        nd.X.p = (const unsigned char*)Xm.p + (size_t)c0 * Xm.ld * xsz;
+        nd.O = Wb;
+        nd.O.p = (const double*)Wb.p + (size_t)c0 * Wb.ld;
+        nd.out = nullptr;
+        nd.out_t = DT_F64;
+        Launch L{Launch::NT};
+        L.off = pg.stg.add(std::vector<NtDesc>{nd});
+        L.nz = 1;
+        int t2 = 0, ne = 0;
+        const bool wide = dtype == DT_F32 && wide_shape(nc, &t2, &ne);
+        L.a0 = dtype | (1 << 8) | (1 << 9) | (pvec ? (1 << 10) : 0) | (wide ? (1 << 11) : 0);
+        L.a1 = d;
+        L.a2 = nc;
+        L.a3 = splits;
+        L.prof = true;
+        L.flops = 2.0 * d * (double)d * nc;
+        L.bytes = (double)d * d * (dtype == DT_F32 ? 4.0 : 8.0);
+        out.push_back(L);
+        if (splits > 1) {
+          FinDesc f{};
+          f.part = G.part;
+          f.M = d;
+          f.N = nc;
+          f.splits = splits;
+          f.mode = FIN_TRANS;
+          f.O = nd.O;
+          f.alpha = 1.0;
+          f.active = act_idx;
+          f.part_f32 = wide ? 1 : 0;   // the 32x32x2 kernel stores FP32 partials
+          Launch F{Launch::FIN};
+          F.off = pg.stg.add(std::vector<FinDesc>{f});
+          F.nz = 1;
+          F.a1 = d;
+          F.a2 = nc;
+          out.push_back(F);
+        }
       }
     } else {
       const int n = (int)op->n;
@@ -1360,7 +1372,7 @@ static void size_partials(Engine& E, const rbcg_ctx* ctx) {
       G.splits2 = G.N <= 144 ? nn_splits(d, (int)G.op->n, 1) : 1;
     } else if (G.op->kind == RBCG_OP_DENSE && G.mv_t == RBCG_F32 && wide_shape(G.N, &t2w, &new_)) {
       G.splits2 = wide_splits(d, G.N);
-    } else if (G.op->kind == RBCG_OP_DENSE && G.N <= 144) {
+    } else if (G.op->kind == RBCG_OP_DENSE) {   // tall kernels (wider groups run in column chunks)
       const int t64 = (d + 63) / 64;
       // about 1024 workgroups: finer granularity lets other CUs absorb a CU held by the
       // convergence monitor on the side stream

@@ -40,7 +40,8 @@ def _x(seed, N, d):
     return X
 
 
-@pytest.mark.parametrize("d,N", [(777, 1), (777, 17), (100, 33), (1000, 65), (4500, 65), (1000, 129), (513, 130)])
+@pytest.mark.parametrize("d,N", [(777, 1), (777, 17), (100, 33), (1000, 65), (4500, 65), (1000, 129), (513, 130),
+                                 (513, 145), (700, 200), (1000, 256)])
 def test_dense_block_product(R, d, N):
     import torch
     rbcg, ctx = R
