@@ -167,7 +167,9 @@ int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, const double* o
 /* Block-Lanczos square root Y ~ A^{1/2} B (def. blansq).  The m_s samples
  * (rows of B) are split into groups of opts.group; each group's samples form
  * one Krylov start block (every sample is augmented by the others in its
- * group).  All groups share each pass over A.  The z-integral uses an
+ * group).  All groups share each block product (one pass over A for up to
+ * 144 fused vectors; wider products run as column chunks of at most 144, one
+ * pass each).  The z-integral uses an
  * opts.nquad-node conformal-map rule on the Ritz-value interval of each
  * group's T_t, evaluated exactly through the Lanczos relation
  * A Q_t = Q_t T_t + Q_{t+1} B_t E_t^T.
