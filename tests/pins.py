@@ -92,3 +92,22 @@ def quadrature_gap(m=1e-6, M=244.0, N=32):
     s, w = oq.sqrt_rule(m, M, N)
     lam = np.logspace(np.log10(m), np.log10(M), 301)
     return float(np.max(np.abs(oq.apply_rule_scalar(lam, s, w) - np.sqrt(lam)) / np.sqrt(lam)))
+
+
+def inv_sqrt_identity_gaps(d=60, m=8, ts=(1, 2, 3), seed=21):
+    """Sec. 5.1 after def. blanisq: bisq_t = A^-1 bsq_t at every t, hence
+    ||A^-1/2 B - bisq_t|| <= ||A^-1|| ||A^1/2 B - bsq_t||.  Returns the largest
+    relative identity gap ||bisq_t A - bsq_t|| / ||bsq_t|| and the largest ratio of
+    the error to its bound, over t (m t < d, so no iterate is exact)."""
+    from oracle import truth as ot
+    A, lam = small_spd(d, p=1.0, seed=seed)
+    B = np.random.default_rng(seed + 1).standard_normal((m, d))
+    gap = ratio = 0.0
+    for t in ts:
+        Ys, _ = ob.sqrt_apply_exact(A, B, t)
+        Yi, _ = ob.inv_sqrt_apply_exact(A, B, t)
+        gap = max(gap, np.linalg.norm(Yi @ A - Ys) / np.linalg.norm(Ys))
+        err_i = np.linalg.norm(ot.inv_sqrt_eig(A, B) - Yi)
+        err_s = np.linalg.norm(ot.sqrt_eig(A, B) - Ys)
+        ratio = max(ratio, err_i / ((1.0 / lam.min()) * err_s))
+    return gap, ratio

@@ -110,3 +110,21 @@ def test_pins_reject_quadrature_off_by_half_node(monkeypatch):
         return s, w
     monkeypatch.setattr(oq, "sqrt_rule", wrong)
     assert pins.quadrature_gap() > 1e-6
+
+
+def _inv_sqrt_keeps_leading_A(A, Bs, t, eta=ob.ETA):
+    return ob.sqrt_apply_exact(A, Bs, t, eta=eta)
+
+
+def _inv_sqrt_positive_power(A, Bs, t, eta=ob.ETA):
+    Bs = np.atleast_2d(np.asarray(Bs, dtype=np.float64))
+    lz = ob.block_lanczos(A, Bs.T, t, eta=eta, first_fixed=False)
+    w, V = np.linalg.eigh(lz["T"])
+    return (lz["Q"] @ ((V * np.sqrt(w)) @ V.T) @ (lz["Q"].T @ Bs.T)).T, lz
+
+
+@pytest.mark.parametrize("bad", [_inv_sqrt_keeps_leading_A, _inv_sqrt_positive_power])
+def test_pins_reject_bad_inverse_square_root(monkeypatch, bad):
+    monkeypatch.setattr(ob, "inv_sqrt_apply_exact", bad)
+    gap, ratio = pins.inv_sqrt_identity_gaps()
+    assert gap > 1e-6 or ratio > 1.0 + 1e-10

@@ -9,7 +9,7 @@ from oracle import krylov as ok
 from oracle import quadrature as oq
 from oracle import truth as ot
 
-from pins import (small_spd, definition_gap, exact_termination_gap, cg_gap, path_gap,
+from pins import (small_spd, inv_sqrt_identity_gaps, definition_gap, exact_termination_gap, cg_gap, path_gap,
                   sqrt_full_space_gap, quadrature_gap)
 
 
@@ -207,6 +207,14 @@ def test_inv_sqrt_full_space_exact():
     Y, _ = ob.inv_sqrt_apply_exact(A, B, 5)
     Yt = ot.inv_sqrt_eig(A, B)
     assert np.max(np.linalg.norm(Y - Yt, axis=1) / np.linalg.norm(Yt, axis=1)) < 1e-9
+
+
+def test_inv_sqrt_is_A_inverse_of_sqrt_iterate():
+    """Sec. 5.1 after def. blanisq: bisq_t = A^-1 bsq_t at every t (here m t < d)
+    and the error bound that follows from it."""
+    gap, ratio = inv_sqrt_identity_gaps()
+    assert gap <= 1e-12
+    assert ratio <= 1.0 + 1e-10
 
 
 def test_sqrt_quadrature_matches_closed_form():
