@@ -251,3 +251,24 @@ def test_invsqrt_full_space_equals_eigh(R):
     assert rc == 0, info
     rel = np.linalg.norm(Z - B, axis=1) / np.linalg.norm(B, axis=1)
     assert rel.max() < 1e-9, rel.max()
+
+
+def test_sqrt_and_invsqrt_chunked_product(R):
+    """160 samples in 5 groups of 32: the fused block product of 160 vectors runs
+    as two column chunks of 80; every group of both the square root and the
+    inverse square root equals the oracle's closed form of its own block."""
+    rbcg, ctx = R
+    note("sqrt + invsqrt, 160 fused vectors (two chunks)")
+    g = np.random.default_rng(81)
+    d = 600
+    A = synth.spd_from_spectrum(np.linspace(1.0, 50.0, d), g)
+    B = g.standard_normal((160, d))
+    op = rbcg.DenseOperator(ctx, to_dev(A))
+    t = 4
+    for inverse, ref in ((False, ob.sqrt_apply_exact), (True, ob.inv_sqrt_apply_exact)):
+        rc, info, Y = _sqrt(R, op, B, t, inverse=inverse)
+        assert rc == 0, info
+        for g0 in range(0, 160, 32):
+            Yo, _ = ref(A, B[g0:g0 + 32], t)
+            rel = np.linalg.norm(Y[g0:g0 + 32] - Yo, axis=1) / np.linalg.norm(Yo, axis=1)
+            assert rel.max() < 1e-9, (inverse, g0, rel.max())
