@@ -190,7 +190,7 @@ def bcg(A, mus, b, Omega, t, eta=ETA):
 def bcg_residual_estimate(lz, mu, bnorm):
     """Norm of the residual b - A_mu x_t of the iterate, from the Lanczos
     relation A Q_t = Q_t T_t + Q_{t+1} B_t E_t^T:  || B_t y_last ||, where
-    y = (T_t + mu I)^-1 ||b|| e_1 and y_last is its last block (Sec. 3.3
+    y = (T_t + mu I)^-1 ||b|| e_1 and y_last is its last block (Sec. 4
     remark on a-posteriori residuals)."""
     n = lz["T"].shape[0]
     e1 = np.zeros(n)

@@ -9,7 +9,7 @@ Passages followed:
   * deflation preconditioner and its inverse      Sec. 2.2, eq. precond_def
   * block-Krylov Nystrom approximation A<K_s>     Sec. 2.2.2, eq. nystromBKI_def
   * theta = smallest eigenvalue of the Nystrom
-    approximation, same Omega as block-CG          Sec. 6 (experiment set-up)
+    approximation, same Omega as block-CG          Sec. 7 (numerical experiments)
 """
 from __future__ import annotations
 

@@ -111,3 +111,93 @@ def inv_sqrt_identity_gaps(d=60, m=8, ts=(1, 2, 3), seed=21):
         err_s = np.linalg.norm(ot.sqrt_eig(A, B) - Ys)
         ratio = max(ratio, err_i / ((1.0 / lam.min()) * err_s))
     return gap, ratio
+
+
+def _z_integral(H, R, lead=None):
+    """(2/pi) int_0^inf lead (H + z^2 I)^-1 R dz by adaptive quadrature in
+    phi = arctan z (dz = (1 + z^2) dphi, finite integrand on [0, pi/2]).
+    This is the integral that defines the block-Lanczos square root and its
+    inverse (def. blansq, def. blanisq), evaluated numerically rather than
+    through a matrix power."""
+    from scipy.integrate import quad_vec
+    n = H.shape[0]
+    eye = np.eye(n)
+
+    def f(phi):
+        z2 = np.tan(phi) ** 2
+        Y = np.linalg.solve(H + z2 * eye, R) * (1.0 + z2)
+        return Y if lead is None else lead @ Y
+    val, _ = quad_vec(f, 0.0, np.pi / 2, epsabs=1e-14, epsrel=1e-12, limit=400)
+    return (2.0 / np.pi) * val
+
+
+def sampling_definition_gaps(d=60, m=4, ts=(1, 2, 3, 5), seed=31):
+    """Sampling iterates outside the full space (m t < d) against their
+    definition.  For the samples B (m x d), every shifted block-CG iterate
+    bcg_t(z^2) of def. blansq is the Galerkin solution over K_t(A, B^T)
+    (def. BCG with the other samples as augmentation), i.e.
+    V (V^T A V + z^2 I)^-1 V^T b_i for any orthonormal basis V of that space.
+    Here V comes from the explicit blocks [B, AB, ..., A^(t-1) B] (no
+    block-Lanczos) and the z-integral is done by adaptive quadrature (no
+    matrix square root).  Returns the largest relative gaps (square root,
+    inverse square root) over t and samples."""
+    A, _ = small_spd(d, p=1.0, seed=seed)
+    B = np.random.default_rng(seed + 1).standard_normal((m, d))
+    gs = gi = 0.0
+    for t in ts:
+        assert m * t < d
+        V = ob.krylov_basis_explicit(lambda X: A @ X, B.T, t)
+        H = V.T @ A @ V
+        H = 0.5 * (H + H.T)
+        R = V.T @ B.T
+        Ys_def = _z_integral(H, R, lead=A @ V).T
+        Yi_def = (V @ _z_integral(H, R)).T
+        Ys, _ = ob.sqrt_apply_exact(A, B, t)
+        Yi, _ = ob.inv_sqrt_apply_exact(A, B, t)
+        gs = max(gs, float(np.max(np.linalg.norm(Ys - Ys_def, axis=1) / np.linalg.norm(Ys_def, axis=1))))
+        gi = max(gi, float(np.max(np.linalg.norm(Yi - Yi_def, axis=1) / np.linalg.norm(Yi_def, axis=1))))
+    return gs, gi
+
+
+def pcg_textbook(A, mu, b, Pinv, t):
+    """Textbook preconditioned conjugate gradients for A_mu x = b with the
+    SPD preconditioner inverse Pinv, from x_0 = 0, t steps.  In exact
+    arithmetic its t-th iterate minimises the A_mu-norm error over
+    K_t(P^-1 A_mu, P^-1 b), i.e. it is pcg_t of def. PCG (Sec. 2.1)."""
+    x = np.zeros_like(b, dtype=np.float64)
+    r = np.array(b, dtype=np.float64, copy=True)
+    z = Pinv @ r
+    p = z.copy()
+    rz = r @ z
+    for _ in range(t):
+        Ap = A @ p + mu * p
+        alpha = rz / (p @ Ap)
+        x = x + alpha * p
+        r = r - alpha * Ap
+        z = Pinv @ r
+        rz_new = r @ z
+        if rz_new <= 0.0:
+            break
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x
+
+
+def pcg_gap(d=120, ell=6, s=2, t_max=8, seed=41):
+    """pcg_definition (Galerkin over an explicit basis of the preconditioned
+    Krylov space) against the textbook PCG recurrence at every t, with the
+    Nystrom deflation preconditioner of eq. precond_def built from a Gaussian
+    Omega (theta = the smallest Nystrom eigenvalue) and for two shifts."""
+    A, _ = small_spd(d, p=2.0, seed=seed)
+    g = np.random.default_rng(seed + 1)
+    b = g.standard_normal(d)
+    Om = g.standard_normal((ell, d))
+    U, D = ok.nystrom(A, Om, s)
+    worst = 0.0
+    for mu in (1e-3, 1e-1):
+        Pinv = ok.deflation_pinv(U, D, D.min(), mu)
+        for t in range(1, t_max + 1):
+            x_def = ok.pcg_definition(A, mu, b, Pinv, t)
+            x_rec = pcg_textbook(A, mu, b, Pinv, t)
+            worst = max(worst, ob.rel_a_err(A, mu, x_def, x_rec))
+    return worst

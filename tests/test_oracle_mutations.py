@@ -128,3 +128,64 @@ def test_pins_reject_bad_inverse_square_root(monkeypatch, bad):
     monkeypatch.setattr(ob, "inv_sqrt_apply_exact", bad)
     gap, ratio = pins.inv_sqrt_identity_gaps()
     assert gap > 1e-6 or ratio > 1.0 + 1e-10
+
+
+def test_pins_reject_sampling_start_basis_not_spanning_B(monkeypatch):
+    """A start basis that does not span the samples (one sample replaced by a
+    random vector) changes the sampling iterates outside the full space; the
+    definition pin over an explicit Krylov basis must catch it."""
+    orig = ob.block_lanczos
+
+    def wrong(A, B, t, eta=ob.ETA, first_fixed=True):
+        B = np.array(B, copy=True)
+        if not first_fixed and B.shape[1] > 1:
+            B[:, -1] = np.random.default_rng(0).standard_normal(B.shape[0])
+        return orig(A, B, t, eta=eta, first_fixed=first_fixed)
+    monkeypatch.setattr(ob, "block_lanczos", wrong)
+    gs, gi = pins.sampling_definition_gaps()
+    assert gs > 1e-6 and gi > 1e-6
+
+
+def test_pins_reject_sampling_basis_one_block_short(monkeypatch):
+    """Dropping the last Krylov block (t - 1 products) is an index mistake
+    that the full-space pin cannot see once m (t - 1) >= d; the definition
+    pin at m t < d must."""
+    orig = ob.block_lanczos
+
+    def short(A, B, t, eta=ob.ETA, first_fixed=True):
+        return orig(A, B, max(1, t - 1), eta=eta, first_fixed=first_fixed)
+    monkeypatch.setattr(ob, "block_lanczos", short)
+    gs, gi = pins.sampling_definition_gaps(ts=(2, 3, 5))
+    assert gs > 1e-6 and gi > 1e-6
+
+
+def _pcg_unpreconditioned(A, mu, b, Pinv, t):
+    # the preconditioner forgotten: the Krylov space of A_mu itself
+    from oracle import krylov as ok
+    return ok.cg_definition(A, mu, b, t)
+
+
+def _pcg_wrong_start(A, mu, b, Pinv, t):
+    # K_t(P^-1 A_mu, b) instead of K_t(P^-1 A_mu, P^-1 b)
+    from oracle import krylov as ok
+    apply_A = ob.as_operator(A)
+    M = lambda v: Pinv @ (apply_A(v[:, None])[:, 0] + mu * v)
+    V = ok.krylov_basis_reorth(M, b, t)
+    return ob.galerkin(apply_A, mu, V, b)
+
+
+def _pcg_preconditioner_not_inverted(A, mu, b, Pinv, t):
+    # P applied where P^-1 belongs
+    from oracle import krylov as ok
+    apply_A = ob.as_operator(A)
+    P = np.linalg.inv(Pinv)
+    M = lambda v: P @ (apply_A(v[:, None])[:, 0] + mu * v)
+    V = ok.krylov_basis_reorth(M, P @ b, t)
+    return ob.galerkin(apply_A, mu, V, b)
+
+
+@pytest.mark.parametrize("bad", [_pcg_unpreconditioned, _pcg_wrong_start, _pcg_preconditioner_not_inverted])
+def test_pins_reject_bad_pcg_definition(monkeypatch, bad):
+    from oracle import krylov as ok
+    monkeypatch.setattr(ok, "pcg_definition", bad)
+    assert pins.pcg_gap() > 1e-6

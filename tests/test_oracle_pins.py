@@ -10,7 +10,7 @@ from oracle import quadrature as oq
 from oracle import truth as ot
 
 from pins import (small_spd, inv_sqrt_identity_gaps, definition_gap, exact_termination_gap, cg_gap, path_gap,
-                  sqrt_full_space_gap, quadrature_gap)
+                  sqrt_full_space_gap, quadrature_gap, sampling_definition_gaps, pcg_gap)
 
 
 # --------------------------------------------------------------- def. BCG / eq. bcg_alg
@@ -43,6 +43,13 @@ def test_cg_definition_matches_recurrence():
         x1 = ok.cg_definition(A, 1e-2, b, t)
         x2 = ok.cg_hestenes_stiefel(A, 1e-2, b, t)
         assert ob.rel_a_err(A, 1e-2, x1, x2) < 1e-10
+
+
+def test_pcg_definition_matches_textbook_recurrence():
+    """def. PCG (optimality over K_t(P^-1 A_mu, P^-1 b)) equals the textbook
+    preconditioned CG recurrence for the Nystrom deflation preconditioner
+    (eq. precond_def) at every t."""
+    assert pcg_gap() < 1e-9
 
 
 # ------------------------------------------------------------------- C1-shaped problem
@@ -215,6 +222,14 @@ def test_inv_sqrt_is_A_inverse_of_sqrt_iterate():
     gap, ratio = inv_sqrt_identity_gaps()
     assert gap <= 1e-12
     assert ratio <= 1.0 + 1e-10
+
+
+def test_sampling_iterates_match_definition_outside_full_space():
+    """m t < d: the square-root and inverse-square-root iterates equal the
+    z-integral of the shifted block-CG iterates (def. blansq, def. blanisq)
+    over an explicit basis of K_t(A, B), integrated numerically."""
+    gs, gi = sampling_definition_gaps()
+    assert gs < 1e-10 and gi < 1e-10
 
 
 def test_sqrt_quadrature_matches_closed_form():
