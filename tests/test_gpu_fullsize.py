@@ -8,14 +8,20 @@ benchmark uses (same library calls, same sizes).
   of its triangular factor); the plain FP64 path at t = 32 (exact termination,
   32 * 129 >= 4096) against the same truth.
 * RBF sampling on 16384 points, 256 samples in 8 groups of 32, 32 nodes: FP64
-  block products against the oracle's closed form (parity, 1e-8).  FP32 block
-  products are reported, not held to parity: sampling has no residual to
-  refine, and FP32 products (the block rounded to FP32, FP32 accumulation)
-  carry errors of about 6e-8 ||A|| per product, far above lambda_min ~ 1e-6
-  of this kernel matrix; measured deviation 6e-3, bounded here at 2e-2.  The
-  inverse square root (FP64 products) of the same samples against the
-  oracle's Q T^{-1/2} Q^T B, to max(1e-8, 1e-13 kappa(T)): T^{-1/2} amplifies
-  the rounding differences of the two Lanczos runs by up to kappa(T).
+  block products against the oracle's closed form (parity, 1e-8), for group 0
+  (first 128-vector column chunk of the fused product) and group 5 (second
+  chunk).  FP32 block products do not meet 1e-8 against the FP64 oracle and
+  are reported, not asserted: sampling has no residual to refine, and for
+  vectors along the small eigenvectors of this kernel matrix the product sums
+  cancel by about ||A|| / lambda_min = 2.4e8, so FP32 accumulation (unit
+  roundoff 6e-8) leaves no correct digit in those directions (measured 6e-3;
+  the oracle run on the same FP32-rounded operands with exact accumulation
+  lands just as far from both).  The FP32 kernel path is pinned instead on a
+  well-conditioned kernel matrix (test_gpu_path_sqrt.py).
+  The inverse square root
+  (FP64 products) of the same samples against the oracle's Q T^{-1/2} Q^T B,
+  to max(1e-8, 1e-13 kappa(T)): T^{-1/2} amplifies the rounding differences
+  of the two Lanczos runs by up to kappa(T).
 """
 import numpy as np
 import pytest
@@ -109,7 +115,7 @@ def test_ridge_path_full_bf16_refined(R):
     assert worst64 < 1e-10
 
 
-def test_rbf_sampling_full_first_group(R):
+def test_rbf_sampling_full_two_chunks(R):
     import torch
     rbcg, ctx = R
     note("full RBF sampling d=16384: generating")
@@ -128,14 +134,22 @@ def test_rbf_sampling_full_first_group(R):
     Y64 = torch.zeros_like(Bd)
     rc, _ = rbcg.sqrt_apply(ctx, op, Bd, Y64, rbcg.opts(t, nquad=32, group=32))
     assert rc == 0
-    Y6 = Y64[:32].cpu().numpy()
-    note("RBF: oracle closed form, group 0")
-    Yo, _ = ob.sqrt_apply_exact(A, B[:32], t)
-    r64 = (np.linalg.norm(Y6 - Yo, axis=1) / np.linalg.norm(Yo, axis=1)).max()
-    r32 = (np.linalg.norm(Yg - Yo, axis=1) / np.linalg.norm(Yo, axis=1)).max()
-    note(f"RBF: FP64 products vs oracle {r64:.2e}; FP32 products vs oracle {r32:.2e}")
-    assert r64 < 1e-8
-    assert r32 < 2e-2
+    Y64h = Y64.cpu().numpy()
+
+    def rel(Ya, Yb):
+        return float((np.linalg.norm(Ya - Yb, axis=1) / np.linalg.norm(Yb, axis=1)).max())
+
+    for grp in (0, 5):
+        note(f"RBF: oracle closed form, group {grp}")
+        Yo, _ = ob.sqrt_apply_exact(A, B[32 * grp:32 * grp + 32], t)
+        r64 = rel(Y64h[32 * grp:32 * grp + 32], Yo)
+        note(f"RBF: group {grp} (column chunk {grp // 4}), FP64 products vs oracle {r64:.2e}")
+        assert r64 < 1e-8
+        if grp == 0:
+            Yo0 = Yo
+    r32 = rel(Yg, Yo0)
+    note(f"RBF: FP32 products vs FP64 oracle {r32:.2e} (reported, not parity: see the module docstring)")
+    assert np.isfinite(Yg).all()
     note("RBF: GPU inverse sqrt (FP64 products)")
     Yi = torch.zeros_like(Bd)
     rc, _ = rbcg.invsqrt_apply(ctx, op, Bd, Yi, rbcg.opts(t, nquad=32, group=32))

@@ -159,6 +159,57 @@ def test_sqrt_matches_oracle_closed_form(R, rbf_small):
         assert rel.max() < 1e-9, rel.max()
 
 
+def test_sqrt_fp32_products_pinned_on_rounded_operands(R):
+    """FP32 block products (A and each block rounded to FP32, FP32 MFMA
+    accumulation) against the oracle run on the same rounded operands with
+    exact accumulation.  What separates the two is the kernel's FP32
+    accumulation; its size on this operator is measured through
+    rbcg_op_apply (largest column-relative error eps of one block product),
+    and the bound is four times the change the oracle shows when each of its
+    products is perturbed by eps.  RBF kernel matrix on 2000 points (ragged
+    last tile) with a 1e-2 nugget, kappa ~ 3e3; two groups of 32."""
+    import torch
+    rbcg, ctx = R
+    P = synth.rbf_problem(6, 2000, 64, ell=0.1, nugget=1e-2)
+    A, B = P["A"], P["B"]
+    note("sqrt fp32 rbf d=2000 nugget 1e-2 t=10")
+    op = rbcg.DenseOperator(ctx, to_dev(A), lo="f32")
+    t = 10
+    rc, info, Y = _sqrt(R, op, B, t, matvec="f32")
+    assert rc == 0, info
+    A32 = A.astype(np.float32).astype(np.float64)
+
+    def op32(X):
+        return A32 @ np.asarray(X).astype(np.float32).astype(np.float64)
+
+    # accumulation error of the FP32 kernel on this operator, one 64-vector block
+    X = synth.rng(31, 0).standard_normal((64, A.shape[0]))
+    W = torch.zeros((64, A.shape[0]), dtype=torch.float64, device="cuda")
+    rbcg.op_apply(ctx, op, to_dev(X), W, "f32")
+    Wr = op32(X.T).T
+    eps = float((np.linalg.norm(W.cpu().numpy() - Wr, axis=1) / np.linalg.norm(Wr, axis=1)).max())
+    g = np.random.default_rng(77)
+
+    def op32_perturbed(X):
+        Wp = op32(X)
+        G = g.standard_normal(Wp.shape)
+        return Wp + eps * G * (np.linalg.norm(Wp, axis=0) / np.linalg.norm(G, axis=0))
+
+    def rel(Ya, Yb):
+        return float((np.linalg.norm(Ya - Yb, axis=1) / np.linalg.norm(Yb, axis=1)).max())
+
+    for grp in range(2):
+        Bg = B[32 * grp:32 * grp + 32]
+        Yr, _ = ob.sqrt_apply_exact(op32, Bg, t)
+        Yp, _ = ob.sqrt_apply_exact(op32_perturbed, Bg, t)
+        Yo, _ = ob.sqrt_apply_exact(A, Bg, t)
+        sens = rel(Yp, Yr)
+        e = rel(Y[32 * grp:32 * grp + 32], Yr)
+        note(f"group {grp}: product eps {eps:.1e}; FP32 GPU vs oracle on rounded operands {e:.2e} "
+             f"(bound 4 x {sens:.2e}); vs FP64 oracle {rel(Y[32 * grp:32 * grp + 32], Yo):.2e}")
+        assert e <= 4.0 * sens
+
+
 def test_sqrt_ragged_last_group(R):
     """40 samples in groups of 16: the last group has 8 samples (its block is
     zero padded and the padding deflates); every group equals the oracle's
