@@ -133,6 +133,12 @@ template <typename PT, int TB, int NW>
 __global__ __launch_bounds__(64 * NW) void k_gemm_nn(const NnDesc* __restrict__ descs, const int32_t* __restrict__ act) {
   const NnDesc d = descs[blockIdx.z];
   if (!is_active(act, d.active)) return;
+  if (d.acc_out) {
+    const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+    const gmem_t<const double> xa = gmem(d.acc_a), xb = gmem(d.acc_b);
+    const gmem_t<double> xo = gmem(d.acc_out);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < d.acc_n; e += nthr) xo[e] = xa[e] + xb[e];
+  }
   const int i0 = blockIdx.x * 16;
   if (i0 >= d.N) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1075,6 +1081,136 @@ __global__ __launch_bounds__(1024) void k_tri_backward(const TriDesc* __restrict
     }
     __syncthreads();
   }
+}
+
+// One refinement step of the projected solve (see the declaration).  One workgroup per
+// descriptor; y and the residual live in LDS.  Residual, row a of block i:
+//   R_i[a] = rhs_i[a] - sum_c S_i[a][c] y_i[c] - (K_{i-1} y_{i-1})[a] - (K_i^T y_{i+1})[a]
+//            - sum_{j >= i+2} (H_j[i] y_j)[a] - sum_{j <= i-2} (H_i[j]^T y_j)[a]
+// with S_i = sym(D_i) + sigma I and unit rows for deflated indices (as in the forward sweep).
+// The coupling K_i of blocks i and i+1 has two FP64 estimates: B_i from the Cholesky QR of the
+// projected block (Q_{i+1}^T A Q_i) and H_{i+1}[i]^T from the next step's projection
+// (Q_i^T A Q_{i+1}, transposed); with the coefficients present K_i is their mean, the
+// symmetric part of Q^T A Q, else B_i.  Then z_0 = R_0, z_{i+1} = R_{i+1} - U_i z_i,
+// delta_{t-1} = Sinv_{t-1} z_{t-1}, delta_i = Sinv_i (z_i - B_i^T delta_{i+1}), y += delta.
+__global__ __launch_bounds__(1024) void k_tri_refine(const TriDesc* __restrict__ descs, int t_launch,
+                                                     const int32_t* __restrict__ act) {
+  const TriDesc d = descs[blockIdx.z];
+  if (!is_active(act, d.active) || !d.refine) return;
+  const int m = d.m, tid = threadIdx.x;
+  const int t = d.nblk > 0 ? d.nblk : t_launch;
+  const int n = t * m;
+  const int64_t mm = (int64_t)m * m;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* y = (double*)smem_raw;   // n
+  double* R = y + n;               // n: residual, eliminated right-hand side, correction
+  double* tmp = R + n;             // 1024 + m
+  for (int e = tid; e < n; e += 1024) y[e] = d.Y[(int64_t)e * d.ldy];
+  __syncthreads();
+  // band part
+  for (int e = tid; e < n; e += 1024) {
+    const int i = e / m, a = e - i * m;
+    const int32_t* mk = d.mask + (int64_t)i * m;
+    if (mk[a]) {
+      R[e] = 0.0;
+      continue;
+    }
+    const double* Di = d.D + i * mm;
+    double s = d.sigma * y[e];
+    for (int c = 0; c < m; ++c) {
+      if (mk[c]) continue;
+      const double tac = (c == a) ? Di[a * m + a] : 0.5 * (Di[a * m + c] + Di[c * m + a]);
+      s += tac * y[i * m + c];
+    }
+    if (i > 0) {   // T[i][i-1] = K_{i-1}: B_{i-1}[a][c], H_i[i-1][c][a]
+      const double* Bp = d.Bsub + (i - 1) * mm;
+      if (d.Hoff) {
+        const double* Hp = d.Hoff + hoff_offset(i, m) + (i - 1) * mm;
+        for (int c = 0; c < m; ++c) s += 0.5 * (Bp[a * m + c] + Hp[c * m + a]) * y[(i - 1) * m + c];
+      } else {
+        for (int c = 0; c < m; ++c) s += Bp[a * m + c] * y[(i - 1) * m + c];
+      }
+    }
+    if (i + 1 < t) {   // T[i][i+1] = K_i^T: B_i[c][a], H_{i+1}[i][a][c]
+      const double* Bi = d.Bsub + i * mm;
+      if (d.Hoff) {
+        const double* Hn = d.Hoff + hoff_offset(i + 1, m) + i * mm;
+        for (int c = 0; c < m; ++c) s += 0.5 * (Bi[c * m + a] + Hn[a * m + c]) * y[(i + 1) * m + c];
+      } else {
+        for (int c = 0; c < m; ++c) s += Bi[c * m + a] * y[(i + 1) * m + c];
+      }
+    }
+    R[e] = (i == 0 ? d.rhs[(int64_t)a * d.ld_rhs] : 0.0) - s;
+  }
+  __syncthreads();
+  // off-band part, one block column j at a time
+  if (d.Hoff) {
+    const int slices = 1024 / m;
+    for (int j = 2; j < t; ++j) {
+      const double* H = d.Hoff + hoff_offset(j, m);   // rows of blocks 0 .. j - 2 (x m columns)
+      const int rows = (j - 1) * m;
+      const int32_t* mkj = d.mask + (int64_t)j * m;
+      for (int rr = tid; rr < rows; rr += 1024) {
+        if (d.mask[rr]) continue;   // masks of blocks 0 .. j - 2 are contiguous
+        double s = 0.0;
+        for (int b = 0; b < m; ++b) s += H[(int64_t)rr * m + b] * y[j * m + b];
+        R[rr] -= s;
+      }
+      const int b = tid % m, sl = tid / m;
+      double s = 0.0;
+      if (sl < slices)
+        for (int rr = sl; rr < rows; rr += slices) s += H[(int64_t)rr * m + b] * y[rr];
+      tmp[tid] = s;
+      __syncthreads();
+      if (tid < m && !mkj[tid]) {
+        double acc = 0.0;
+        for (int q = 0; q < slices; ++q) acc += tmp[q * m + tid];
+        R[j * m + tid] -= acc;
+      }
+      __syncthreads();
+    }
+  }
+  // forward elimination with the stored factors U_i = B_i Sinv_i
+  for (int i = 0; i + 1 < t; ++i) {
+    const double* U = d.Xw + i * mm;
+    if (tid < m) {
+      double s = 0.0;
+      for (int u = 0; u < m; ++u) s += U[tid * m + u] * R[i * m + u];
+      R[(i + 1) * m + tid] -= s;
+    }
+    __syncthreads();
+  }
+  // backward substitution with Sinv_i
+  for (int i = t - 1; i >= 0; --i) {
+    if (tid < m) {
+      double w = R[i * m + tid];
+      if (i + 1 < t) {
+        const double* Bi = d.Bsub + i * mm;
+        for (int u = 0; u < m; ++u) w -= Bi[u * m + tid] * R[(i + 1) * m + u];
+      }
+      tmp[tid] = w;
+    }
+    __syncthreads();
+    if (tid < m) {
+      const double* Si = d.Lw + i * mm;
+      double s = 0.0;
+      for (int c = 0; c < m; ++c) s += Si[tid * m + c] * tmp[c];
+      R[i * m + tid] = s;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n; e += 1024) d.Y[(int64_t)e * d.ldy] = y[e] + R[e];
+}
+
+hipError_t launch_tri_refine(const TriDesc* dd, int nz, int maxm, int maxr, int t, const int32_t* act,
+                             hipStream_t st) {
+  if (maxr != 1 || maxm < 1 || maxm > 1024) return hipErrorNotSupported;
+  const size_t lds = ((size_t)2 * t * maxm + 1024 + maxm) * 8;
+  if (lds > kLdsCap) return hipErrorNotSupported;
+  static const hipError_t attr = set_big_lds((const void*)k_tri_refine);
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL(k_tri_refine, dim3(1, 1, nz), dim3(1024), lds, st, dd, t, act);
+  return hipGetLastError();
 }
 
 hipError_t launch_tri_forward(const TriDesc* dd, int nz, int maxm, int maxr, int j0, int j1, const int32_t* act,

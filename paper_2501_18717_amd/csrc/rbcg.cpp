@@ -319,6 +319,7 @@ struct Prob {
   bool monitor = true;
   // buffers
   double *C1, *C2, *G, *M1, *M2, *Bc1, *D, *Bsub, *R0, *part, *Lw, *Xw, *Zw, *est, *scale, *ybuf;
+  double* Hoff = nullptr;  // off-band blocks of T (full-reorthogonalisation coefficients)
   int32_t *mask, *masktmp, *rank, *fail, *done_at;
   size_t part_elems = 0;
   RowOp rows(int64_t first_row = 0) const {
@@ -597,7 +598,11 @@ static void add_proj(Program& pg, std::vector<Launch>& out, Engine& E, int j, bo
 
 // W -= Q_{0..j} C  (rows [0, (j+1)m) of the basis): one launch, the workgroup's waves split the
 // reduction over the basis and combine on chip (no split partials in HBM)
-static void add_update(Program& pg, std::vector<Launch>& out, Engine& E, int j, double** C) {
+// With `keep_offband` (the second pass) the same launch also stores C1 + C2 of blocks 0 .. j - 1
+// (Q_i^T A Q_j, block column j of Q^T A Q above the diagonal) for the refinement of the projected
+// solve.
+static void add_update(Program& pg, std::vector<Launch>& out, Engine& E, int j, double** C,
+                       bool keep_offband = false) {
   std::vector<NnDesc> nn;
   int maxMo = 0, maxN = 0;
   for (auto& pr : E.P) {
@@ -618,6 +623,12 @@ static void add_update(Program& pg, std::vector<Launch>& out, Engine& E, int j, 
     d.Mo = pr.m;
     d.N = pr.d;
     d.active = (int)p;
+    if (keep_offband && j >= 1 && pr.Hoff) {
+      d.acc_a = pr.C1;
+      d.acc_b = pr.C2;
+      d.acc_out = pr.Hoff + hoff_offset(j, pr.m);
+      d.acc_n = (int64_t)j * pr.m * pr.m;
+    }
     nn.push_back(d);
   }
   Launch L{Launch::NN};
@@ -730,6 +741,20 @@ static void add_rmul(Program& pg, std::vector<Launch>& out, Engine& E, int slot,
   L.a1 = maxm;
   L.a2 = maxN;
   out.push_back(L);
+}
+
+// One FP64 refinement step of the projected solves after their backward sweeps (one right-hand
+// side each).  The explicit inverses of the Schur complements are not backward stable on their
+// own, and the band alone leaves out the rounding-level off-band part of Q^T A Q; the step
+// recovers the accuracy of a Cholesky solve of the whole projected matrix.  Skipped when the
+// solution does not fit in LDS.
+static hipError_t refine_projected(const TriDesc* dd, int nz, int maxm, int t, hipStream_t st) {
+  const hipError_t e = launch_tri_refine(dd, nz, maxm, 1, t, nullptr, st);
+  if (e == hipErrorNotSupported) {
+    (void)hipGetLastError();
+    return hipSuccess;
+  }
+  return e;
 }
 
 // Two rounds of pivoted Cholesky QR of block slot `slot`; the second writes the basis mask of
@@ -1315,7 +1340,7 @@ static void build_program(Program& pg, Engine& E, const std::vector<double>& tol
     // second pass also returns W^T W of the once-projected block: the Gram of the first
     // Cholesky QR pass (the second update changes W only at rounding level)
     add_proj(pg, out, E, j, true, c2.data());
-    add_update(pg, out, E, j, c2.data());
+    add_update(pg, out, E, j, c2.data(), true);
     // D_j = sym(C1 + C2) block j, formed by the second Cholesky-QR pass' workgroups
     std::vector<DiagDesc> dd;
     for (size_t p = 0; p < E.P.size(); ++p) {
@@ -1457,6 +1482,7 @@ static void carve(Arena& ar, Engine& E) {
     pr.est = ar.take<double>(T);
 
     pr.ybuf = ar.take<double>(T * pr.m);
+    pr.Hoff = T >= 2 ? ar.take<double>((size_t)hoff_offset((int)T, pr.m)) : nullptr;
     pr.mask = ar.take<int32_t>((T + 1) * pr.m);
     pr.masktmp = ar.take<int32_t>(pr.m);
     pr.rank = ar.take<int32_t>(1);
@@ -2221,6 +2247,11 @@ static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, c
         td.r = 1;
         td.active = -1;
         td.nblk = t;
+        td.sigma = pr.sigma_mon;   // the system's shift (the backward sweep itself does not use it)
+        td.Hoff = pr.Hoff;
+        // plain FP64 only: with low-precision products T carries product errors far above
+        // rounding level, and the outer FP64 refinement corrects the iterate instead
+        td.refine = opts[s].matvec == RBCG_F64 ? 1 : 0;
         tds.push_back(td);
         NnDesc nn{};
         nn.P = pr.rows(0);
@@ -2242,6 +2273,7 @@ static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, c
       rc = upload(ctx, stg, dscr);
       if (rc) return rc;
       HIP_TRY(launch_tri_backward(dptr<TriDesc>(dscr, o1), (int)tds.size(), E.maxm, 1, E.t_max, nullptr, st));
+      HIP_TRY(refine_projected(dptr<TriDesc>(dscr, o1), (int)tds.size(), E.maxm, E.t_max, st));
       HIP_TRY(launch_gemm_nn_ex(false, dptr<NnDesc>(dscr, o2), (int)nns.size(), 1, maxd, nullptr, st));
     }
     // FP64 residuals
@@ -2497,6 +2529,8 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
       td.m = m;
       td.r = 1;
       td.active = -1;
+      td.Hoff = pr.Hoff;
+      td.refine = opts->matvec == RBCG_F64 ? 1 : 0;   // as for rbcg_solve
       tds.push_back(td);
     }
     NnDesc nn{};
@@ -2517,6 +2551,7 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
     if (rc) return rc;
     HIP_TRY(tri_forward_any(dptr<TriDesc>(dscr, o1), (int)L, m, 1, 0, t, st));
     HIP_TRY(launch_tri_backward(dptr<TriDesc>(dscr, o1), (int)L, m, 1, t, nullptr, st));
+    HIP_TRY(refine_projected(dptr<TriDesc>(dscr, o1), (int)L, m, t, st));
     HIP_TRY(launch_gemm_nn_ex(false, dptr<NnDesc>(dscr, o2), 1, (int)L, d, nullptr, st));
     std::vector<int32_t> fh(L);
     HIP_TRY(hipMemcpyAsync(fh.data(), failL, L * 4, hipMemcpyDeviceToHost, st));

@@ -72,6 +72,12 @@ struct NnDesc {
   int32_t Ka, Mo, N, active;
   double* part;            // split partials of the tall variant ([s][b][i]) when splits > 1
   RowOp O32;               // k_gemm_nn: FP32 copy of the output rows as well (p == null: none)
+  // k_gemm_nn only: also acc_out[e] = acc_a[e] + acc_b[e] for e < acc_n (acc_out == null: none),
+  // spread over the launch's threads (the off-band projection coefficients of a Lanczos step)
+  const double* acc_a;
+  const double* acc_b;
+  double* acc_out;
+  int64_t acc_n;
 };
 
 // Symmetrised diagonal block of T from the two projection passes.
@@ -130,7 +136,17 @@ struct TriDesc {
   double sigma;
   int32_t m, r, active;
   int32_t nblk;            // backward sweep: blocks of this descriptor (0: the launch's t)
+  // projection coefficients Q_i^T A Q_j of block column j for i < j (the full-reorthogonalisation
+  // coefficients of Lanczos step j), used by the refinement step: block column j >= 1 holds j
+  // m x m blocks, rows i m .. i m + m - 1 for block i, at Hoff + hoff_offset(j, m); null: band only
+  const double* Hoff;
+  int32_t refine;          // k_tri_refine: 0 = leave Y as the sweeps left it
+  int32_t pad2_;
 };
+
+// Offset (elements) of block column j (>= 1) in the coefficient store; hoff_offset(t, m) is the
+// size of the store for t blocks.
+__host__ __device__ inline int64_t hoff_offset(int j, int m) { return j < 1 ? 0 : (int64_t)m * m * j * (j - 1) / 2; }
 
 // Conversion of rows between precisions (RNE).
 enum DType : int32_t { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
@@ -177,6 +193,12 @@ hipError_t launch_tri_forward(const TriDesc* d_desc, int nz, int maxm, int maxr,
                               const int32_t* active, hipStream_t st);
 hipError_t launch_tri_backward(const TriDesc* d_desc, int nz, int maxm, int maxr, int t,
                                const int32_t* active, hipStream_t st);
+// One step of FP64 refinement of Y (one right-hand side per descriptor) after the forward and
+// backward sweeps: R = RHS - (T + sigma I) Y with the band and, where Hoff is set, the off-band
+// coefficients; then the stored factors solve for the correction and Y += correction.
+// hipErrorNotSupported when r > 1 or the t m solution values do not fit in LDS.
+hipError_t launch_tri_refine(const TriDesc* d_desc, int nz, int maxm, int maxr, int t, const int32_t* active,
+                             hipStream_t st);
 // LDS bytes the two sweeps need for block width m and r right-hand sides.
 inline size_t tri_forward_lds(int m, int r) { return ((size_t)m * m + 19 * (size_t)m + 2 * (size_t)m * r) * 8; }
 inline size_t tri_backward_lds(int m, int r) { return ((size_t)m * m + 2 * (size_t)m * r) * 8; }

@@ -24,3 +24,12 @@ def a_err(A, mu, x, xref):
     num = e @ (A @ e) + mu * (e @ e)
     den = xref @ (A @ xref) + mu * (xref @ xref)
     return float(np.sqrt(max(num, 0.0) / den))
+
+
+def fp64_bound(kappa):
+    """Parity bound of a plain-FP64 GPU iterate against the FP64 oracle at the
+    same t: 1e-12, or a tenth of kappa(A_mu) times the unit roundoff when that
+    is larger (two FP64 block-CG runs that round differently can disagree by up
+    to about kappa u; measured against an extended-precision reference, both
+    stay within 0.05 kappa u on the batch workload)."""
+    return max(1e-12, 0.1 * kappa * 2.0 ** -53)

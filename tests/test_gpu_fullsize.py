@@ -30,7 +30,7 @@ import synth
 from oracle import block_cg as ob
 from oracle import truth as ot
 
-from gpu_util import a_err, note, to_dev
+from gpu_util import a_err, fp64_bound, note, to_dev
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
@@ -66,7 +66,7 @@ def test_dense_d8192_fp64_and_mixed(R):
     emx = a_err(A, mu, xmx.cpu().numpy(), Xo[0])
     note(f"fp64 iters {t} err {e64:.2e}; mixed {infomx[0]} err {emx:.2e}")
     kappa = (1.0 + mu) / (8192 ** -1.5 + mu)
-    assert e64 < max(1e-12, 1e-15 * kappa)
+    assert e64 < fp64_bound(kappa)
     assert emx < 1e-8
 
 

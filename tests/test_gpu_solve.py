@@ -1,10 +1,10 @@
 """GPU parity of rbcg_solve (through the C ABI) against the FP64 CPU oracle.
 
 Tolerances: plain FP64 block-CG iterates must match the oracle's iterate at
-the same t to a relative A_mu-norm difference of max(1e-12, 1e-15 kappa),
-kappa = cond(A + mu I): two correct FP64 implementations that round
-differently agree only to about kappa times the unit roundoff on
-ill-conditioned systems.  Mixed precision with FP64 refinement must match
+the same t to a relative A_mu-norm difference of max(1e-12, 0.1 kappa u),
+kappa = cond(A + mu I), u = 2^-53: two correct FP64 implementations that
+round differently agree only to about kappa u on ill-conditioned systems
+(measured against an extended-precision reference in test_gpu_batch.py).  Mixed precision with FP64 refinement must match
 the converged oracle solution to 1e-8.
 """
 import numpy as np
@@ -14,7 +14,7 @@ import synth
 from oracle import block_cg as ob
 from oracle import truth as ot
 
-from gpu_util import a_err, note, to_dev
+from gpu_util import a_err, fp64_bound, note, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -85,7 +85,7 @@ def test_ragged_shapes(R, d, k, t, p, mu):
     assert rc == 0, info
     X, _ = ob.bcg(A, [mu], b, Om if k else None, t)
     kappa = (lam[0] + mu) / (lam[-1] + mu)
-    assert a_err(A, mu, x, X[0]) < max(1e-12, 1e-15 * kappa)
+    assert a_err(A, mu, x, X[0]) < fp64_bound(kappa)
 
 
 @pytest.mark.parametrize("d,k,t", [(200, 128, 2), (150, 64, 3)])
@@ -135,7 +135,7 @@ def test_batched_uneven_systems_match_one_at_a_time(R):
         # one the exact-width factorization kernel serves, a different kernel (pivot ties may
         # break differently): equal up to rounding, at the oracle-parity bound
         rc1, _, x1 = _solve_one(R, A, mu, b, Om, t)
-        assert a_err(A, mu, x1, xd.cpu().numpy()) < max(1e-12, 1e-15 * kappa)
+        assert a_err(A, mu, x1, xd.cpu().numpy()) < fp64_bound(kappa)
 
 
 def test_rtol_stops_and_reports_relres(R):
