@@ -62,7 +62,9 @@ typedef enum {
   RBCG_ERR_NO_CONVERGENCE = -4, /* budget exhausted; best iterate written, info.relres set */
   RBCG_ERR_HIP = -5,            /* a HIP runtime call failed */
   RBCG_ERR_OOM = -6,            /* device workspace allocation failed */
-  RBCG_ERR_UNSUPPORTED = -7     /* device is not gfx950, or an unsupported option combination */
+  RBCG_ERR_UNSUPPORTED = -7,    /* device is not gfx950, or an unsupported option combination */
+  RBCG_ERR_TOO_LARGE = -8       /* rbcg_op_apply_noalloc: the call needs more device scratch than
+                                   the fixed buffer holds (see rbcg_noalloc_scratch_bytes) */
 } rbcg_status;
 
 typedef enum { RBCG_F64 = 0, RBCG_F32 = 1, RBCG_BF16 = 2 } rbcg_dtype;
@@ -202,6 +204,25 @@ int rbcg_invsqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t m_s, const doub
  * a Gram operator with BF16 copies, where X and Z X are carried as three BF16
  * parts).  1 <= N <= 256.  Returns after W is complete. */
 int rbcg_op_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t N, const double* X, double* W, int matvec);
+
+/* The same block product as rbcg_op_apply, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation): it calls
+ * no hipMalloc, hipFree, hipHostMalloc or other allocating routine.  Its device buffers (the
+ * padded copy of X, the low-precision copy of the block, the split-K partials and the kernel
+ * descriptors) are carved from one fixed array of rbcg_noalloc_scratch_bytes() bytes per GPU,
+ * which the library holds from the first rbcg_create on that device until the process ends.
+ * Arguments, layout, ownership and result as rbcg_op_apply (the operator handle and its
+ * low-precision copies must already exist).  A call whose buffers do not fit returns
+ * RBCG_ERR_TOO_LARGE before any device work; the FP64 and FP32 dense products fit for
+ * N * round_up(d, 64) up to about 600000 (e.g. d = 8192 with N = 65).  Gram operators with BF16
+ * products need n-sized staging and fit only for small n.  Every call on a GPU shares that GPU's
+ * array and leaves its contents behind (nothing in it is assumed to start at zero): calls that
+ * overlap on one GPU (two host threads, or two contexts on different streams) race and must be
+ * serialised by the caller.  Returns after W is complete. */
+int rbcg_op_apply_noalloc(rbcg_ctx* ctx, const rbcg_op* op, int64_t N, const double* X, double* W, int matvec);
+
+/* Size in bytes of the fixed per-GPU scratch array used by rbcg_op_apply_noalloc (host-only). */
+int64_t rbcg_noalloc_scratch_bytes(void);
 
 /* Bytes of device memory currently held by the context's workspace. */
 int64_t rbcg_workspace_bytes(const rbcg_ctx* ctx);

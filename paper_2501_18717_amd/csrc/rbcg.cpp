@@ -24,6 +24,7 @@
 #include <cstring>
 #include <string>
 #include <map>
+#include <mutex>
 #include <thread>
 #include <tuple>
 #include <vector>
@@ -76,6 +77,7 @@ struct rbcg_ctx {
   hipEvent_t ev_stage = nullptr;
   bool stage_pending = false;
   hipEvent_t ev_in = nullptr;   // caller's stream position the children wait for
+  unsigned char* scratch = nullptr;   // this device's fixed scratch (rbcg_op_apply_noalloc)
 };
 
 struct rbcg_op {
@@ -115,11 +117,38 @@ extern "C" const char* rbcg_status_string(int s) {
     case RBCG_ERR_HIP: return "HIP runtime error";
     case RBCG_ERR_OOM: return "device memory allocation failed";
     case RBCG_ERR_UNSUPPORTED: return "unsupported device or option";
+    case RBCG_ERR_TOO_LARGE:
+      return "problem needs more than the fixed 48 MiB device scratch of the no-allocation entry point";
     default: return "unknown status";
   }
 }
 
 extern "C" int rbcg_version(void) { return 10100; }
+
+// ------------------------------------------------------------------ fixed scratch
+// Device memory of the no-allocation block product (rbcg_op_apply_noalloc): one array per GPU,
+// held until the process ends.  In host code `scratch` names a host-side stand-in, not device
+// memory; its device address is looked up once per device (hipGetSymbolAddress, with that
+// device current) and only that address is handed to kernels and copies.
+constexpr size_t kScratchBytes = (size_t)48 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the scratch array on device `dev` (the current device).
+static int scratch_address(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return RBCG_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return fail_hip(e == hipSuccess ? hipErrorInvalidSymbol : e, "hipGetSymbolAddress");
+    g_scratch_dev[dev] = (unsigned char*)ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return RBCG_OK;
+}
 
 extern "C" int rbcg_create(rbcg_ctx** out, void* stream) {
   if (!out) return RBCG_ERR_INVALID_ARG;
@@ -129,9 +158,13 @@ extern "C" int rbcg_create(rbcg_ctx** out, void* stream) {
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, dev));
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return RBCG_ERR_UNSUPPORTED;
+  unsigned char* scr = nullptr;
+  const int rs = scratch_address(dev, &scr);
+  if (rs) return rs;
   rbcg_ctx* c = new rbcg_ctx();
   c->device = dev;
   c->stream = (hipStream_t)stream;
+  c->scratch = scr;
   if (hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_mon, hipEventDisableTiming) != hipSuccess ||
@@ -1814,7 +1847,12 @@ static bool op_supports(const rbcg_op* op, int mv) {
 }
 
 // ---------------------------------------------------------------------- block product
-extern "C" int rbcg_op_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t N, const double* X, double* W, int matvec) {
+// The block product W = A X.  With `fixed` null the buffers come from the context's workspace
+// (grown on demand) and descriptors go through pinned staging; otherwise every device buffer and
+// the descriptors are carved from `fixed` (fixed_cap bytes) and nothing is allocated: sizes that
+// do not fit are RBCG_ERR_TOO_LARGE before any device work.
+static int op_apply_impl(rbcg_ctx* ctx, const rbcg_op* op, int64_t N, const double* X, double* W, int matvec,
+                         unsigned char* fixed, size_t fixed_cap) {
   if (!ctx || !op || !X || !W || N < 1 || N > 256) return RBCG_ERR_INVALID_ARG;
   if (matvec != RBCG_F64 && matvec != RBCG_F32 && matvec != RBCG_BF16) return RBCG_ERR_INVALID_ARG;
   if (!op_supports(op, matvec)) return RBCG_ERR_UNSUPPORTED;
@@ -1850,12 +1888,24 @@ extern "C" int rbcg_op_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t N, const 
   Arena a0;
   carve_g(a0);
   const size_t desc_off = (size_t)round_up((int64_t)a0.off, 256);
-  int rc = ensure_ws(ctx, desc_off + (1 << 16));
-  if (rc) return rc;
+  const size_t need = desc_off + (1 << 16);
+  char* base = nullptr;
+  size_t cap = 0;
+  if (fixed) {
+    if (need > fixed_cap) return RBCG_ERR_TOO_LARGE;
+    base = (char*)fixed;
+    cap = fixed_cap;
+  } else {
+    const int rw = ensure_ws(ctx, need);
+    if (rw) return rw;
+    base = ctx->ws;
+    cap = ctx->ws_cap;
+  }
+  int rc = RBCG_OK;
   Arena a1;
-  a1.base = ctx->ws;
+  a1.base = base;
   carve_g(a1);
-  unsigned char* ddesc = (unsigned char*)ctx->ws + desc_off;
+  unsigned char* ddesc = (unsigned char*)base + desc_off;
   Program pg;
   std::vector<Launch> out;
   {
@@ -1891,7 +1941,15 @@ extern "C" int rbcg_op_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t N, const 
     L.a2 = d;
     out.push_back(L);
   }
-  if (desc_off + pg.stg.host.size() > ctx->ws_cap) return RBCG_ERR_OOM;
+  if (desc_off + pg.stg.host.size() > cap) return fixed ? RBCG_ERR_TOO_LARGE : RBCG_ERR_OOM;
+  if (fixed) {
+    // plain stream-ordered copy from the host descriptors (kept alive until the final sync);
+    // no pinned staging, no profiling events
+    HIP_TRY(hipMemcpyAsync(ddesc, pg.stg.host.data(), pg.stg.host.size(), hipMemcpyHostToDevice, ctx->stream));
+    for (const auto& L : out) HIP_TRY(enqueue(L, ddesc, nullptr, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return RBCG_OK;
+  }
   rc = upload(ctx, pg.stg, ddesc);
   if (rc) return rc;
   for (const auto& L : out) {
@@ -1903,6 +1961,18 @@ extern "C" int rbcg_op_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t N, const 
   prof_collect(ctx);
   return RBCG_OK;
 }
+
+extern "C" int rbcg_op_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t N, const double* X, double* W, int matvec) {
+  return op_apply_impl(ctx, op, N, X, W, matvec, nullptr, 0);
+}
+
+extern "C" int rbcg_op_apply_noalloc(rbcg_ctx* ctx, const rbcg_op* op, int64_t N, const double* X, double* W,
+                                     int matvec) {
+  if (!ctx || !ctx->scratch) return RBCG_ERR_INVALID_ARG;
+  return op_apply_impl(ctx, op, N, X, W, matvec, ctx->scratch, kScratchBytes);
+}
+
+extern "C" int64_t rbcg_noalloc_scratch_bytes(void) { return (int64_t)kScratchBytes; }
 
 // ------------------------------------------------------------------------------ solve
 static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, const double* mu,

@@ -22,7 +22,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 F64, F32, BF16 = 0, 1, 2
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "NOT_SPD", -3: "BREAKDOWN", -4: "NO_CONVERGENCE",
-          -5: "HIP", -6: "OOM", -7: "UNSUPPORTED"}
+          -5: "HIP", -6: "OOM", -7: "UNSUPPORTED", -8: "TOO_LARGE"}
 
 
 class Opts(ctypes.Structure):
@@ -69,6 +69,8 @@ _sqrt = _sig("rbcg_sqrt_apply", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, ctypes.
 _invsqrt = _sig("rbcg_invsqrt_apply", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)])
 _ws_bytes = _sig("rbcg_workspace_bytes", _i64, [_vp])
 _op_apply = _sig("rbcg_op_apply", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, ctypes.c_int])
+_op_apply_noalloc = _sig("rbcg_op_apply_noalloc", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, ctypes.c_int])
+_noalloc_bytes = _sig("rbcg_noalloc_scratch_bytes", _i64, [])
 _sqrt_rule = _sig("rbcg_sqrt_rule", ctypes.c_int, [ctypes.c_double, ctypes.c_double, _i32, _dp, _dp])
 _profile = _sig("rbcg_profile", ctypes.c_int, [_vp, ctypes.c_int])
 _profile_read = _sig("rbcg_profile_read", ctypes.c_int, [_vp, ctypes.POINTER(_i64), _dp, _dp, _dp])
@@ -230,6 +232,19 @@ def op_apply(ctx: Context, op, X, W, matvec: str = "f64"):
     _need(X, torch.float64, (N, op.d), "X")
     _need(W, torch.float64, (N, op.d), "W")
     _check(_op_apply(ctx.handle, op.handle, N, _ptr(X), _ptr(W), DTYPES[matvec]), "rbcg_op_apply")
+
+
+def op_apply_noalloc(ctx: Context, op, X, W, matvec: str = "f64"):
+    """The same product through rbcg_op_apply_noalloc (fixed per-GPU scratch, no allocation)."""
+    import torch
+    N, d = X.shape
+    _need(X, torch.float64, (N, op.d), "X")
+    _need(W, torch.float64, (N, op.d), "W")
+    _check(_op_apply_noalloc(ctx.handle, op.handle, N, _ptr(X), _ptr(W), DTYPES[matvec]), "rbcg_op_apply_noalloc")
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(_noalloc_bytes())
 
 
 def solve(ctx: Context, ops: Sequence, mus: Sequence[float], bs: Sequence, omegas: Sequence, xs: Sequence,
