@@ -119,7 +119,7 @@ typedef struct {
                           (default 1e-10 when 0) */
   double sweep_tol;    /* low-precision products with rtol > 0: reduction of the residual
                           that one Krylov space aims for before the next FP64 residual
-                          (0 = default: 1e-4 for FP32, 1e-3 for BF16); never below what
+                          (0 = default: 1e-4 for FP32, 1e-6 for BF16); never below what
                           the remaining rtol needs */
 } rbcg_opts;
 
@@ -162,7 +162,10 @@ int rbcg_solve(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, const dou
  *   X      device, L x d row-major (FP64), row l = solution for mu[l]
  *   info   host[L]
  * With opts.matvec low-precision and rtol > 0, each refinement sweep builds
- * a new space on [R Omega] where R holds the residuals of all shifts. */
+ * a new space on [R Omega] where R holds the FP64 residuals of the shifts not
+ * yet at rtol; only those shifts are corrected.  With the environment
+ * variable RBCG_DEBUG set, each sweep prints one line (its Krylov steps and
+ * the range of relative residuals) to stderr. */
 int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, const double* omega, int32_t k,
               int64_t L, const double* mu, double* X, const rbcg_opts* opts, rbcg_info* info);
 

@@ -15,9 +15,6 @@ hipError_t nt_f32_o1(int, const NtDesc*, int, int, int, const int32_t*, hipStrea
 hipError_t nt_f32_o0(int, const NtDesc*, int, int, int, const int32_t*, hipStream_t);
 hipError_t nt_f32f64_o1(int, const NtDesc*, int, int, int, const int32_t*, hipStream_t);
 hipError_t nt_f32f64_o0(int, const NtDesc*, int, int, int, const int32_t*, hipStream_t);
-hipError_t nt_bf16_o1_split(int, const NtDesc*, int, int, int, const int32_t*, hipStream_t);
-hipError_t nt_bf16_o1(int, const NtDesc*, int, int, int, const int32_t*, hipStream_t);
-hipError_t nt_bf16_o0(int, const NtDesc*, int, int, int, const int32_t*, hipStream_t);
 
 hipError_t launch_gemm_nt_ex(int dtype, int out_t, bool xsplit, const NtDesc* dd, int nz, int maxM, int maxN,
                              int splits, const int32_t* act, hipStream_t st) {
@@ -28,9 +25,6 @@ hipError_t launch_gemm_nt_ex(int dtype, int out_t, bool xsplit, const NtDesc* dd
     case DT_F32: return out_t ? nt_f32_o1(tn, dd, nz, maxM, splits, act, st) : nt_f32_o0(tn, dd, nz, maxM, splits, act, st);
     case DT_F32F64:
       return out_t ? nt_f32f64_o1(tn, dd, nz, maxM, splits, act, st) : nt_f32f64_o0(tn, dd, nz, maxM, splits, act, st);
-    case DT_BF16:
-      if (xsplit) return nt_bf16_o1_split(tn, dd, nz, maxM, splits, act, st);
-      return out_t ? nt_bf16_o1(tn, dd, nz, maxM, splits, act, st) : nt_bf16_o0(tn, dd, nz, maxM, splits, act, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -524,6 +524,10 @@ static void prof_collect(rbcg_ctx* c) {
 static hipError_t enqueue(const Launch& L, unsigned char* dbase, const int32_t* act, hipStream_t st) {
   switch (L.kind) {
     case Launch::NT:
+      if (L.a0 & (1 << 13))   // BF16 Gram-operator pass (FP32 split-K partials)
+        return launch_gram_bf16(dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a2, L.a3, act, st);
+      if (L.a0 & (1 << 14))   // sum of the first pass's partials into the three BF16 parts of Z X
+        return launch_gram_combine(dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a2, L.a3, act, st);
       if (L.a0 & (1 << 12)) return launch_gram(dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a3, act, st);
       if (L.a0 & (1 << 11)) {   // FP32 product on the 32x32x2 kernel
         int t2 = 0, ne = 0;
@@ -1067,7 +1071,8 @@ static void add_matvec(Program& pg, std::vector<Launch>& out, Engine& E, int j) 
     } else {
       const int n = (int)op->n;
       if (G.mv_t == RBCG_BF16) {
-        // X -> BF16 hi/lo pairs; Y^T = (Z X)^T as BF16 pairs; W = Z^T Y
+        // X -> three BF16 parts; Y = Z X as three BF16 parts; W = Z^T Y as FP64 split-K partials
+        // (both passes on the dedicated BF16 Gram kernel)
         CvtDesc c{};
         c.src = Xb;
         c.dst = plain_rows(G.xlo, G.ld_xlo);
@@ -1083,65 +1088,71 @@ static void add_matvec(Program& pg, std::vector<Launch>& out, Engine& E, int j) 
         C.a1 = G.N;
         C.a2 = d;
         out.push_back(C);
-        NtDesc n1{};
-        n1.P = plain_rows(op->lo, op->ld_lo);
-        n1.X = plain_rows(G.xlo, G.ld_xlo);
-        n1.M = n;
-        n1.N = G.N;
-        n1.K = d;
-        n1.active = act_idx;
-        n1.O = plain_rows(G.ylo, G.ld_ylo);
-        n1.out_t = 3;
-        Launch L1{Launch::NT};
-        L1.off = pg.stg.add(std::vector<NtDesc>{n1});
-        L1.nz = 1;
-        L1.a0 = DT_BF16 | (1 << 8);
-        L1.flag = true;
-        L1.a1 = n;
-        L1.a2 = G.N;
-        L1.a3 = 1;
-        L1.prof = true;
-        L1.flops = 2.0 * n * (double)d * G.N;
-        L1.bytes = 2.0 * n * (double)d;
-        out.push_back(L1);
-        NtDesc n2{};
-        n2.P = plain_rows(op->lot, op->ld_lot);
-        n2.X = plain_rows(G.ylo, G.ld_ylo);
-        n2.M = d;
-        n2.N = G.N;
-        n2.K = n;
-        n2.active = act_idx;
-        n2.part = G.part;
-        n2.O = Wb;
-        n2.out_t = DT_F64;
-        const int splits = G.splits2;
-        Launch L2{Launch::NT};
-        L2.off = pg.stg.add(std::vector<NtDesc>{n2});
-        L2.nz = 1;
-        L2.a0 = DT_BF16 | (1 << 8);
-        L2.flag = true;
-        L2.a1 = d;
-        L2.a2 = G.N;
-        L2.a3 = splits;
-        L2.prof = true;
-        L2.flops = 2.0 * n * (double)d * G.N;
-        L2.bytes = 2.0 * n * (double)d;
-        out.push_back(L2);
-        if (splits > 1) {
+        // column chunks of at most 144 vectors (one pass over Z and Z^T each)
+        const int s1 = gram_bf16_splits(d), s2 = G.splits2;
+        const int nch = (G.N + 143) / 144;
+        const int cw = (G.N + nch - 1) / nch;
+        for (int c0 = 0; c0 < G.N; c0 += cw) {
+          const int nc = std::min(cw, G.N - c0);
+          NtDesc n1{};
+          n1.P = plain_rows(op->lo, op->ld_lo);
+          n1.X = plain_rows((const unsigned short*)G.xlo + (size_t)3 * c0 * G.ld_xlo, G.ld_xlo);
+          n1.M = n;
+          n1.N = nc;
+          n1.K = d;
+          n1.active = act_idx;
+          n1.part = G.part;
+          n1.O = plain_rows((const unsigned short*)G.ylo + (size_t)3 * c0 * G.ld_ylo, G.ld_ylo);
+          Launch L1{Launch::NT};
+          L1.off = pg.stg.add(std::vector<NtDesc>{n1});
+          L1.nz = 1;
+          L1.a0 = DT_BF16 | (1 << 13);
+          L1.a1 = n;
+          L1.a2 = nc;
+          L1.a3 = s1;
+          L1.prof = true;
+          L1.flops = 2.0 * n * (double)d * nc;
+          L1.bytes = 2.0 * n * (double)d;
+          out.push_back(L1);
+          Launch Lc = L1;
+          Lc.a0 = DT_BF16 | (1 << 14);
+          Lc.prof = false;
+          out.push_back(Lc);
+          NtDesc n2{};
+          n2.P = plain_rows(op->lot, op->ld_lot);
+          n2.X = n1.O;
+          n2.M = d;
+          n2.N = nc;
+          n2.K = n;
+          n2.active = act_idx;
+          n2.part = G.part;
+          Launch L2{Launch::NT};
+          L2.off = pg.stg.add(std::vector<NtDesc>{n2});
+          L2.nz = 1;
+          L2.a0 = DT_BF16 | (1 << 13);
+          L2.a1 = d;
+          L2.a2 = nc;
+          L2.a3 = s2;
+          L2.prof = true;
+          L2.flops = 2.0 * n * (double)d * nc;
+          L2.bytes = 2.0 * n * (double)d;
+          out.push_back(L2);
           FinDesc f{};
           f.part = G.part;
           f.M = d;
-          f.N = G.N;
-          f.splits = splits;
+          f.N = nc;
+          f.splits = s2;
           f.mode = FIN_TRANS;
           f.O = Wb;
+          f.O.p = (const double*)Wb.p + (size_t)c0 * Wb.ld;
           f.alpha = 1.0;
           f.active = act_idx;
+          f.part_f32 = 1;
           Launch F{Launch::FIN};
           F.off = pg.stg.add(std::vector<FinDesc>{f});
           F.nz = 1;
           F.a1 = d;
-          F.a2 = G.N;
+          F.a2 = nc;
           out.push_back(F);
         }
       } else {
@@ -1435,6 +1446,9 @@ static void size_partials(Engine& E, const rbcg_ctx* ctx) {
       // about 1024 workgroups: finer granularity lets other CUs absorb a CU held by the
       // convergence monitor on the side stream
       G.splits2 = std::max(1, std::min(std::max(1, 1024 / t64), std::max(1, d / 512)));
+    } else if (G.op->kind == RBCG_OP_GRAM && G.mv_t == RBCG_BF16) {
+      // second pass of the BF16 Gram kernel: FP32 chains of about 1024 values of n, summed in FP64
+      G.splits2 = gram_bf16_splits(Kp);
     } else {
       G.splits2 = pick_splits(tiles, 1, Kp);
     }
@@ -1452,6 +1466,11 @@ static void size_partials(Engine& E, const rbcg_ctx* ctx) {
     int smax = G.splits2;
     for (int s : G.tune) smax = std::max(smax, s);
     G.part_elems = smax > 1 ? (size_t)smax * d * G.N : 0;
+    // both passes of the BF16 Gram kernel write FP32 partials into the same buffer (the first
+    // pass's are combined before the second pass writes)
+    if (G.op->kind == RBCG_OP_GRAM && G.mv_t == RBCG_BF16)
+      G.part_elems =
+          (std::max((size_t)gram_bf16_splits(d) * (size_t)G.op->n, (size_t)smax * d) * std::min(G.N, 144) + 1) / 2;
   }
   // batched dense groups share one product launch per precision: one split count for all of them,
   // about 1024 workgroups in total
@@ -1826,7 +1845,10 @@ static int sqnorms(rbcg_ctx* ctx, RowOp x, int rows, int n, double* dout, double
 static double sweep_floor(const rbcg_opts& o) {
   if (o.matvec == RBCG_F64) return 0.0;
   if (o.sweep_tol > 0.0) return o.sweep_tol;
-  return o.matvec == RBCG_F32 ? 1e-4 : 1e-3;
+  // BF16 Gram products: each Krylov space runs (nearly) to the whole space, where the correction
+  // is accurate to the rounding of Z (measured: 1e-3 per sweep at t = 32, 0.03 when stopped at a
+  // reduction of 1e-3, which the Lanczos estimate reports too early)
+  return o.matvec == RBCG_F32 ? 1e-4 : 1e-6;
 }
 
 static bool valid_opts(const rbcg_opts* o) {
@@ -2445,12 +2467,13 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
   const int64_t ldv = pr.ldv;
   const size_t T = (size_t)E.t_max;
   const size_t mm = (size_t)m * m;
-  double *Rbuf, *rpart, *rys, *mu_dev, *sq_dev, *Lws, *Xws, *Zws, *Yall, *Bhat;
+  double *Rbuf, *Rcmp, *rpart, *rys, *mu_dev, *sq_dev, *Lws, *Xws, *Zws, *Yall, *Bhat;
   unsigned char* dscr;
   int32_t* failL;
   auto carve_all = [&](Arena& a) {
     carve(a, E);
     Rbuf = a.take<double>((size_t)L * ldv);
+    Rcmp = a.take<double>((size_t)L * ldv);
     rpart = a.take<double>(std::max<size_t>(rp.part_elems, 1));
     rys = a.take<double>(std::max<size_t>(rp.ys_elems, 1));
     mu_dev = a.take<double>(L);
@@ -2492,9 +2515,23 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
   std::vector<char> spd_fail(L, 0);
   int loads = 0, sweeps = 0, iters = 0;
   const int max_sweeps = refine ? opts->refine_max : 1;
+  // shifts whose iterate is corrected by the current sweep (all of them in the first sweep; after
+  // that the ones whose FP64 residual still misses rtol) and the column of each in the sweep's
+  // right-hand sides
+  std::vector<int> act_l;
+  for (int64_t l = 0; l < L; ++l) act_l.push_back((int)l);
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     std::vector<CopyDesc> cps;
     int nstart;
+    const int La = (int)act_l.size();
+    if (sweep > 0) {
+      // the monitor follows the smallest shift still being corrected
+      int jm = 0;
+      for (int j = 1; j < La; ++j)
+        if (mu[act_l[j]] < mu[act_l[jm]]) jm = j;
+      l_min = act_l[jm];
+      pr.sigma_mon = mu[l_min];
+    }
     if (sweep == 0) {
       CopyDesc c{};
       c.src = plain_rows(b, d);
@@ -2518,28 +2555,48 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
       pr.mon_col = 0;
       nstart = 1;
     } else {
-      // [R, Omega[0 : m - L]]: every shift's residual is in the start block
+      // [R_act, Omega[0 : m - La]]: the residual of every shift still being corrected is in the
+      // start block (gathered into Rcmp first: the Gaussian refill reads them there too)
+      {
+        Staging gs;
+        std::vector<CopyDesc> gat;
+        for (int j = 0; j < La; ++j) {
+          CopyDesc g{};
+          g.src = plain_rows(Rbuf + (size_t)act_l[j] * ldv, ldv);
+          g.dst = plain_rows(Rcmp + (size_t)j * ldv, ldv);
+          g.alpha = 1.0;
+          g.rows = 1;
+          g.rows_total = 1;
+          g.n = d;
+          g.active = -1;
+          gat.push_back(g);
+        }
+        const size_t og = gs.add(gat);
+        rc = upload(ctx, gs, dscr);
+        if (rc) return rc;
+        HIP_TRY(launch_copy(dptr<CopyDesc>(dscr, og), La, 1, d, nullptr, st));
+      }
       CopyDesc c{};
-      c.src = plain_rows(Rbuf, ldv);
+      c.src = plain_rows(Rcmp, ldv);
       c.dst = pr.block(0);
       c.alpha = 1.0;
-      c.rows = (int)L;
-      c.rows_total = (int)L;
+      c.rows = La;
+      c.rows_total = La;
       c.n = d;
       c.active = -1;
       cps.push_back(c);
       CopyDesc o{};
       o.src = plain_rows(k > 0 ? omega : b, d);
-      o.dst = RowOp{pr.q + L * ldv, ldv, pr.bs, m, 0};
+      o.dst = RowOp{pr.q + (size_t)La * ldv, ldv, pr.bs, m, 0};
       o.alpha = 1.0;
-      o.rows = m - (int)L;
-      o.rows_total = m - (int)L;
+      o.rows = m - La;
+      o.rows_total = m - La;
       o.n = d;
       o.active = -1;
       cps.push_back(o);
       pr.force_first = false;
-      pr.mon_col = l_min;
-      nstart = (int)L;
+      pr.mon_col = (int)(std::find(act_l.begin(), act_l.end(), l_min) - act_l.begin());
+      nstart = La;
     }
     std::vector<double> tol(1, 0.0);
     double rmax = bnorm;
@@ -2552,11 +2609,11 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
     Program pg;
     Refill rf;
     if (sweep > 0) {
-      rf.R = plain_rows(Rbuf, ldv);
-      rf.L = (int)L;
+      rf.R = plain_rows(Rcmp, ldv);
+      rf.L = La;
       rf.omega = plain_rows(omega, d);
-      rf.src_first = m - (int)L;
-      rf.src_avail = k > 0 ? k - (m - (int)L) : 0;
+      rf.src_first = m - La;
+      rf.src_avail = k > 0 ? k - (m - La) : 0;
     }
     build_program(pg, E, tol, refine, cps, std::max(nstart, m), sweep > 0 ? &rf : nullptr);
     if (desc_off + pg.stg.host.size() > ctx->ws_cap) return RBCG_ERR_OOM;
@@ -2578,21 +2635,24 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
     iters = t;
     loads += t;
     sweeps += 1;
-    // all shifts: forward + backward sweeps; rhs = column l of R0 (sweep > 0) or column 0
+    // every corrected shift: forward + backward sweeps; rhs = column j of R0 (sweep > 0) or
+    // column 0, then x_l (+)= Q y_l
     Staging stg;
     std::vector<TriDesc> tds;
-    for (int64_t l = 0; l < L; ++l) {
+    std::vector<NnDesc> nns;
+    for (int j = 0; j < La; ++j) {
+      const int l = act_l[j];
       TriDesc td{};
       td.D = pr.D;
       td.Bsub = pr.Bsub;
       td.mask = pr.mask;
-      td.rhs = pr.R0 + (sweep == 0 ? 0 : l);
+      td.rhs = pr.R0 + (sweep == 0 ? 0 : j);
       td.ld_rhs = m;
-      td.Lw = Lws + l * T * mm;
-      td.Xw = Xws + l * T * mm;
-      td.Zw = Zws + l * (T + 1) * m;
-      td.Y = Yall + l;
-      td.ldy = L;
+      td.Lw = Lws + (size_t)j * T * mm;
+      td.Xw = Xws + (size_t)j * T * mm;
+      td.Zw = Zws + (size_t)j * (T + 1) * m;
+      td.Y = Yall + j;
+      td.ldy = La;
       td.est = nullptr;
       td.fail = failL + l;
       td.sigma = mu[l];
@@ -2602,27 +2662,28 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
       td.Hoff = pr.Hoff;
       td.refine = opts->matvec == RBCG_F64 ? 1 : 0;   // as for rbcg_solve
       tds.push_back(td);
+      NnDesc nn{};
+      nn.P = pr.rows(0);
+      nn.C = Yall + j;
+      nn.ldc = La;
+      nn.Y = plain_rows(X + (size_t)l * d, d);
+      nn.O = plain_rows(X + (size_t)l * d, d);
+      nn.alpha = 1.0;
+      nn.beta = sweep == 0 ? 0.0 : 1.0;
+      nn.Ka = t * m;
+      nn.Mo = 1;
+      nn.N = d;
+      nn.active = -1;
+      nns.push_back(nn);
     }
-    NnDesc nn{};
-    nn.P = pr.rows(0);
-    nn.C = Yall;
-    nn.ldc = L;
-    nn.Y = plain_rows(X, d);
-    nn.O = plain_rows(X, d);
-    nn.alpha = 1.0;
-    nn.beta = sweep == 0 ? 0.0 : 1.0;
-    nn.Ka = t * m;
-    nn.Mo = (int)L;
-    nn.N = d;
-    nn.active = -1;
     const size_t o1 = stg.add(tds);
-    const size_t o2 = stg.add(std::vector<NnDesc>{nn});
+    const size_t o2 = stg.add(nns);
     rc = upload(ctx, stg, dscr);
     if (rc) return rc;
-    HIP_TRY(tri_forward_any(dptr<TriDesc>(dscr, o1), (int)L, m, 1, 0, t, st));
-    HIP_TRY(launch_tri_backward(dptr<TriDesc>(dscr, o1), (int)L, m, 1, t, nullptr, st));
-    HIP_TRY(refine_projected(dptr<TriDesc>(dscr, o1), (int)L, m, t, st));
-    HIP_TRY(launch_gemm_nn_ex(false, dptr<NnDesc>(dscr, o2), 1, (int)L, d, nullptr, st));
+    HIP_TRY(tri_forward_any(dptr<TriDesc>(dscr, o1), La, m, 1, 0, t, st));
+    HIP_TRY(launch_tri_backward(dptr<TriDesc>(dscr, o1), La, m, 1, t, nullptr, st));
+    HIP_TRY(refine_projected(dptr<TriDesc>(dscr, o1), La, m, t, st));
+    HIP_TRY(launch_gemm_nn_ex(false, dptr<NnDesc>(dscr, o2), La, 1, d, nullptr, st));
     std::vector<int32_t> fh(L);
     HIP_TRY(hipMemcpyAsync(fh.data(), failL, L * 4, hipMemcpyDeviceToHost, st));
     // residuals of every shift (FP64)
@@ -2633,13 +2694,28 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
     rc = sqnorms(ctx, plain_rows(Rbuf, ldv), (int)L, d, sq_dev, host_sq, dscr);
     if (rc) return rc;
     bool all = true;
+    std::vector<int> next_l;
     for (int64_t l = 0; l < L; ++l) {
       relres[l] = std::sqrt(host_sq[l]) / bnorm;
-      if (fh[l]) {   // as in the solve: with refinement the FP64 residual decides
+      const bool corrected = std::find(act_l.begin(), act_l.end(), (int)l) != act_l.end();
+      if (corrected && fh[l]) {   // as in the solve: with refinement the FP64 residual decides
         if (refine) spd_fail[l] = 1;
         else status[l] = RBCG_ERR_NOT_SPD;
       }
-      if (refine && !(relres[l] <= opts->rtol)) all = false;
+      if (refine && !(relres[l] <= opts->rtol)) {
+        all = false;
+        next_l.push_back((int)l);
+      }
+    }
+    if (!next_l.empty()) act_l = next_l;
+    if (std::getenv("RBCG_DEBUG")) {
+      double rlo = relres[0], rhi = relres[0];
+      for (int64_t l = 1; l < L; ++l) {
+        rlo = std::min(rlo, relres[l]);
+        rhi = std::max(rhi, relres[l]);
+      }
+      std::fprintf(stderr, "rbcg_path: sweep %d t %d target %.1e relres [%.2e, %.2e] (smallest shift %.2e)\n", sweep, t,
+                   tol[0], rlo, rhi, relres[l_min]);
     }
     if (!refine || all) break;
   }

@@ -168,6 +168,17 @@ hipError_t launch_gemm_nt_ex(int dtype, int out_t, bool xsplit, const NtDesc* d_
 // over k into part (splits x m x m, FIN_T2R order).
 bool gram_supported(int m);
 hipError_t launch_gram(const NtDesc* d_desc, int nz, int maxm, int splits, const int32_t* active, hipStream_t st);
+// BF16 products of the Gram operator with the right operand as three BF16 parts (rows 3c, 3c + 1,
+// 3c + 2 of X), N <= 144, FP32 MFMA accumulation over `splits` ranges of k, each written as FP32
+// partials part[s][c][i] (reduced in FP64 by k_finish with part_f32, or by launch_gram_combine).
+hipError_t launch_gram_bf16(const NtDesc* d_desc, int nz, int maxM, int maxN, int splits, const int32_t* active,
+                            hipStream_t st);
+// Sum of those partials in FP64, stored as three BF16 parts in rows 3c .. 3c + 2 of O.
+hipError_t launch_gram_combine(const NtDesc* d_desc, int nz, int maxM, int maxN, int splits, const int32_t* active,
+                               hipStream_t st);
+// Split count of a BF16 Gram pass over K values of k (about 1024 values per split).
+int gram_bf16_splits(int K);
+int gram_bf16_rows_per_workgroup();
 hipError_t launch_finish(const FinDesc* d_desc, int nz, int maxM, int maxN, const int32_t* active,
                          hipStream_t st, int lanes_per_output = 1);
 hipError_t launch_gemm_nn_ex(bool p_f32, const NnDesc* d_desc, int nz, int maxMo, int maxN,
