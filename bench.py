@@ -1,17 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of randomized block-CG on one MI355X.
 
-Workload (default): the dense SPD system with d = 8192, lambda_i = i^-1.5,
+Headline workload: the dense SPD system with d = 8192, lambda_i = i^-1.5,
 mu = 1e-4, b ~ N(0, I) and a 8192 x 64 Gaussian block Omega, solved to a
 relative FP64 residual of 1e-10.  One step = one complete solve through the
 C ABI (rbcg_solve): the mixed-precision path (FP32 MFMA block products with
 FP32 accumulation, everything else FP64, FP64 iterative refinement).  The
 plain FP64 GPU solve of the same system is timed beside it.
 
+In the same run (sub-objects of the one JSON line, each timed with its own
+step count, skipped with --no-ridge / --no-batch):
+  ridge    the 64-shift ridge path, Z = G diag(exp(-j/400)) with n = 200000,
+           d = 4096, k = 128: BF16 products + FP64 refinement against FP64
+           products, with the HBM and MFMA rates of the BF16 Gram product;
+  batched  200 independent dense SPD systems of uneven d and k in one
+           batched call (FP64 products, and FP32 products + refinement)
+           against the same systems solved one call at a time in FP64.
+
 Printed (one JSON line): solves/s of the mixed path, the plain FP64 rate,
 the error of both against the FP64 oracle, the roofline of the dominant
 kernel (the block-product GEMM, timed with HIP events on the library's
-stream over the timed region), and the CPU oracle's rate on this host.
+stream over the timed region), the CPU oracle's rate on this host (with the
+CPU model and thread count), and the two sub-objects above.
 """
 from __future__ import annotations
 
@@ -67,6 +77,19 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    """Model name of the host CPU (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.lower().startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or None
+
+
 def a_err(A, mu, x, xref):
     import numpy as np
     e = x - xref
@@ -79,6 +102,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-ridge", action="store_true", help="default run: skip the ridge-path sub-object")
+    ap.add_argument("--no-batch", action="store_true", help="default run: skip the batched sub-object")
+    ap.add_argument("--sub-steps", type=int, default=2,
+                    help="default run: timed steps of the ridge and batched sub-objects")
     ap.add_argument("--workload", choices=["dense", "batch", "ridge", "sqrt"], default="dense",
                     help="dense: the d=8192 system (default); batch: uneven independent systems; "
                          "ridge: the 64-shift ridge path, n=200000, d=4096; sqrt: RBF sampling, 16384 points")
@@ -193,7 +220,7 @@ def main():
         err_mix = a_err(A, mu, xm, xo)
         err_64 = a_err(A, mu, x6, xo)
         cpu = {"value": 1.0 / t_cpu, "unit": "solves/s", "cores": int(threads or os.cpu_count() or 1),
-               "kind": "oracle",
+               "cpu_model": cpu_model(), "kind": "oracle",
                "sample": f"one full solve of the d=8192 k=64 system by the FP64 oracle (t={t_ref} block products, "
                          f"relres {rel_o:.2e}), {t_cpu:.1f}s"}
         log(f"oracle: {t_cpu:.1f}s, err mixed {err_mix:.2e}, err fp64 {err_64:.2e}")
@@ -233,10 +260,31 @@ def main():
         "speedup_mixed_vs_fp64": t_64 / t_mix,
         "cpu_baseline": cpu,
     }
+    # free the dense system before the sub-objects
+    del op, ctx, Ad, bd, omd, x_mix, x_64
+    torch.cuda.empty_cache()
+    if not args.no_ridge:
+        out["ridge"] = ridge_leg(args.sub_steps, 1)
+        torch.cuda.empty_cache()
+    if not args.no_batch:
+        out["batched"] = batch_leg(args.sub_steps, 1, args.nsys)
+        torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 
 def run_batch(args):
+    sub = batch_leg(args.steps, args.warmup, args.nsys)
+    out = {
+        "metric": "solves/s at 1e-8 rel A-norm err: mixed+batched vs plain FP64; HBM/MFMA % peak",
+        "value": sub["value"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sub["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic", "config": {"workload": sub.pop("workload"), "nsys": sub["nsys"]},
+    }
+    out.update({k: v for k, v in sub.items() if k not in ("value", "ms_per_step", "unit")})
+    print(json.dumps(out), flush=True)
+
+
+def batch_leg(steps, warmup, nsys):
     """Independent systems of uneven size: d ~ U{1000..16000}, lambda_i = i^-p with p ~ U[1, 3],
     mu = 10^U[-6, -2], k ~ U{8, 16, 32, 64, 128}; eigenbases from four Householder reflectors,
     formed on the GPU.  One step = all systems solved to rtol 1e-10 (FP64 products) by one batched
@@ -249,7 +297,7 @@ def run_batch(args):
 
     rtol, t_max = 1e-10, 64
     dev = torch.device("cuda:0")
-    params = synth.batch_params(5, args.nsys, 1000, 16000)
+    params = synth.batch_params(5, nsys, 1000, 16000)
     log(f"batch: forming {len(params)} systems on the GPU")
     t0 = time.time()
     ctx = rbcg.Context()
@@ -283,12 +331,12 @@ def run_batch(args):
             infos += info
         return rc, infos
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         batched()
         one_at_a_time()
     torch.cuda.synchronize()
     t_b = 0.0
-    for _ in range(args.steps):
+    for _ in range(steps):
         t1 = time.time()
         rc_b, info_b = batched()
         torch.cuda.synchronize()
@@ -297,14 +345,14 @@ def run_batch(args):
     batched(opts_mx)
     torch.cuda.synchronize()
     t_m = 0.0
-    for _ in range(args.steps):
+    for _ in range(steps):
         t1 = time.time()
         rc_m, info_m = batched(opts_mx)
         torch.cuda.synchronize()
         t_m += time.time() - t1
         log(f"batch: batched mixed call {time.time() - t1:.2f}s rc={rc_m}")
     t_1 = 0.0
-    for _ in range(args.steps):
+    for _ in range(steps):
         t1 = time.time()
         rc_1, info_1 = one_at_a_time()
         torch.cuda.synchronize()
@@ -312,37 +360,28 @@ def run_batch(args):
         log(f"batch: one at a time {time.time() - t1:.2f}s rc={rc_1}")
     loads = [i["matrix_loads"] for i in info_b]
     flops = sum(2.0 * p["d"] ** 2 * (p["k"] + 1) * i["matrix_loads"] for p, i in zip(params, info_b))
-    out = {
-        "metric": "solves/s at 1e-8 rel A-norm err: mixed+batched vs plain FP64; HBM/MFMA % peak",
-        "value": len(params) * args.steps / t_b,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * t_b / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"batch of {len(params)} independent dense SPD systems, d in [1000, 16000], "
-                               "lambda_i=i^-p p in [1,3], mu in [1e-6, 1e-2], k in {8..128}, rtol 1e-10, "
-                               "FP64 products, one batched call", "nsys": len(params), "gbytes": gb},
-        "one_at_a_time": {"value": len(params) * args.steps / t_1, "unit": "solves/s",
-                          "ms_per_step": 1e3 * t_1 / args.steps},
-        "batched_mixed": {"value": len(params) * args.steps / t_m, "unit": "solves/s",
-                          "ms_per_step": 1e3 * t_m / args.steps, "status": rc_m,
+    sub = {
+        "workload": f"batch of {len(params)} independent dense SPD systems, d in [1000, 16000], "
+                    "lambda_i=i^-p p in [1,3], mu in [1e-6, 1e-2], k in {8..128}, rtol 1e-10",
+        "nsys": len(params), "gbytes": gb, "steps": steps,
+        "value": len(params) * steps / t_b, "unit": "solves/s", "ms_per_step": 1e3 * t_b / steps,
+        "note": "value: FP64 products, one batched call",
+        "one_at_a_time": {"value": len(params) * steps / t_1, "unit": "solves/s",
+                          "ms_per_step": 1e3 * t_1 / steps, "note": "FP64 products, one call per system"},
+        "batched_mixed": {"value": len(params) * steps / t_m, "unit": "solves/s",
+                          "ms_per_step": 1e3 * t_m / steps, "status": rc_m,
                           "max_relres": max(i["relres"] for i in info_m),
                           "loads_total": sum(i["matrix_loads"] for i in info_m),
-                          "note": "FP32-MFMA products + FP64 refinement"},
+                          "note": "FP32-MFMA products + FP64 refinement, one batched call"},
         "speedup_batched_mixed_vs_one_at_a_time_fp64": t_1 / t_m,
         "speedup_batched_vs_one_at_a_time": t_1 / t_b,
         "status": {"batched": rc_b, "one_at_a_time": rc_1,
                    "max_relres": max(i["relres"] for i in info_b),
                    "loads_min_max": [min(loads), max(loads)]},
-        "block_product_tflops_avg": flops * args.steps / t_b / 1e12,
+        "block_product_tflops_avg": flops * steps / t_b / 1e12,
     }
-    print(json.dumps(out), flush=True)
+    del ops, Ads, bs, oms, ctx
+    return sub
 
 
 def _timed(fn, steps):
@@ -359,16 +398,34 @@ def _timed(fn, steps):
 
 
 def run_ridge(args):
+    sub = ridge_leg(args.steps, args.warmup)
+    out = {
+        "metric": "solves/s at 1e-8 rel A-norm err: mixed+batched vs plain FP64; HBM/MFMA % peak",
+        "value": sub["value"], "unit": sub["unit"], "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sub["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16-mfma+f64", "data": "synthetic",
+        "config": {"workload": sub.pop("workload"), "n": 200000, "d": 4096, "k": 128, "shifts": sub["shifts"]},
+    }
+    out.update({k: v for k, v in sub.items() if k not in ("value", "ms_per_step", "unit")})
+    print(json.dumps(out), flush=True)
+
+
+def ridge_leg(steps, warmup):
     """Ridge path: Z = G diag(exp(-j/400)) (n = 200000, d = 4096, FP32), 64 shifts log-spaced over
     [1e-6, 1], k = 128.  One step = the whole path: plain FP64 products at t = 32 (the Krylov space
-    is the whole space, 32 * 129 >= 4096), and BF16 products with FP64 refinement to rtol 2e-12."""
+    is the whole space, 32 * 129 >= 4096), and BF16 products with FP64 refinement to rtol 2e-12.
+    The BF16 Gram product's two passes (Y = Z X, then Z^T Y) are timed with HIP events on the
+    library's stream over the BF16 timed region."""
     import torch
 
     import synth
     from paper_2501_18717_amd import rbcg
 
-    log("ridge: generating Z (200000 x 4096, seeded)")
-    P = synth.ridge_problem(3, 200000, 4096, 128)
+    n, d, k = 200000, 4096, 128
+    log(f"ridge: generating Z ({n} x {d}, seeded)")
+    t0 = time.time()
+    P = synth.ridge_problem(3, n, d, k)
+    log(f"ridge: generated in {time.time() - t0:.1f}s")
     dev = torch.device("cuda:0")
     ctx = rbcg.Context()
     Zd = torch.from_numpy(P["Z"]).to(dev)
@@ -377,31 +434,46 @@ def run_ridge(args):
     bd = torch.from_numpy(P["b"]).to(dev)
     omd = torch.from_numpy(P["omega"]).to(dev)
     mus = list(P["mus"])
-    X = torch.zeros((len(mus), 4096), dtype=torch.float64, device=dev)
+    del P
+    X = torch.zeros((len(mus), d), dtype=torch.float64, device=dev)
     o64 = rbcg.opts(32)
     o16 = rbcg.opts(32, rtol=2e-12, matvec="bf16", refine_max=20)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         rbcg.path(ctx, op64, bd, omd, mus, X, o64, check=False)
         rbcg.path(ctx, op16, bd, omd, mus, X, o16, check=False)
-    t64, (rc64, i64) = _timed(lambda: rbcg.path(ctx, op64, bd, omd, mus, X, o64, check=False), args.steps)
-    log(f"ridge: fp64 {t64 / args.steps:.3f}s per path rc={rc64}")
-    t16, (rc16, i16) = _timed(lambda: rbcg.path(ctx, op16, bd, omd, mus, X, o16, check=False), args.steps)
-    log(f"ridge: bf16 {t16 / args.steps:.3f}s per path rc={rc16} sweeps {i16[0]['refine_sweeps']}")
-    out = {
-        "metric": "solves/s at 1e-8 rel A-norm err: mixed+batched vs plain FP64; HBM/MFMA % peak",
-        "value": len(mus) * args.steps / t16, "unit": "shift solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * t16 / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "bf16-mfma+f64", "data": "synthetic",
-        "config": {"workload": "ridge path n=200000 d=4096 k=128, 64 shifts in [1e-6, 1], BF16 Z with FP64 "
-                               "refinement to rtol 2e-12", "n": 200000, "d": 4096, "k": 128, "shifts": len(mus)},
-        "fp64_gpu": {"value": len(mus) * args.steps / t64, "unit": "shift solves/s",
-                     "ms_per_step": 1e3 * t64 / args.steps, "status": rc64, "loads": i64[0]["matrix_loads"],
+    t64, (rc64, i64) = _timed(lambda: rbcg.path(ctx, op64, bd, omd, mus, X, o64, check=False), steps)
+    log(f"ridge: fp64 {t64 / steps:.3f}s per path rc={rc64}")
+    ctx.profile(True)
+    t16, (rc16, i16) = _timed(lambda: rbcg.path(ctx, op16, bd, omd, mus, X, o16, check=False), steps)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    log(f"ridge: bf16 {t16 / steps:.3f}s per path rc={rc16} sweeps {i16[0]['refine_sweeps']}; product passes {prof}")
+    # one pass streams Z (BF16, 2 n d bytes) once: the algorithmic bytes; its MFMA work is 3 x 2 n d N flops
+    # (the right operand in three BF16 parts)
+    npass = max(prof["launches"], 1)
+    avg_ms = prof["ms"] / npass
+    gbs = prof["bytes"] / npass / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None
+    tfs = 3.0 * prof["flops"] / npass / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else None
+    sub = {
+        "workload": "ridge path n=200000 d=4096 k=128, 64 shifts in [1e-6, 1], BF16 Z with FP64 refinement to "
+                    "rtol 2e-12",
+        "shifts": len(mus), "steps": steps,
+        "value": len(mus) * steps / t16, "unit": "shift solves/s", "ms_per_step": 1e3 * t16 / steps,
+        "note": "value: BF16-MFMA products + FP64 refinement",
+        "fp64_gpu": {"value": len(mus) * steps / t64, "unit": "shift solves/s",
+                     "ms_per_step": 1e3 * t64 / steps, "status": rc64, "loads": i64[0]["matrix_loads"],
                      "relres_max": max(i["relres"] for i in i64)},
         "mixed": {"status": rc16, "refine_sweeps": i16[0]["refine_sweeps"], "loads": i16[0]["matrix_loads"],
                   "relres_max": max(i["relres"] for i in i16)},
         "speedup_mixed_vs_fp64": t64 / t16,
+        "gram_bf16_pass": {"kernel": "k_gram_bf16<9> (one pass over Z or Z^T, 16x16x32 BF16 MFMA)",
+                           "launches": prof["launches"], "avg_launch_ms": avg_ms,
+                           "algorithmic_bytes": prof["bytes"] / npass, "achieved_GBs": gbs,
+                           "hbm_frac": gbs / PEAK_HBM_GBS if gbs else None,
+                           "mfma_TFLOPs": tfs, "mfma_frac": tfs / PEAK_TFLOPS["bf16"] if tfs else None},
     }
-    print(json.dumps(out), flush=True)
+    del op64, op16, Zd, ctx
+    return sub
 
 
 def run_sqrt(args):

@@ -93,10 +93,13 @@ int rbcg_destroy(rbcg_ctx* ctx);
  * Dense:  A is d x d, row-major, FP64, leading dimension lda >= d, symmetric
  *         positive semi-definite (Sec. 1).  `lo` chooses which low-precision
  *         copy to build now: RBCG_F64 = none, RBCG_F32 = FP32 copy (RNE).
- * Gram:   A = Z^T Z with Z n x d row-major FP32, ldz >= d (Sec. 1, ridge
- *         regression).  The block product is Z^T (Z X) (two passes over Z).
- *         `lo` = RBCG_BF16 builds BF16 copies of Z and of Z^T (RNE);
- *         RBCG_F64 builds none (FP64 arithmetic on the FP32 values).
+ * Gram:   A = Z^T Z with Z n x d row-major FP32, ldz >= d, 1 <= n < 2^31,
+ *         1 <= d <= 2^21 (Sec. 1, ridge regression).  The block product is
+ *         Z^T (Z X) (two passes over Z).  The handle always holds an FP32
+ *         copy of Z^T (4 n d bytes), which the second pass of the FP64
+ *         products and residuals streams; `lo` = RBCG_BF16 also builds BF16
+ *         copies of Z and of Z^T (RNE); RBCG_F64 builds no further copy
+ *         (FP64 arithmetic on the FP32 values).
  */
 int rbcg_op_create_dense(rbcg_ctx* ctx, rbcg_op** op, int64_t d, const double* A /*device*/,
                          int64_t lda, int lo);

@@ -235,127 +235,6 @@ hipError_t launch_gemm_nn_ex(bool p_f32, const NnDesc* dd, int nz, int maxMo, in
 }
 
 // ---------------------------------------------------------------------------------------------
-// Tall NN update: O[b][i] = beta * Y[b][i] + alpha * sum_a C[a][b] P[a][i], i < N (long),
-// b < Mo (<= 144), a in this split's range.  Workgroup = 4 waves = 64 columns i (16 per wave),
-// all TB row tiles of b.  The C chunk (16 values of a x 16 TB values of b) is staged in LDS,
-// double-buffered and shared by the waves; each lane streams its 4 P values per chunk one chunk
-// ahead.  MFMA A operand = C^T (b x a) from LDS, B operand = P (a x i); D rows b, columns i.
-// ---------------------------------------------------------------------------------------------
-template <typename PT, int TB>
-__global__ __launch_bounds__(256) void k_nn_tall(const NnDesc* __restrict__ descs, int splits,
-                                                 const int32_t* __restrict__ act) {
-  constexpr int BW = 16 * TB;            // padded b range
-  constexpr int CS = BW + 2;             // LDS row stride (doubles)
-  const NnDesc d = descs[blockIdx.z];
-  if (!is_active(act, d.active)) return;
-  const int i0 = blockIdx.x * 64;
-  if (i0 >= d.N) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int q = lane >> 4, r16 = lane & 15;
-  const int i = i0 + 16 * wave + r16;
-  const bool ival = i < d.N;
-  const int s = blockIdx.y;
-  const int per = ((d.Ka + splits - 1) / splits + 15) / 16 * 16;
-  const int ab = s * per, ae = min(d.Ka, ab + per);
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* cs = (double*)smem_raw;        // [2][16][CS]
-  const gmem_t<const PT> P = gmem((const PT*)d.P.p);
-  auto load_p = [&](int a0, double* pv) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int a = a0 + 4 * e + q;
-      pv[e] = (ival && a < ae) ? (double)P[row_off(d.P, a) + i] : 0.0;
-    }
-  };
-  auto stage_c = [&](int a0, int buf) {
-    double* dst = cs + buf * 16 * CS;
-    for (int e = tid; e < 16 * BW; e += 256) {
-      const int r = e / BW, b = e - r * BW;
-      const int a = a0 + r;
-      dst[r * CS + b] = (a < ae && b < d.Mo) ? gmem(d.C)[(int64_t)a * d.ldc + b] : 0.0;
-    }
-  };
-  v4d acc[TB];
-#pragma unroll
-  for (int tb = 0; tb < TB; ++tb) acc[tb] = v4d{0, 0, 0, 0};
-  double pcur[4], pnext[4];
-  int buf = 0;
-  if (ab < ae) {
-    stage_c(ab, 0);
-    load_p(ab, pcur);
-  }
-  __syncthreads();
-  for (int a0 = ab; a0 < ae; a0 += 16) {
-    const bool more = a0 + 16 < ae;
-    if (more) {
-      load_p(a0 + 16, pnext);
-      stage_c(a0 + 16, buf ^ 1);
-    }
-    const double* cb = cs + buf * 16 * CS;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const double* crow = cb + (4 * e + q) * CS + r16;
-#pragma unroll
-      for (int tb = 0; tb < TB; ++tb)
-        acc[tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(crow[16 * tb], pcur[e], acc[tb], 0, 0, 0);
-    }
-    __syncthreads();
-    buf ^= 1;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) pcur[e] = pnext[e];
-  }
-  if (!ival) return;
-#pragma unroll
-  for (int tb = 0; tb < TB; ++tb) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int b = 16 * tb + q + 4 * r;
-      if (b >= d.Mo) continue;
-      const double v = acc[tb][r];
-      if (splits > 1) {
-        gmem(d.part)[((int64_t)s * d.Mo + b) * d.N + i] = v;
-      } else {
-        double out = d.alpha * v;
-        if (d.beta != 0.0) out += d.beta * gmem((const double*)d.Y.p)[row_off(d.Y, b) + i];
-        gmem((double*)d.O.p)[row_off(d.O, b) + i] = out;
-      }
-    }
-  }
-}
-
-template <typename PT, int TB>
-static hipError_t launch_nn_tall_t(const NnDesc* dd, int nz, int maxN, int splits, const int32_t* act,
-                                   hipStream_t st) {
-  const size_t lds = (size_t)2 * 16 * (16 * TB + 2) * 8;
-  hipLaunchKernelGGL((k_nn_tall<PT, TB>), dim3((maxN + 63) / 64, splits, nz), dim3(256), lds, st, dd, splits, act);
-  return hipGetLastError();
-}
-
-template <typename PT>
-static hipError_t dispatch_nn_tall(int tb, const NnDesc* dd, int nz, int maxN, int splits, const int32_t* act,
-                                   hipStream_t st) {
-  switch (tb) {
-    case 1: return launch_nn_tall_t<PT, 1>(dd, nz, maxN, splits, act, st);
-    case 2: return launch_nn_tall_t<PT, 2>(dd, nz, maxN, splits, act, st);
-    case 3: return launch_nn_tall_t<PT, 3>(dd, nz, maxN, splits, act, st);
-    case 4: return launch_nn_tall_t<PT, 4>(dd, nz, maxN, splits, act, st);
-    case 5: return launch_nn_tall_t<PT, 5>(dd, nz, maxN, splits, act, st);
-    case 6: return launch_nn_tall_t<PT, 6>(dd, nz, maxN, splits, act, st);
-    case 7: case 8: return launch_nn_tall_t<PT, 8>(dd, nz, maxN, splits, act, st);
-    case 9: return launch_nn_tall_t<PT, 9>(dd, nz, maxN, splits, act, st);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-hipError_t launch_nn_tall(bool p_f32, const NnDesc* dd, int nz, int maxMo, int maxN, int splits, const int32_t* act,
-                          hipStream_t st) {
-  const int tb = (maxMo + 15) / 16;
-  if (tb < 1 || tb > 9 || splits < 1) return hipErrorInvalidValue;
-  return p_f32 ? dispatch_nn_tall<float>(tb, dd, nz, maxN, splits, act, st)
-               : dispatch_nn_tall<double>(tb, dd, nz, maxN, splits, act, st);
-}
-
-// ---------------------------------------------------------------------------------------------
 // Cholesky QR factor of a small Gram matrix with rank-revealing pivoting (one workgroup per
 // problem).  See QrDesc.  The pivot at each step is the column with the largest remaining
 // Schur-complement diagonal relative to its own squared norm, so the factor is rank revealing;
@@ -1099,10 +978,14 @@ __global__ __launch_bounds__(1024) void k_tri_refine(const TriDesc* __restrict__
   double* y = (double*)smem_raw;   // n
   double* R = y + n;               // n: residual, eliminated right-hand side, correction
   double* tmp = R + n;             // 1024 + m
-  for (int e = tid; e < n; e += 1024) y[e] = d.Y[(int64_t)e * d.ldy];
+  const bool apply = d.refine == 2;   // Y = (T + sigma I)^{-1} rhs for a right-hand side over all t blocks
+  for (int e = tid; e < n; e += 1024) {
+    y[e] = apply ? 0.0 : d.Y[(int64_t)e * d.ldy];
+    if (apply) R[e] = d.mask[e] ? 0.0 : d.rhs[(int64_t)e * d.ld_rhs];
+  }
   __syncthreads();
   // band part
-  for (int e = tid; e < n; e += 1024) {
+  for (int e = tid; e < n && !apply; e += 1024) {
     const int i = e / m, a = e - i * m;
     const int32_t* mk = d.mask + (int64_t)i * m;
     if (mk[a]) {
@@ -1138,7 +1021,7 @@ __global__ __launch_bounds__(1024) void k_tri_refine(const TriDesc* __restrict__
   }
   __syncthreads();
   // off-band part, one block column j at a time
-  if (d.Hoff) {
+  if (d.Hoff && !apply) {
     const int slices = 1024 / m;
     for (int j = 2; j < t; ++j) {
       const double* H = d.Hoff + hoff_offset(j, m);   // rows of blocks 0 .. j - 2 (x m columns)
@@ -1361,27 +1244,51 @@ hipError_t launch_convert(const CvtDesc* dd, int nz, int maxRows, int maxCols, c
 }
 
 // Transpose-convert an FP32 matrix (rows x cols, ld) into BF16 (cols x rows, ldt).
-__global__ __launch_bounds__(256) void k_transpose_bf16(const float* __restrict__ src, int64_t ld, int rows, int cols,
-                                                        unsigned short* __restrict__ dst, int64_t ldt) {
+// dst[c][r] = src[r][c] for a rows x cols FP32 matrix, stored as BF16 (OutBf16) or FP32; 32 x 32
+// tiles through LDS, row tiles on grid x (up to 2^31 rows), column tiles on grid y.
+template <bool OutBf16>
+__global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ src, int64_t ld, int rows, int cols,
+                                                   void* __restrict__ dstv, int64_t ldt) {
   __shared__ float tile[32][33];
-  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int64_t r0 = (int64_t)blockIdx.x * 32;
+  const int c0 = blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int y = ty; y < 32; y += 8) {
-    const int rr = r0 + y, cc = c0 + tx;
-    tile[y][tx] = (rr < rows && cc < cols) ? src[(int64_t)rr * ld + cc] : 0.f;
+    const int64_t rr = r0 + y;
+    const int cc = c0 + tx;
+    tile[y][tx] = (rr < rows && cc < cols) ? src[rr * ld + cc] : 0.f;
   }
   __syncthreads();
   for (int y = ty; y < 32; y += 8) {
-    const int cc = c0 + y, rr = r0 + tx;
-    if (cc < cols && rr < rows) dst[(int64_t)cc * ldt + rr] = f32_to_bf16(tile[tx][y]);
+    const int cc = c0 + y;
+    const int64_t rr = r0 + tx;
+    if (cc >= cols || rr >= rows) continue;
+    if constexpr (OutBf16)
+      ((unsigned short*)dstv)[(int64_t)cc * ldt + rr] = f32_to_bf16(tile[tx][y]);
+    else
+      ((float*)dstv)[(int64_t)cc * ldt + rr] = tile[tx][y];
   }
+}
+
+static hipError_t launch_transpose(bool bf16, const float* src, int64_t ld, int rows, int cols, void* dst, int64_t ldt,
+                                   hipStream_t st) {
+  if (rows < 1 || cols < 1 || (cols + 31) / 32 > 65535) return hipErrorInvalidValue;
+  dim3 grid((rows + 31) / 32, (cols + 31) / 32);
+  if (bf16)
+    hipLaunchKernelGGL(k_transpose<true>, grid, dim3(256), 0, st, src, ld, rows, cols, dst, ldt);
+  else
+    hipLaunchKernelGGL(k_transpose<false>, grid, dim3(256), 0, st, src, ld, rows, cols, dst, ldt);
+  return hipGetLastError();
 }
 
 hipError_t launch_transpose_bf16(const float* src, int64_t ld, int rows, int cols, unsigned short* dst, int64_t ldt,
                                  hipStream_t st) {
-  dim3 grid((cols + 31) / 32, (rows + 31) / 32);
-  hipLaunchKernelGGL(k_transpose_bf16, grid, dim3(256), 0, st, src, ld, rows, cols, dst, ldt);
-  return hipGetLastError();
+  return launch_transpose(true, src, ld, rows, cols, dst, ldt, st);
+}
+
+hipError_t launch_transpose_f32(const float* src, int64_t ld, int rows, int cols, float* dst, int64_t ldt,
+                                hipStream_t st) {
+  return launch_transpose(false, src, ld, rows, cols, dst, ldt, st);
 }
 
 // ---------------------------------------------------------------------------------------------

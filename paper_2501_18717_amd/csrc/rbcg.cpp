@@ -90,6 +90,8 @@ struct rbcg_op {
   int64_t ld_lo = 0;
   void* lot = nullptr;      // gram: BF16 Z^T (d x ld_lot)
   int64_t ld_lot = 0;
+  void* zt = nullptr;       // gram: FP32 Z^T (d x ld_zt), for the FP64 products and residuals
+  int64_t ld_zt = 0;
   int device = 0;
 };
 
@@ -269,7 +271,7 @@ extern "C" int rbcg_op_create_dense(rbcg_ctx* ctx, rbcg_op** out, int64_t d, con
 
 extern "C" int rbcg_op_create_gram(rbcg_ctx* ctx, rbcg_op** out, int64_t n, int64_t d, const float* Z, int64_t ldz,
                                    int lo) {
-  if (!ctx || !out || !Z || d < 1 || n < 1 || ldz < d || n > (int64_t)1 << 31 || d > (int64_t)1 << 30)
+  if (!ctx || !out || !Z || d < 1 || n < 1 || ldz < d || n > INT32_MAX || d > (int64_t)1 << 21)
     return RBCG_ERR_INVALID_ARG;
   if (lo != RBCG_F64 && lo != RBCG_BF16) return RBCG_ERR_INVALID_ARG;
   *out = nullptr;
@@ -281,13 +283,35 @@ extern "C" int rbcg_op_create_gram(rbcg_ctx* ctx, rbcg_op** out, int64_t n, int6
   op->ld = ldz;
   op->lo_t = lo;
   op->device = ctx->device;
+  auto drop = [&]() {
+    if (op->lo) (void)hipFree(op->lo);
+    if (op->lot) (void)hipFree(op->lot);
+    if (op->zt) (void)hipFree(op->zt);
+    delete op;
+  };
+  op->ld_zt = round_up(n, 64);
+  if (hipMalloc(&op->zt, (size_t)d * op->ld_zt * 4) != hipSuccess) {
+    op->zt = nullptr;
+    drop();
+    return RBCG_ERR_OOM;
+  }
+  hipError_t e = launch_transpose_f32(Z, ldz, (int)n, (int)d, (float*)op->zt, op->ld_zt, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    drop();
+    return fail_hip(e, "gram FP32 transpose");
+  }
   if (lo == RBCG_BF16) {
     op->ld_lo = round_up(d, 64);
     op->ld_lot = round_up(n, 64);
-    if (hipMalloc(&op->lo, (size_t)n * op->ld_lo * 2) != hipSuccess) { delete op; return RBCG_ERR_OOM; }
+    if (hipMalloc(&op->lo, (size_t)n * op->ld_lo * 2) != hipSuccess) {
+      op->lo = nullptr;
+      drop();
+      return RBCG_ERR_OOM;
+    }
     if (hipMalloc(&op->lot, (size_t)d * op->ld_lot * 2) != hipSuccess) {
-      (void)hipFree(op->lo);
-      delete op;
+      op->lot = nullptr;
+      drop();
       return RBCG_ERR_OOM;
     }
     CvtDesc h{};
@@ -299,7 +323,7 @@ extern "C" int rbcg_op_create_gram(rbcg_ctx* ctx, rbcg_op** out, int64_t n, int6
     h.dst_t = DT_BF16;
     h.active = -1;
     CvtDesc* dd = nullptr;
-    hipError_t e = hipMalloc(&dd, sizeof(CvtDesc));
+    e = hipMalloc(&dd, sizeof(CvtDesc));
     if (e == hipSuccess) e = hipMemcpy(dd, &h, sizeof h, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_convert(dd, 1, (int)n, (int)d, nullptr, ctx->stream);
     if (e == hipSuccess)
@@ -307,9 +331,7 @@ extern "C" int rbcg_op_create_gram(rbcg_ctx* ctx, rbcg_op** out, int64_t n, int6
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (dd) (void)hipFree(dd);
     if (e != hipSuccess) {
-      (void)hipFree(op->lo);
-      (void)hipFree(op->lot);
-      delete op;
+      drop();
       return fail_hip(e, "gram lo copies");
     }
   }
@@ -321,6 +343,7 @@ extern "C" int rbcg_op_destroy(rbcg_op* op) {
   if (!op) return RBCG_ERR_INVALID_ARG;
   if (op->lo) (void)hipFree(op->lo);
   if (op->lot) (void)hipFree(op->lot);
+  if (op->zt) (void)hipFree(op->zt);
   delete op;
   return RBCG_OK;
 }
@@ -374,7 +397,8 @@ struct MvGroup {
   int64_t ld_xlo = 0;
   void* ylo = nullptr;       // gram: three-part BF16 copy of Z X (3N x ld_ylo)
   int64_t ld_ylo = 0;
-  double* ys = nullptr;      // gram FP64: Z X (n x N)
+  double* ys = nullptr;      // gram FP64: Z X of one column chunk (row c, element i; <= 144 rows)
+  int64_t ld_ys = 0;
   double* part = nullptr;
   size_t part_elems = 0;
   int splits2 = 1;           // splits of the second gram pass (or of the dense product)
@@ -385,6 +409,7 @@ struct Engine {
   std::vector<Prob> P;
   std::vector<MvGroup> Gs;
   int t_max = 1;
+  int t_run = 0;                // run_steps: step limit below t_max when > 0
   int maxm = 1;
   double eta2 = 1e-20, tau = 1e-15;
   int32_t* active = nullptr;    // device, per problem
@@ -404,14 +429,16 @@ static int pick_splits(int tiles, int nz, int K) {
   return std::max(1, std::min(want, std::min(cap, 256)));
 }
 
-// Splits of the tall NN update (64 output columns per workgroup): about 768 workgroups, at
-// least 64 values of the reduction index per split.
-static int nn_splits(int N, int Ka, int nz) {
-  const int tiles = (N + 63) / 64;
-  const int want = std::max(1, 768 / std::max(1, tiles * nz));
-  const int cap = std::max(1, Ka / 64);
-  return std::max(1, std::min(want, std::min(cap, 64)));
+// FP64 Gram product: row stride of the rows of Z X (16-byte rows for the tall kernel's loads), and
+// the splits of its second pass W = Z^T (Z X) over n: about 2048 workgroups of 64 rows of W, at
+// least 1024 values of n per split.
+static int64_t gram_ys_ld(const rbcg_op* op) { return round_up(op->n, 2); }
+static int gram64_splits(int d, int64_t n) {
+  const int tiles = (d + 63) / 64;
+  int s = std::min(64, std::max(1, 2048 / tiles));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(s, n / 1024));
 }
+
 
 // Splits of the projection products [Q_0..Q_j W]^T W on the tall kernel (64-row tiles):
 // about 256 workgroups, at least 128 values of k per split.  More splits fill more of the chip
@@ -547,8 +574,6 @@ static hipError_t enqueue(const Launch& L, unsigned char* dbase, const int32_t* 
                                L.a3, act, st);
     case Launch::FIN: return launch_finish(dptr<FinDesc>(dbase, L.off), L.nz, L.a1, L.a2, act, st, std::max(1, L.a3));
     case Launch::NN:
-      if (L.a0 & (1 << 9))
-        return launch_nn_tall(L.flag, dptr<NnDesc>(dbase, L.off), L.nz, L.a1, L.a2, L.a3, act, st);
       return launch_gemm_nn_ex(L.flag, dptr<NnDesc>(dbase, L.off), L.nz, L.a1, L.a2, act, st);
     case Launch::QR: return launch_qr_factor(dptr<QrDesc>(dbase, L.off), L.nz, L.a1, L.flag, act, st);
     case Launch::DIAG: return launch_diag(dptr<DiagDesc>(dbase, L.off), L.nz, L.a1, act, st);
@@ -1156,69 +1181,75 @@ static void add_matvec(Program& pg, std::vector<Launch>& out, Engine& E, int j) 
           out.push_back(F);
         }
       } else {
-        // FP64 arithmetic on the FP32 values of Z: ys = Z X (n x N row-major), W = Z^T ys
-        NtDesc n1{};
-        n1.P = plain_rows(op->data, op->ld);
-        n1.X = Xb;
-        n1.M = n;
-        n1.N = G.N;
-        n1.K = d;
-        n1.active = act_idx;
-        n1.out = G.ys;
-        n1.ldo = G.N;
-        Launch L1{Launch::NT};
-        L1.off = pg.stg.add(std::vector<NtDesc>{n1});
-        L1.nz = 1;
-        L1.a0 = DT_F32F64;   // FP32 P, FP64 arithmetic
-        if (G.N <= 144 && op->ld % 4 == 0 && ((uintptr_t)op->data % 16) == 0)
-          L1.a0 |= (1 << 9) | (1 << 10);   // tall kernel, 16-byte rows of Z
-        L1.a1 = n;
-        L1.a2 = G.N;
-        L1.a3 = 1;
-        out.push_back(L1);
-        NnDesc nn{};
-        nn.P = plain_rows(op->data, op->ld);
-        nn.C = G.ys;
-        nn.ldc = G.N;
-        nn.Y = Wb;
-        nn.O = Wb;
-        nn.alpha = 1.0;
-        nn.beta = 0.0;
-        nn.Ka = n;
-        nn.Mo = G.N;
-        nn.N = d;
-        nn.active = act_idx;
-        nn.part = G.part;
-        Launch L2{Launch::NN};
-        L2.off = pg.stg.add(std::vector<NnDesc>{nn});
-        L2.nz = 1;
-        L2.flag = true;
-        L2.a1 = G.N;
-        L2.a2 = d;
-        const bool tall = G.N <= 144;
-        if (tall) {
-          L2.a0 = 1 << 9;
+        // FP64 arithmetic on the FP32 values of Z, per column chunk of at most 144 vectors, both
+        // passes on the tall block-product kernel: Y = Z X into rows of ys (row c, element i),
+        // then W = Z^T Y from the transposed FP32 copy of Z, split over n with the FP64 partials
+        // summed by the finish kernel
+        const bool pv1 = op->ld % 4 == 0 && ((uintptr_t)op->data % 16) == 0;
+        const int nch = (G.N + 143) / 144;
+        const int cw = (G.N + nch - 1) / nch;
+        for (int c0 = 0; c0 < G.N; c0 += cw) {
+          const int nc = std::min(cw, G.N - c0);
+          NtDesc n1{};
+          n1.P = plain_rows(op->data, op->ld);
+          n1.X = plain_rows((const double*)Xb.p + (size_t)c0 * Xb.ld, Xb.ld);
+          n1.M = n;
+          n1.N = nc;
+          n1.K = d;
+          n1.active = act_idx;
+          n1.O = plain_rows(G.ys, G.ld_ys);
+          n1.out = nullptr;
+          n1.out_t = DT_F64;
+          Launch L1{Launch::NT};
+          L1.off = pg.stg.add(std::vector<NtDesc>{n1});
+          L1.nz = 1;
+          L1.a0 = DT_F32F64 | (1 << 9) | (pv1 ? (1 << 10) : 0);   // FP32 P, FP64 arithmetic
+          L1.a1 = n;
+          L1.a2 = nc;
+          L1.a3 = 1;
+          L1.prof = true;
+          L1.flops = 2.0 * n * (double)d * nc;
+          L1.bytes = 4.0 * n * (double)d;
+          out.push_back(L1);
+          NtDesc n2{};
+          n2.P = plain_rows(op->zt, op->ld_zt);
+          n2.X = plain_rows(G.ys, G.ld_ys);
+          n2.M = d;
+          n2.N = nc;
+          n2.K = n;
+          n2.active = act_idx;
+          n2.part = G.part;
+          n2.O = plain_rows((const double*)Wb.p + (size_t)c0 * Wb.ld, Wb.ld);
+          n2.out = nullptr;
+          n2.out_t = DT_F64;
+          Launch L2{Launch::NT};
+          L2.off = pg.stg.add(std::vector<NtDesc>{n2});
+          L2.nz = 1;
+          L2.a0 = DT_F32F64 | (1 << 9) | (1 << 10);
+          L2.a1 = d;
+          L2.a2 = nc;
           L2.a3 = G.splits2;
-        }
-        out.push_back(L2);
-        if (tall && G.splits2 > 1) {
-          FinDesc f{};
-          f.part = G.part;
-          f.M = d;
-          f.N = G.N;
-          f.splits = G.splits2;
-          f.mode = FIN_AXPBY;
-          f.O = Wb;
-          f.rhs = Wb;
-          f.alpha = 1.0;
-          f.beta = 0.0;
-          f.active = act_idx;
-          Launch F{Launch::FIN};
-          F.off = pg.stg.add(std::vector<FinDesc>{f});
-          F.nz = 1;
-          F.a1 = d;
-          F.a2 = G.N;
-          out.push_back(F);
+          L2.prof = true;
+          L2.flops = 2.0 * n * (double)d * nc;
+          L2.bytes = 4.0 * n * (double)d;
+          out.push_back(L2);
+          if (G.splits2 > 1) {
+            FinDesc f{};
+            f.part = G.part;
+            f.M = d;
+            f.N = nc;
+            f.splits = G.splits2;
+            f.mode = FIN_TRANS;
+            f.O = n2.O;
+            f.alpha = 1.0;
+            f.active = act_idx;
+            Launch F{Launch::FIN};
+            F.off = pg.stg.add(std::vector<FinDesc>{f});
+            F.nz = 1;
+            F.a1 = d;
+            F.a2 = nc;
+            out.push_back(F);
+          }
         }
       }
     }
@@ -1437,8 +1468,8 @@ static void size_partials(Engine& E, const rbcg_ctx* ctx) {
     int tiles = (d + 15) / 16, t2w = 0, new_ = 0;
     int Kp = (G.op->kind == RBCG_OP_GRAM && G.mv_t == RBCG_BF16) ? (int)G.op->n : d;
     if (G.op->kind == RBCG_OP_GRAM && G.mv_t != RBCG_BF16) {
-      // FP64 path: the second product W = Z^T (Z X) on the tall NN kernel (widths <= 144)
-      G.splits2 = G.N <= 144 ? nn_splits(d, (int)G.op->n, 1) : 1;
+      // FP64 path: the second pass W = Z^T (Z X) on the tall kernel, split over n
+      G.splits2 = gram64_splits(d, G.op->n);
     } else if (G.op->kind == RBCG_OP_DENSE && G.mv_t == RBCG_F32 && wide_shape(G.N, &t2w, &new_)) {
       G.splits2 = wide_splits(d, G.N);
     } else if (G.op->kind == RBCG_OP_DENSE) {   // tall kernels (wider groups run in column chunks)
@@ -1506,7 +1537,8 @@ static void carve(Arena& ar, Engine& E) {
       G.ld_ylo = round_up(G.op->n, 64);
       G.ylo = ar.take<unsigned short>((size_t)3 * G.N * G.ld_ylo);
     } else if (G.op->kind == RBCG_OP_GRAM) {
-      G.ys = ar.take<double>((size_t)G.op->n * G.N);
+      G.ld_ys = gram_ys_ld(G.op);
+      G.ys = ar.take<double>((size_t)G.ld_ys * std::min(G.N, 144));
     }
     G.part = G.part_elems ? ar.take<double>(G.part_elems) : nullptr;
     for (int i = 0; i < G.count; ++i) {
@@ -1630,7 +1662,8 @@ static int run_steps(rbcg_ctx* ctx, Engine& E, Program& pg, unsigned char* dbase
     return e;
   };
   int j = 0;
-  for (; j < E.t_max; ++j) {
+  const int tlim = E.t_run > 0 ? std::min(E.t_run, E.t_max) : E.t_max;
+  for (; j < tlim; ++j) {
     const auto& steps = pg.steps[j + 1];
     const int pe = (int)pg.prod_end.size() > j + 1 ? pg.prod_end[j + 1] : 0;
     bool marked = false;
@@ -1732,9 +1765,10 @@ static ResidPlan plan_resid(const rbcg_op* op, int rows) {
     rp.splits = pick_splits((d + 15) / 16, 1, d);
     rp.part_elems = (size_t)rp.splits * rows * d;
   } else {
-    rp.splits = 0;
-    rp.part_elems = 0;
-    rp.ys_elems = (size_t)op->n * rows;
+    // the residual epilogue needs split partials: at least two splits
+    rp.splits = std::max(2, gram64_splits(d, op->n));
+    rp.part_elems = (size_t)rp.splits * d * std::min(rows, 144);
+    rp.ys_elems = (size_t)gram_ys_ld(op) * std::min(rows, 144);
   }
   return rp;
 }
@@ -1778,49 +1812,62 @@ static int residual(rbcg_ctx* ctx, const rbcg_op* op, int rows, RowOp rhs, RowOp
     HIP_TRY(launch_finish(dptr<FinDesc>(dscratch, o2), 1, d, rows, nullptr, st));
     return RBCG_OK;
   }
-  // gram: ys = Z X (n x rows), R = rhs - mu X, R -= Z^T ys
+  // gram, per chunk of at most 144 rows: ys = Z X (row c, element i), then R = rhs - mu X - Z^T ys
+  // with the second pass split over n (FP64 arithmetic on the FP32 values of Z and Z^T)
   const int n = (int)op->n;
-  NtDesc n1{};
-  n1.P = plain_rows(op->data, op->ld);
-  n1.X = X;
-  n1.M = n;
-  n1.N = rows;
-  n1.K = d;
-  n1.active = -1;
-  n1.out = ys;
-  n1.ldo = rows;
-  FinDesc f{};
-  f.part = nullptr;
-  f.M = d;
-  f.N = rows;
-  f.splits = 0;
-  f.mode = FIN_RESID;
-  f.O = R;
-  f.rhs = rhs;
-  f.xin = X;
-  f.mu = mu_dev;
-  f.alpha = 1.0;
-  f.active = -1;
-  NnDesc nn{};
-  nn.P = plain_rows(op->data, op->ld);
-  nn.C = ys;
-  nn.ldc = rows;
-  nn.Y = R;
-  nn.O = R;
-  nn.alpha = -1.0;
-  nn.beta = 1.0;
-  nn.Ka = n;
-  nn.Mo = rows;
-  nn.N = d;
-  nn.active = -1;
-  const size_t o1 = stg.add(std::vector<NtDesc>{n1});
-  const size_t o2 = stg.add(std::vector<FinDesc>{f});
-  const size_t o3 = stg.add(std::vector<NnDesc>{nn});
+  const int64_t ldy = gram_ys_ld(op);
+  const bool pv1 = op->ld % 4 == 0 && ((uintptr_t)op->data % 16) == 0;
+  auto rows_from = [](RowOp o, int c0) {   // plain row operands: rows c0, c0 + 1, ...
+    o.p = (const double*)o.p + (int64_t)c0 * o.ld;
+    return o;
+  };
+  const int nch = (rows + 143) / 144;
+  const int cw = (rows + nch - 1) / nch;
+  std::vector<size_t> offs;
+  for (int c0 = 0; c0 < rows; c0 += cw) {
+    const int nc = std::min(cw, rows - c0);
+    NtDesc n1{};
+    n1.P = plain_rows(op->data, op->ld);
+    n1.X = rows_from(X, c0);
+    n1.M = n;
+    n1.N = nc;
+    n1.K = d;
+    n1.active = -1;
+    n1.O = plain_rows(ys, ldy);
+    n1.out = nullptr;
+    n1.out_t = DT_F64;
+    NtDesc n2{};
+    n2.P = plain_rows(op->zt, op->ld_zt);
+    n2.X = plain_rows(ys, ldy);
+    n2.M = d;
+    n2.N = nc;
+    n2.K = n;
+    n2.active = -1;
+    n2.part = part;
+    FinDesc f{};
+    f.part = part;
+    f.M = d;
+    f.N = nc;
+    f.splits = rp.splits;
+    f.mode = FIN_RESID;
+    f.O = rows_from(R, c0);
+    f.rhs = rows_from(rhs, c0);
+    f.xin = rows_from(X, c0);
+    f.mu = mu_dev + c0;
+    f.alpha = 1.0;
+    f.active = -1;
+    offs.push_back(stg.add(std::vector<NtDesc>{n1}));
+    offs.push_back(stg.add(std::vector<NtDesc>{n2}));
+    offs.push_back(stg.add(std::vector<FinDesc>{f}));
+  }
   int rc = upload(ctx, stg, dscratch);
   if (rc) return rc;
-  HIP_TRY(launch_gemm_nt_ex(3, 0, false, dptr<NtDesc>(dscratch, o1), 1, n, rows, 1, nullptr, st));
-  HIP_TRY(launch_finish(dptr<FinDesc>(dscratch, o2), 1, d, rows, nullptr, st));
-  HIP_TRY(launch_gemm_nn_ex(true, dptr<NnDesc>(dscratch, o3), 1, rows, d, nullptr, st));
+  for (int c0 = 0, q = 0; c0 < rows; c0 += cw, q += 3) {
+    const int nc = std::min(cw, rows - c0);
+    HIP_TRY(mv_f32f64((nc + 15) / 16, pv1, dptr<NtDesc>(dscratch, offs[q]), 1, n, 1, nullptr, st));
+    HIP_TRY(mv_f32f64((nc + 15) / 16, true, dptr<NtDesc>(dscratch, offs[q + 1]), 1, d, rp.splits, nullptr, st));
+    HIP_TRY(launch_finish(dptr<FinDesc>(dscratch, offs[q + 2]), 1, d, nc, nullptr, st));
+  }
   return RBCG_OK;
 }
 
@@ -1903,7 +1950,8 @@ static int op_apply_impl(rbcg_ctx* ctx, const rbcg_op* op, int64_t N, const doub
       G.ld_ylo = round_up(op->n, 64);
       G.ylo = a.take<unsigned short>((size_t)3 * G.N * G.ld_ylo);
     } else if (op->kind == RBCG_OP_GRAM) {
-      G.ys = a.take<double>((size_t)op->n * G.N);
+      G.ld_ys = gram_ys_ld(op);
+      G.ys = a.take<double>((size_t)G.ld_ys * std::min(G.N, 144));
     }
     G.part = G.part_elems ? a.take<double>(G.part_elems) : nullptr;
   };
@@ -2433,6 +2481,11 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
   if (refine && opts->refine_max > 1 && L + 1 > m) return RBCG_ERR_UNSUPPORTED;
   hipStream_t st = ctx->stream;
   const int d = (int)op->d;
+  // Low-precision products whose first Krylov space can span R^d (t_max m >= d): that space is
+  // built out to the whole space and the refinement corrections reuse it (recycled steps below)
+  const int t_full = (d + m - 1) / m;
+  const bool recycle = refine && opts->matvec != RBCG_F64 && t_full <= opts->t_max && opts->refine_max > 1 &&
+                       L <= 144;
   Engine E;
   E.t_max = opts->t_max;
   E.eta2 = opts->eta > 0 ? opts->eta * opts->eta : 1e-20;
@@ -2467,7 +2520,8 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
   const int64_t ldv = pr.ldv;
   const size_t T = (size_t)E.t_max;
   const size_t mm = (size_t)m * m;
-  double *Rbuf, *Rcmp, *rpart, *rys, *mu_dev, *sq_dev, *Lws, *Xws, *Zws, *Yall, *Bhat;
+  const int64_t ldcc = round_up((int64_t)T * m, 2);
+  double *Rbuf, *Rcmp, *rpart, *rys, *mu_dev, *sq_dev, *Lws, *Xws, *Zws, *Yall, *Bhat, *Ccoef;
   unsigned char* dscr;
   int32_t* failL;
   auto carve_all = [&](Arena& a) {
@@ -2483,6 +2537,7 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
     Zws = a.take<double>(L * (T + 1) * m);
     Yall = a.take<double>(T * m * L);
     Bhat = a.take<double>((size_t)L * m);
+    Ccoef = a.take<double>(recycle ? (size_t)L * ldcc : 1);
     failL = a.take<int32_t>(L);
     dscr = a.take<unsigned char>(1 << 20);
   };
@@ -2520,7 +2575,58 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
   // right-hand sides
   std::vector<int> act_l;
   for (int64_t l = 0; l < L; ++l) act_l.push_back((int)l);
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+  // residuals of the shifts in act_l, in that order, into the rows of Rcmp
+  auto gather = [&]() -> int {
+    Staging gs;
+    std::vector<CopyDesc> gat;
+    for (size_t j = 0; j < act_l.size(); ++j) {
+      CopyDesc g{};
+      g.src = plain_rows(Rbuf + (size_t)act_l[j] * ldv, ldv);
+      g.dst = plain_rows(Rcmp + j * ldv, ldv);
+      g.alpha = 1.0;
+      g.rows = 1;
+      g.rows_total = 1;
+      g.n = d;
+      g.active = -1;
+      gat.push_back(g);
+    }
+    const size_t og = gs.add(gat);
+    int r = upload(ctx, gs, dscr);
+    if (r) return r;
+    HIP_TRY(launch_copy(dptr<CopyDesc>(dscr, og), (int)act_l.size(), 1, d, nullptr, st));
+    return RBCG_OK;
+  };
+  // FP64 residuals of all shifts, their norms, and the shifts still above rtol
+  auto check_residuals = [&](bool* all_out) -> int {
+    int r = residual(ctx, op, (int)L, RowOp{b, 0, 0, 0x3fffffff, 0}, plain_rows(X, d), plain_rows(Rbuf, ldv), mu_dev,
+                     rp, rpart, rys, dscr);
+    if (r) return r;
+    r = sqnorms(ctx, plain_rows(Rbuf, ldv), (int)L, d, sq_dev, host_sq, dscr);
+    if (r) return r;
+    bool all = true;
+    std::vector<int> next_l;
+    for (int64_t l = 0; l < L; ++l) {
+      relres[l] = std::sqrt(host_sq[l]) / bnorm;
+      if (refine && !(relres[l] <= opts->rtol)) {
+        all = false;
+        next_l.push_back((int)l);
+      }
+    }
+    if (!next_l.empty()) act_l = next_l;
+    *all_out = all;
+    return RBCG_OK;
+  };
+  auto debug_line = [&](const char* what, int sweep, int t, double target) {
+    if (!std::getenv("RBCG_DEBUG")) return;
+    double rlo = relres[0], rhi = relres[0];
+    for (int64_t l = 1; l < L; ++l) {
+      rlo = std::min(rlo, relres[l]);
+      rhi = std::max(rhi, relres[l]);
+    }
+    std::fprintf(stderr, "rbcg_path: %s %d t %d target %.1e relres [%.2e, %.2e] (smallest shift %.2e)\n", what, sweep,
+                 t, target, rlo, rhi, relres[l_min]);
+  };
+  for (int sweep = 0; sweeps < max_sweeps; ++sweep) {
     std::vector<CopyDesc> cps;
     int nstart;
     const int La = (int)act_l.size();
@@ -2557,25 +2663,8 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
     } else {
       // [R_act, Omega[0 : m - La]]: the residual of every shift still being corrected is in the
       // start block (gathered into Rcmp first: the Gaussian refill reads them there too)
-      {
-        Staging gs;
-        std::vector<CopyDesc> gat;
-        for (int j = 0; j < La; ++j) {
-          CopyDesc g{};
-          g.src = plain_rows(Rbuf + (size_t)act_l[j] * ldv, ldv);
-          g.dst = plain_rows(Rcmp + (size_t)j * ldv, ldv);
-          g.alpha = 1.0;
-          g.rows = 1;
-          g.rows_total = 1;
-          g.n = d;
-          g.active = -1;
-          gat.push_back(g);
-        }
-        const size_t og = gs.add(gat);
-        rc = upload(ctx, gs, dscr);
-        if (rc) return rc;
-        HIP_TRY(launch_copy(dptr<CopyDesc>(dscr, og), La, 1, d, nullptr, st));
-      }
+      rc = gather();
+      if (rc) return rc;
       CopyDesc c{};
       c.src = plain_rows(Rcmp, ldv);
       c.dst = pr.block(0);
@@ -2606,6 +2695,9 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
       t = std::max(t, sweep_floor(*opts));
       tol[0] = std::min(t, 0.5);
     }
+    const bool build_full = recycle && sweep == 0;
+    if (build_full) tol[0] = 0.0;   // no early stop: the space is built out to R^d
+    E.t_run = build_full ? t_full : 0;
     Program pg;
     Refill rf;
     if (sweep > 0) {
@@ -2623,7 +2715,7 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
     if (rc) return rc;
     HIP_TRY(hipMemcpy(E.tolv, tol.data(), sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpyAsync(pr.scale, &rmax, sizeof(double), hipMemcpyHostToDevice, st));
-    const int32_t tm = E.t_max - 1;
+    const int32_t tm = (E.t_run > 0 ? std::min(E.t_run, E.t_max) : E.t_max) - 1;
     HIP_TRY(hipMemcpyAsync(pr.done_at, &tm, 4, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemsetAsync(failL, 0, L * sizeof(int32_t), st));
     int steps = 0;
@@ -2686,39 +2778,120 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
     HIP_TRY(launch_gemm_nn_ex(false, dptr<NnDesc>(dscr, o2), La, 1, d, nullptr, st));
     std::vector<int32_t> fh(L);
     HIP_TRY(hipMemcpyAsync(fh.data(), failL, L * 4, hipMemcpyDeviceToHost, st));
-    // residuals of every shift (FP64)
-    rc = residual(ctx, op, (int)L, RowOp{b, 0, 0, 0x3fffffff, 0}, plain_rows(X, d), plain_rows(Rbuf, ldv), mu_dev, rp,
-                  rpart, rys, dscr);
+    const std::vector<int> corrected_l = act_l;
+    bool all = true;
+    rc = check_residuals(&all);
     if (rc) return rc;
     loads += 1;
-    rc = sqnorms(ctx, plain_rows(Rbuf, ldv), (int)L, d, sq_dev, host_sq, dscr);
-    if (rc) return rc;
-    bool all = true;
-    std::vector<int> next_l;
-    for (int64_t l = 0; l < L; ++l) {
-      relres[l] = std::sqrt(host_sq[l]) / bnorm;
-      const bool corrected = std::find(act_l.begin(), act_l.end(), (int)l) != act_l.end();
-      if (corrected && fh[l]) {   // as in the solve: with refinement the FP64 residual decides
+    for (int l : corrected_l)
+      if (fh[l]) {   // as in the solve: with refinement the FP64 residual decides
         if (refine) spd_fail[l] = 1;
         else status[l] = RBCG_ERR_NOT_SPD;
       }
-      if (refine && !(relres[l] <= opts->rtol)) {
-        all = false;
-        next_l.push_back((int)l);
-      }
-    }
-    if (!next_l.empty()) act_l = next_l;
-    if (std::getenv("RBCG_DEBUG")) {
-      double rlo = relres[0], rhi = relres[0];
-      for (int64_t l = 1; l < L; ++l) {
-        rlo = std::min(rlo, relres[l]);
-        rhi = std::max(rhi, relres[l]);
-      }
-      std::fprintf(stderr, "rbcg_path: sweep %d t %d target %.1e relres [%.2e, %.2e] (smallest shift %.2e)\n", sweep, t,
-                   tol[0], rlo, rhi, relres[l_min]);
-    }
+    debug_line("sweep", sweep, t, tol[0]);
     if (!refine || all) break;
+    if (build_full) {
+      // Recycled refinement.  The space of this sweep spans R^d, so Q (T + mu I)^{-1} Q^T is an
+      // approximate inverse of A_mu, accurate to the low-precision products that built T.  Each
+      // step corrects every shift still above rtol with it, without a new Krylov space:
+      // C = Q^T R (FP64), y_l = (T + mu_l I)^{-1} c_l with the factors of this sweep's solve,
+      // x_l += Q y_l, then the FP64 residuals.  A step costs one FP64 product against the t of a
+      // sweep; one that reduces the largest residual of the corrected shifts by less than a
+      // factor of 3 hands over to ordinary sweeps.
+      const int nb = t * m;
+      const bool pv = ((uintptr_t)pr.q % 16) == 0 && pr.ldv % 2 == 0 && pr.bs % 2 == 0;
+      bool stalled = false;
+      while (!all && !stalled && sweeps < max_sweeps) {
+        const int La = (int)act_l.size();
+        rc = gather();
+        if (rc) return rc;
+        int cs = std::max(1, std::min(512 / ((nb + 63) / 64), d / 256));
+        cs = (int)std::min<int64_t>(cs, (int64_t)(rp.part_elems / ((size_t)La * nb)));
+        if (cs < 1) break;
+        Staging stg;
+        NtDesc nd{};
+        nd.P = pr.rows(0);
+        nd.X = plain_rows(Rcmp, ldv);
+        nd.M = nb;
+        nd.N = La;
+        nd.K = d;
+        nd.active = -1;
+        nd.part = rpart;
+        nd.O = plain_rows(Ccoef, ldcc);
+        nd.out = nullptr;
+        nd.out_t = DT_F64;
+        FinDesc f{};
+        f.part = rpart;
+        f.M = nb;
+        f.N = La;
+        f.splits = cs;
+        f.mode = FIN_TRANS;
+        f.O = plain_rows(Ccoef, ldcc);
+        f.alpha = 1.0;
+        f.active = -1;
+        std::vector<TriDesc> tds;
+        std::vector<NnDesc> nns;
+        double before = 0.0;
+        for (int j = 0; j < La; ++j) {
+          const int l = act_l[j];
+          before = std::max(before, relres[l]);
+          TriDesc td{};
+          td.D = pr.D;
+          td.Bsub = pr.Bsub;
+          td.mask = pr.mask;
+          td.rhs = Ccoef + (size_t)j * ldcc;
+          td.ld_rhs = 1;
+          td.Lw = Lws + (size_t)l * T * mm;   // the factors of shift l from this sweep's solve
+          td.Xw = Xws + (size_t)l * T * mm;
+          td.Zw = Zws + (size_t)l * (T + 1) * m;
+          td.Y = Yall + j;
+          td.ldy = La;
+          td.fail = failL + l;
+          td.sigma = mu[l];
+          td.m = m;
+          td.r = 1;
+          td.active = -1;
+          td.nblk = t;
+          td.refine = 2;
+          tds.push_back(td);
+          NnDesc nn{};
+          nn.P = pr.rows(0);
+          nn.C = Yall + j;
+          nn.ldc = La;
+          nn.Y = plain_rows(X + (size_t)l * d, d);
+          nn.O = plain_rows(X + (size_t)l * d, d);
+          nn.alpha = 1.0;
+          nn.beta = 1.0;
+          nn.Ka = nb;
+          nn.Mo = 1;
+          nn.N = d;
+          nn.active = -1;
+          nns.push_back(nn);
+        }
+        const size_t o0 = stg.add(std::vector<NtDesc>{nd});
+        const size_t o1 = stg.add(std::vector<FinDesc>{f});
+        const size_t o2 = stg.add(tds);
+        const size_t o3 = stg.add(nns);
+        rc = upload(ctx, stg, dscr);
+        if (rc) return rc;
+        HIP_TRY(mv_f64((La + 15) / 16, pv, dptr<NtDesc>(dscr, o0), 1, nb, cs, nullptr, st));
+        if (cs > 1) HIP_TRY(launch_finish(dptr<FinDesc>(dscr, o1), 1, nb, La, nullptr, st));
+        HIP_TRY(launch_tri_refine(dptr<TriDesc>(dscr, o2), La, m, 1, t, nullptr, st));
+        HIP_TRY(launch_gemm_nn_ex(false, dptr<NnDesc>(dscr, o3), La, 1, d, nullptr, st));
+        const std::vector<int> stepped = act_l;
+        rc = check_residuals(&all);
+        if (rc) return rc;
+        loads += 1;
+        sweeps += 1;
+        double after = 0.0;
+        for (int l : stepped) after = std::max(after, relres[l]);
+        stalled = !(after <= 0.3 * before);
+        debug_line("recycled step", sweeps - 1, t, 0.3);
+      }
+      if (all) break;
+    }
   }
+  E.t_run = 0;
   int ndefl = 0;
   rc = count_deflated(pr, std::min(iters, E.t_max), st, &ndefl);
   if (rc) return rc;

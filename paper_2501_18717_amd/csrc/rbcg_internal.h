@@ -140,7 +140,9 @@ struct TriDesc {
   // coefficients of Lanczos step j), used by the refinement step: block column j >= 1 holds j
   // m x m blocks, rows i m .. i m + m - 1 for block i, at Hoff + hoff_offset(j, m); null: band only
   const double* Hoff;
-  int32_t refine;          // k_tri_refine: 0 = leave Y as the sweeps left it
+  int32_t refine;          // k_tri_refine: 0 = leave Y as the sweeps left it, 1 = one refinement
+                           // step, 2 = apply the stored factors to a right-hand side over all t
+                           // blocks (rhs[e * ld_rhs], e < t m), Y = (T + sigma I)^{-1} rhs
   int32_t pad2_;
 };
 
@@ -183,11 +185,6 @@ hipError_t launch_finish(const FinDesc* d_desc, int nz, int maxM, int maxN, cons
                          hipStream_t st, int lanes_per_output = 1);
 hipError_t launch_gemm_nn_ex(bool p_f32, const NnDesc* d_desc, int nz, int maxMo, int maxN,
                              const int32_t* active, hipStream_t st);
-// Same product, 64 output columns per workgroup with the C chunk staged in LDS and P streamed
-// one chunk ahead; with splits > 1 the partial sums go to `part` ([s][b][i], s < splits) and
-// a FIN_AXPBY finish forms O = beta Y + alpha sum.  Mo <= 144.
-hipError_t launch_nn_tall(bool p_f32, const NnDesc* d_desc, int nz, int maxMo, int maxN, int splits,
-                          const int32_t* active, hipStream_t st);
 // uniform: every problem of the launch has block width maxm (enables the exact-width kernels).
 hipError_t launch_qr_factor(const QrDesc* d_desc, int nz, int maxm, bool uniform, const int32_t* active,
                             hipStream_t st);
@@ -206,7 +203,9 @@ hipError_t launch_tri_backward(const TriDesc* d_desc, int nz, int maxm, int maxr
                                const int32_t* active, hipStream_t st);
 // One step of FP64 refinement of Y (one right-hand side per descriptor) after the forward and
 // backward sweeps: R = RHS - (T + sigma I) Y with the band and, where Hoff is set, the off-band
-// coefficients; then the stored factors solve for the correction and Y += correction.
+// coefficients; then the stored factors solve for the correction and Y += correction.  With
+// refine = 2 the descriptor's right-hand side spans all t blocks and Y = (T + sigma I)^{-1} rhs
+// with the stored factors (band T, as the forward sweep factored it).
 // hipErrorNotSupported when r > 1 or the t m solution values do not fit in LDS.
 hipError_t launch_tri_refine(const TriDesc* d_desc, int nz, int maxm, int maxr, int t, const int32_t* active,
                              hipStream_t st);
@@ -230,8 +229,12 @@ hipError_t launch_copy(const CopyDesc* d_desc, int nz, int maxRows, int maxN, co
 struct FillDesc { RowOp dst; const int32_t* mask; RowOp src; int32_t src_first, src_avail, m, n, active, pad_; };
 hipError_t launch_fill(const FillDesc* d_desc, int nz, int maxN, const int32_t* active, hipStream_t st);
 
+// dst (cols x ldt) = src^T for a rows x cols FP32 matrix (row-major, leading dimension ld), as
+// BF16 or FP32
 hipError_t launch_transpose_bf16(const float* src, int64_t ld, int rows, int cols, unsigned short* dst,
                                  int64_t ldt, hipStream_t st);
+hipError_t launch_transpose_f32(const float* src, int64_t ld, int rows, int cols, float* dst, int64_t ldt,
+                                hipStream_t st);
 
 // Quadrature-node sum and block-tridiagonal product for the square root.
 struct WsumDesc { const double* Y; int64_t node_stride; const double* w; int32_t nq, n, r, active; double* out; };

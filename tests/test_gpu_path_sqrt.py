@@ -109,20 +109,47 @@ def test_gram_path_fp64_iterates_match_oracle(R, ridge_small):
 
 
 def test_gram_path_bf16_refined_reaches_fp64_answer(R, ridge_small):
-    """BF16 Z and Z^T copies on MFMA (hi/lo split vectors) with FP64
-    refinement: every shift within 1e-8 of the dense ridge solution."""
+    """BF16 Z and Z^T copies on MFMA (three-part BF16 vectors) with FP64
+    refinement: every shift within 1e-8 of the dense ridge solution.  Here
+    t_max m >= d, so the first space is built out to R^d and the refinement
+    steps reuse it (one FP64 residual product per step, no new space)."""
     rbcg, ctx = R
     P = ridge_small
     note("gram path bf16 refine")
     op = rbcg.GramOperator(ctx, to_dev(P["Z"]), lo="bf16")
-    rc, info, X = _path(R, op, P["b"], P["omega"], P["mus"], 8, rtol=1e-11, matvec="bf16", refine_max=8)
+    rc, info, X = _path(R, op, P["b"], P["omega"], P["mus"], 8, rtol=1e-12, matvec="bf16", refine_max=12)
     assert rc == 0, info
+    note(f"  loads {info[0]['matrix_loads']} sweeps/steps {info[0]['refine_sweeps']} iters {info[0]['iters']}")
+    # the first space spans R^d after ceil(384 / 64) = 6 products; the rest are recycled steps and
+    # at most a few fresh sweeps
+    assert info[0]["matrix_loads"] <= 6 + 1 + 12 + 2 * 6, info[0]
     Z64 = P["Z"].astype(np.float64)
     A = Z64.T @ Z64
     Xt = ot.ridge_path_svd(P["Z"], P["f"], P["mus"])
     for i, mu in enumerate(P["mus"]):
         assert a_err(A, mu, X[i], Xt[i]) < 1e-8, (i, mu, info[i])
     assert all(inf["precision_used"] == 2 for inf in info)
+
+
+def test_dense_path_fp32_refined_partial_spaces(R):
+    """FP32 products with FP64 refinement where one Krylov space cannot span
+    R^d (t_max m = 384 < d = 600): each refinement sweep builds a fresh space
+    on [R Omega]; every shift reaches rtol and lies within 1e-8 of the dense
+    solve in A_mu-norm."""
+    rbcg, ctx = R
+    P = synth.dense_problem(7, 600, 1.5, 31, 1e-3)
+    A, b = P["A"], P["b"]
+    mus = [float(v) for v in np.logspace(-4, -1, 8)]
+    note("dense path f32 refine d=600 k=31 t=12 L=8")
+    op = rbcg.DenseOperator(ctx, to_dev(A), lo="f32")
+    rc, info, X = _path(R, op, b, P["omega"], mus, 12, rtol=1e-11, matvec="f32", refine_max=20)
+    assert rc == 0, info
+    note(f"  loads {info[0]['matrix_loads']} sweeps {info[0]['refine_sweeps']}")
+    assert info[0]["refine_sweeps"] >= 2
+    for i, mu in enumerate(mus):
+        xt = np.linalg.solve(A + mu * np.eye(A.shape[0]), b)
+        assert a_err(A, mu, X[i], xt) < 1e-8, (i, mu, info[i])
+        assert info[i]["relres"] <= 1e-11
 
 
 def _sqrt(R, op, B, t, nquad=32, group=32, matvec="f64", inverse=False):
