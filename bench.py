@@ -77,6 +77,18 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def copy_probe(dev):
+    """Three untimed 1 GiB device-to-device copies: a known-size reference for HBM counter runs."""
+    import torch
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    log("copy probe: 3 x 1 GiB device copies done")
+
+
 def cpu_model():
     """Model name of the host CPU (first processor in /proc/cpuinfo)."""
     try:
@@ -110,6 +122,7 @@ def main():
                     help="dense: the d=8192 system (default); batch: uneven independent systems; "
                          "ridge: the 64-shift ridge path, n=200000, d=4096; sqrt: RBF sampling, 16384 points")
     ap.add_argument("--nsys", type=int, default=200, help="batch workload: number of systems")
+    ap.add_argument("--no-fp64", action="store_true", help="ridge workload: skip the FP64-product leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run three untimed 1 GiB device-to-device copies (known-size reference for "
                          "HBM counter runs)")
@@ -146,13 +159,7 @@ def main():
     bd = torch.from_numpy(b).to(dev)
     omd = torch.from_numpy(Om).to(dev)
     if args.copy_probe:
-        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        log("copy probe: 3 x 1 GiB device copies done")
+        copy_probe(dev)
     ctx = rbcg.Context()
     op = rbcg.DenseOperator(ctx, Ad, lo="f32")
     x_mix = torch.zeros_like(bd)
@@ -398,7 +405,10 @@ def _timed(fn, steps):
 
 
 def run_ridge(args):
-    sub = ridge_leg(args.steps, args.warmup)
+    if args.copy_probe:
+        import torch
+        copy_probe(torch.device("cuda:0"))
+    sub = ridge_leg(args.steps, args.warmup, fp64=not args.no_fp64)
     out = {
         "metric": "solves/s at 1e-8 rel A-norm err: mixed+batched vs plain FP64; HBM/MFMA % peak",
         "value": sub["value"], "unit": sub["unit"], "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -410,7 +420,7 @@ def run_ridge(args):
     print(json.dumps(out), flush=True)
 
 
-def ridge_leg(steps, warmup):
+def ridge_leg(steps, warmup, fp64=True):
     """Ridge path: Z = G diag(exp(-j/400)) (n = 200000, d = 4096, FP32), 64 shifts log-spaced over
     [1e-6, 1], k = 128.  One step = the whole path: plain FP64 products at t = 32 (the Krylov space
     is the whole space, 32 * 129 >= 4096), and BF16 products with FP64 refinement to rtol 2e-12.
@@ -439,10 +449,12 @@ def ridge_leg(steps, warmup):
     o64 = rbcg.opts(32)
     o16 = rbcg.opts(32, rtol=2e-12, matvec="bf16", refine_max=20)
     for _ in range(warmup):
-        rbcg.path(ctx, op64, bd, omd, mus, X, o64, check=False)
+        if fp64:
+            rbcg.path(ctx, op64, bd, omd, mus, X, o64, check=False)
         rbcg.path(ctx, op16, bd, omd, mus, X, o16, check=False)
-    t64, (rc64, i64) = _timed(lambda: rbcg.path(ctx, op64, bd, omd, mus, X, o64, check=False), steps)
-    log(f"ridge: fp64 {t64 / steps:.3f}s per path rc={rc64}")
+    if fp64:
+        t64, (rc64, i64) = _timed(lambda: rbcg.path(ctx, op64, bd, omd, mus, X, o64, check=False), steps)
+        log(f"ridge: fp64 {t64 / steps:.3f}s per path rc={rc64}")
     ctx.profile(True)
     t16, (rc16, i16) = _timed(lambda: rbcg.path(ctx, op16, bd, omd, mus, X, o16, check=False), steps)
     prof = ctx.profile_read()
@@ -462,10 +474,10 @@ def ridge_leg(steps, warmup):
         "note": "value: BF16-MFMA products + FP64 refinement",
         "fp64_gpu": {"value": len(mus) * steps / t64, "unit": "shift solves/s",
                      "ms_per_step": 1e3 * t64 / steps, "status": rc64, "loads": i64[0]["matrix_loads"],
-                     "relres_max": max(i["relres"] for i in i64)},
+                     "relres_max": max(i["relres"] for i in i64)} if fp64 else None,
         "mixed": {"status": rc16, "refine_sweeps": i16[0]["refine_sweeps"], "loads": i16[0]["matrix_loads"],
                   "relres_max": max(i["relres"] for i in i16)},
-        "speedup_mixed_vs_fp64": t64 / t16,
+        "speedup_mixed_vs_fp64": t64 / t16 if fp64 else None,
         "gram_bf16_pass": {"kernel": "k_gram_bf16<9> (one pass over Z or Z^T, 16x16x32 BF16 MFMA)",
                            "launches": prof["launches"], "avg_launch_ms": avg_ms,
                            "algorithmic_bytes": prof["bytes"] / npass, "achieved_GBs": gbs,
