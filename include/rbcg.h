@@ -124,7 +124,23 @@ typedef struct {
                           that one Krylov space aims for before the next FP64 residual
                           (0 = default: 1e-4 for FP32, 1e-6 for BF16); never below what
                           the remaining rtol needs */
+  uint64_t seed;       /* start blocks passed as NULL (omega, or omega[s] of rbcg_solve) with
+                          k > 0 are drawn on the device from this seed: the layout of
+                          rbcg_omega_fill with stream = s (system index) for rbcg_solve and
+                          stream = 0 for rbcg_path */
+  int32_t reorth;      /* rbcg_reorth: how each new block is orthogonalised against the basis
+                          (Sec. 3.2 uses full reorthogonalisation; the numerical appendix also
+                          runs none and a partial scheme).  One policy per rbcg_solve call. */
+  int32_t reorth_blocks; /* RBCG_REORTH_PARTIAL: leading blocks kept (default 3 when 0) */
 } rbcg_opts;
+
+typedef enum {
+  RBCG_REORTH_FULL = 0,     /* against every previous block, two passes (BCGS2); the default */
+  RBCG_REORTH_NONE = 1,     /* against the last two blocks only: the block three-term
+                               recurrence of block Lanczos, two passes */
+  RBCG_REORTH_PARTIAL = 2   /* full while the basis has reorth_blocks blocks, then against
+                               those leading blocks and the last two only */
+} rbcg_reorth;
 
 /* Per-result report. */
 typedef struct {
@@ -139,13 +155,27 @@ typedef struct {
 
 /* ----------------------------------------------------------------- solvers */
 
+/* Gaussian start block drawn on the device (the Omega of def. BCG, i.i.d.
+ * N(0, 1) entries): out[r][c], r < rows, c < cols, row stride ld (device,
+ * FP64, caller-owned).  Element e = r cols + c is standard normal number
+ * e mod 2 of Philox4x32-10 (Salmon et al., SC 2011) called with counter
+ * (lo32(e / 2), hi32(e / 2), stream, 0) and key (lo32(seed), hi32(seed)); a
+ * call's words x0..x3 give u1 = ((x0 2^32 + x1) >> 11 + 1/2) 2^-53 and
+ * u2 = ((x2 2^32 + x3) >> 11 + 1/2) 2^-53, and the Box-Muller pair
+ * sqrt(-2 ln u1) (cos, sin)(2 pi u2).  The solvers use this layout for start
+ * blocks passed as NULL.  Blocking; RBCG_ERR_INVALID_ARG for rows < 0,
+ * cols < 1, ld < cols or sizes above 2^31 - 1. */
+int rbcg_omega_fill(rbcg_ctx* ctx, uint64_t seed, uint32_t stream, int64_t rows, int64_t cols,
+                    double* out /*device*/, int64_t ld);
+
 /* Independent systems (A_s + mu_s I) x_s = b_s, s = 0..nsys-1, advanced
  * together (one launch per kernel for all systems).
  *   ops[s]    operator of system s (host array of nsys handles); d_s = its dimension
  *   mu        host[nsys], mu_s >= 0
  *   b         host[nsys] of device pointers to b_s (length d_s, FP64)
- *   omega     host[nsys] of device pointers to Omega_s (k_s x d_s row-major FP64);
- *             may be NULL for k_s = 0
+ *   omega     host[nsys] of device pointers to Omega_s (k_s x d_s row-major FP64),
+ *             or NULL (the array or an entry): Omega_s is drawn on the device
+ *             from opts[s].seed, stream s (see rbcg_omega_fill); unused for k_s = 0
  *   k         host[nsys], 0 <= k_s < d_s; block width m_s = k_s + 1
  *   x         host[nsys] of device pointers to x_s (length d_s, FP64), written
  *   opts      host[nsys] options per system
@@ -160,13 +190,19 @@ int rbcg_solve(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, const dou
 /* Regularization path: one Krylov space K_t(A, [b Omega]) serves all L
  * shifts (eq. bcg_alg).
  *   b      device, length d (FP64)
- *   omega  device, k x d row-major (FP64); NULL when k = 0
+ *   omega  device, k x d row-major (FP64), or NULL: drawn on the device from
+ *          opts.seed, stream 0 (see rbcg_omega_fill); unused when k = 0
  *   mu     host[L], each >= 0
  *   X      device, L x d row-major (FP64), row l = solution for mu[l]
  *   info   host[L]
  * With opts.matvec low-precision and rtol > 0, each refinement sweep builds
  * a new space on [R Omega] where R holds the FP64 residuals of the shifts not
- * yet at rtol; only those shifts are corrected.  With the environment
+ * yet at rtol; only those shifts are corrected.  When t_max m >= d (and
+ * L <= 144, refine_max > 1), the first space is built out to the whole of
+ * R^d instead and the refinement steps reuse it: x_l += Q (T + mu_l I)^{-1}
+ * Q^T r_l with the factors of the first solve, one FP64 residual per step;
+ * a step that contracts by less than 3x hands over to fresh sweeps.
+ * info.refine_sweeps counts spaces and reuse steps.  With the environment
  * variable RBCG_DEBUG set, each sweep prints one line (its Krylov steps and
  * the range of relative residuals) to stderr. */
 int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, const double* omega, int32_t k,

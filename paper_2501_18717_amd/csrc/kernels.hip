@@ -1429,3 +1429,65 @@ hipError_t launch_converge(const ConvDesc* dd, int nz, hipStream_t st) {
 }
 
 }  // namespace rbcg
+
+namespace rbcg {
+
+// ---------------------------------------------------------------------------------------------
+// Seeded Gaussian block: out[r][c] (r < rows, c < cols, row stride ld) = standard normal number
+// e mod 2 of Philox4x32-10 call e / 2 (e = r cols + c), counter (lo32, hi32 of e / 2, stream, 0),
+// key (lo32, hi32 of seed); the call's four words give two 53-bit uniforms in (0, 1) and the
+// Box-Muller pair.  Philox4x32-10 as published (Salmon et al., SC 2011): ten rounds of
+// multiply-high/low by 0xD2511F53 and 0xCD9E8D57 with the key bumped by 0x9E3779B9, 0xBB67AE85.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int rnd = 0; rnd < 10; ++rnd) {
+    if (rnd) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gaussian(double* __restrict__ out, int64_t ld, int rows, int cols,
+                                                  uint64_t seed, uint32_t stream) {
+  const int64_t n = (int64_t)rows * cols;
+  const int64_t ncall = (n + 1) / 2;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < ncall; p += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t c[4] = {(uint32_t)p, (uint32_t)((uint64_t)p >> 32), stream, 0u};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const uint64_t a = (((uint64_t)c[0] << 32) | c[1]) >> 11;
+    const uint64_t b = (((uint64_t)c[2] << 32) | c[3]) >> 11;
+    const double u1 = ((double)a + 0.5) * 0x1p-53;
+    const double u2 = ((double)b + 0.5) * 0x1p-53;
+    const double r = sqrt(-2.0 * log(u1));
+    const double th = 2.0 * 3.141592653589793 * u2;
+    const double g[2] = {r * cos(th), r * sin(th)};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t e = 2 * p + h;
+      if (e >= n) break;
+      const int64_t rr = e / cols, cc = e - rr * cols;
+      out[rr * ld + cc] = g[h];
+    }
+  }
+}
+
+hipError_t launch_gaussian(double* out, int64_t ld, int rows, int cols, uint64_t seed, uint32_t stream,
+                           hipStream_t st) {
+  const int64_t ncall = ((int64_t)rows * cols + 1) / 2;
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((ncall + 255) / 256, 8192));
+  hipLaunchKernelGGL(k_gaussian, dim3(blocks), dim3(256), 0, st, out, ld, rows, cols, seed, stream);
+  return hipGetLastError();
+}
+
+}  // namespace rbcg

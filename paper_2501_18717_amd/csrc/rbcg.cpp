@@ -78,6 +78,8 @@ struct rbcg_ctx {
   bool stage_pending = false;
   hipEvent_t ev_in = nullptr;   // caller's stream position the children wait for
   unsigned char* scratch = nullptr;   // this device's fixed scratch (rbcg_op_apply_noalloc)
+  double* om_buf = nullptr;           // seeded Gaussian blocks of the current call
+  size_t om_cap = 0;                  // (doubles)
 };
 
 struct rbcg_op {
@@ -193,6 +195,7 @@ extern "C" int rbcg_destroy(rbcg_ctx* c) {
   if (c->stage) (void)hipHostFree(c->stage);
   if (c->ev_stage) (void)hipEventDestroy(c->ev_stage);
   if (c->ws) (void)hipFree(c->ws);
+  if (c->om_buf) (void)hipFree(c->om_buf);
   if (c->pinned) (void)hipHostFree(c->pinned);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
@@ -410,6 +413,8 @@ struct Engine {
   std::vector<MvGroup> Gs;
   int t_max = 1;
   int t_run = 0;                // run_steps: step limit below t_max when > 0
+  int reorth = RBCG_REORTH_FULL;  // reorthogonalisation policy of every problem of the engine
+  int reorth_blocks = 3;          // RBCG_REORTH_PARTIAL: leading blocks kept
   int maxm = 1;
   double eta2 = 1e-20, tau = 1e-15;
   int32_t* active = nullptr;    // device, per problem
@@ -600,44 +605,73 @@ struct Program {
 };
 
 // Build NT descriptors "rows [0, M) of basis p against block rows X" for all problems.
+// Basis blocks the new block W (slot j + 1) is projected against at step j, as ranges [lo, hi] of
+// block indices: the whole basis (full reorthogonalisation, Sec. 3.2), the last two blocks only
+// (the three-term block-Lanczos recurrence, no reorthogonalisation), or the first p blocks plus
+// the last two (the simple partial scheme of the numerical appendix: full reorthogonalisation
+// while the basis has p blocks, afterwards against those p blocks only).
+static std::vector<std::pair<int, int>> proj_ranges(const Engine& E, int j) {
+  if (E.reorth == RBCG_REORTH_NONE) return {{std::max(0, j - 1), j}};
+  if (E.reorth == RBCG_REORTH_PARTIAL) {
+    const int p = std::max(1, E.reorth_blocks);
+    if (j - 1 > p) return {{0, p - 1}, {j - 1, j}};
+  }
+  return {{0, j}};
+}
+
+// C = [Q_lo .. Q_hi (, W)]^T W for every range of proj_ranges (W itself in the last range's
+// product, which gives the Gram of W), block rows at their own positions in Cdst.
 static void add_proj(Program& pg, std::vector<Launch>& out, Engine& E, int j, bool with_w, double** Cdst) {
   std::vector<NtDesc> nt;
   std::vector<FinDesc> fin;
-  int maxM = 0, maxN = 0, tiles = 0;
+  const auto ranges = proj_ranges(E, j);
+  int maxM = 0, maxN = 0, maxTot = 0;
   for (size_t p = 0; p < E.P.size(); ++p) {
     const Prob& pr = E.P[p];
-    const int M = (j + 1 + (with_w ? 1 : 0)) * pr.m;
-    maxM = std::max(maxM, M);
+    int tot = 0;
+    for (size_t r = 0; r < ranges.size(); ++r) {
+      const int nb = ranges[r].second - ranges[r].first + 1 + (with_w && r + 1 == ranges.size() ? 1 : 0);
+      maxM = std::max(maxM, nb * pr.m);
+      tot += nb * pr.m;
+    }
+    maxTot = std::max(maxTot, tot);
     maxN = std::max(maxN, pr.m);
   }
-  (void)tiles;
   int K = 0;
   for (auto& pr : E.P) K = std::max(K, pr.d);
-  const int splits = proj_splits(maxM, (int)E.P.size(), K);
+  // one split count for the launch, sized by the rows of all ranges together (the partial buffer
+  // holds them one after the other)
+  const int splits = proj_splits(maxTot, (int)E.P.size(), K);
   for (size_t p = 0; p < E.P.size(); ++p) {
     const Prob& pr = E.P[p];
-    NtDesc d{};
-    d.P = pr.rows(0);
-    d.X = pr.block(j + 1);
-    d.M = (j + 1 + (with_w ? 1 : 0)) * pr.m;
-    d.N = pr.m;
-    d.K = pr.d;
-    d.active = (int)p;
-    d.part = pr.part;
-    d.out = Cdst[p];
-    d.ldo = pr.m;
-    nt.push_back(d);
-    FinDesc f{};
-    f.part = pr.part;
-    f.M = d.M;
-    f.N = d.N;
-    f.splits = splits;
-    f.mode = FIN_T2R;
-    f.out = Cdst[p];
-    f.ldo = pr.m;
-    f.alpha = 1.0;
-    f.active = (int)p;
-    fin.push_back(f);
+    int64_t poff = 0;
+    for (size_t r = 0; r < ranges.size(); ++r) {
+      const int lo = ranges[r].first;
+      const int nb = ranges[r].second - lo + 1 + (with_w && r + 1 == ranges.size() ? 1 : 0);
+      NtDesc d{};
+      d.P = pr.rows((int64_t)lo * pr.m);
+      d.X = pr.block(j + 1);
+      d.M = nb * pr.m;
+      d.N = pr.m;
+      d.K = pr.d;
+      d.active = (int)p;
+      d.part = pr.part + poff;
+      d.out = Cdst[p] + (int64_t)lo * pr.m * pr.m;
+      d.ldo = pr.m;
+      nt.push_back(d);
+      FinDesc f{};
+      f.part = d.part;
+      f.M = d.M;
+      f.N = d.N;
+      f.splits = splits;
+      f.mode = FIN_T2R;
+      f.out = d.out;
+      f.ldo = pr.m;
+      f.alpha = 1.0;
+      f.active = (int)p;
+      fin.push_back(f);
+      poff += (int64_t)splits * d.M * d.N;
+    }
   }
   Launch L{Launch::NT};
   L.off = pg.stg.add(nt);
@@ -658,48 +692,52 @@ static void add_proj(Program& pg, std::vector<Launch>& out, Engine& E, int j, bo
   }
 }
 
-// W -= Q_{0..j} C  (rows [0, (j+1)m) of the basis): one launch, the workgroup's waves split the
-// reduction over the basis and combine on chip (no split partials in HBM)
-// With `keep_offband` (the second pass) the same launch also stores C1 + C2 of blocks 0 .. j - 1
-// (Q_i^T A Q_j, block column j of Q^T A Q above the diagonal) for the refinement of the projected
-// solve.
+// W -= Q_{lo..hi} C for each range of proj_ranges, one launch per range (they update the same W):
+// each launch's workgroup waves split the reduction over the basis and combine on chip (no split
+// partials in HBM).  With `keep_offband` (the second pass, full reorthogonalisation only) the
+// launch also stores C1 + C2 of blocks 0 .. j - 1 (Q_i^T A Q_j, block column j of Q^T A Q above
+// the diagonal) for the refinement of the projected solve.
 static void add_update(Program& pg, std::vector<Launch>& out, Engine& E, int j, double** C,
                        bool keep_offband = false) {
-  std::vector<NnDesc> nn;
+  const auto ranges = proj_ranges(E, j);
   int maxMo = 0, maxN = 0;
   for (auto& pr : E.P) {
     maxMo = std::max(maxMo, pr.m);
     maxN = std::max(maxN, pr.d);
   }
-  for (size_t p = 0; p < E.P.size(); ++p) {
-    const Prob& pr = E.P[p];
-    NnDesc d{};
-    d.P = pr.rows(0);
-    d.C = C[p];
-    d.ldc = pr.m;
-    d.Y = pr.block(j + 1);
-    d.O = pr.block(j + 1);
-    d.alpha = -1.0;
-    d.beta = 1.0;
-    d.Ka = (j + 1) * pr.m;
-    d.Mo = pr.m;
-    d.N = pr.d;
-    d.active = (int)p;
-    if (keep_offband && j >= 1 && pr.Hoff) {
-      d.acc_a = pr.C1;
-      d.acc_b = pr.C2;
-      d.acc_out = pr.Hoff + hoff_offset(j, pr.m);
-      d.acc_n = (int64_t)j * pr.m * pr.m;
+  for (size_t r = 0; r < ranges.size(); ++r) {
+    const int lo = ranges[r].first, nb = ranges[r].second - lo + 1;
+    std::vector<NnDesc> nn;
+    for (size_t p = 0; p < E.P.size(); ++p) {
+      const Prob& pr = E.P[p];
+      NnDesc d{};
+      d.P = pr.rows((int64_t)lo * pr.m);
+      d.C = C[p] + (int64_t)lo * pr.m * pr.m;
+      d.ldc = pr.m;
+      d.Y = pr.block(j + 1);
+      d.O = pr.block(j + 1);
+      d.alpha = -1.0;
+      d.beta = 1.0;
+      d.Ka = nb * pr.m;
+      d.Mo = pr.m;
+      d.N = pr.d;
+      d.active = (int)p;
+      if (keep_offband && j >= 1 && pr.Hoff && lo == 0 && ranges.size() == 1) {
+        d.acc_a = pr.C1;
+        d.acc_b = pr.C2;
+        d.acc_out = pr.Hoff + hoff_offset(j, pr.m);
+        d.acc_n = (int64_t)j * pr.m * pr.m;
+      }
+      nn.push_back(d);
     }
-    nn.push_back(d);
+    Launch L{Launch::NN};
+    L.off = pg.stg.add(nn);
+    L.nz = (int)nn.size();
+    L.a0 = 0;
+    L.a1 = maxMo;
+    L.a2 = maxN;
+    out.push_back(L);
   }
-  Launch L{Launch::NN};
-  L.off = pg.stg.add(nn);
-  L.nz = (int)nn.size();
-  L.a0 = 0;
-  L.a1 = maxMo;
-  L.a2 = maxN;
-  out.push_back(L);
 }
 
 // G = W^T W for the W in block slot `slot`
@@ -1566,7 +1604,8 @@ static void carve(Arena& ar, Engine& E) {
     pr.est = ar.take<double>(T);
 
     pr.ybuf = ar.take<double>(T * pr.m);
-    pr.Hoff = T >= 2 ? ar.take<double>((size_t)hoff_offset((int)T, pr.m)) : nullptr;
+    // the off-band coefficients exist only with full reorthogonalisation
+    pr.Hoff = (T >= 2 && E.reorth == RBCG_REORTH_FULL) ? ar.take<double>((size_t)hoff_offset((int)T, pr.m)) : nullptr;
     pr.mask = ar.take<int32_t>((T + 1) * pr.m);
     pr.masktmp = ar.take<int32_t>(pr.m);
     pr.rank = ar.take<int32_t>(1);
@@ -1906,6 +1945,8 @@ static bool valid_opts(const rbcg_opts* o) {
   if (o->rtol > 0.0 && o->refine_max < 1) return false;
   if (o->nquad < 0 || o->group < 0 || !(o->eta >= 0.0)) return false;
   if (!(o->sweep_tol >= 0.0) || !(o->sweep_tol < 1.0)) return false;
+  if (o->reorth != RBCG_REORTH_FULL && o->reorth != RBCG_REORTH_NONE && o->reorth != RBCG_REORTH_PARTIAL) return false;
+  if (o->reorth_blocks < 0) return false;
   return true;
 }
 
@@ -2092,8 +2133,55 @@ static int tune_products(rbcg_ctx* ctx, Engine& E, unsigned char* ddesc) {
 }
 
 
+extern "C" int rbcg_omega_fill(rbcg_ctx* ctx, uint64_t seed, uint32_t stream, int64_t rows, int64_t cols, double* out,
+                               int64_t ld) {
+  if (!ctx || !out || rows < 0 || cols < 1 || ld < cols || rows > INT32_MAX || cols > INT32_MAX) return RBCG_ERR_INVALID_ARG;
+  if (rows == 0) return RBCG_OK;
+  HIP_TRY(launch_gaussian(out, ld, (int)rows, (int)cols, seed, stream, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return RBCG_OK;
+}
+
+// Start blocks of the systems that come without Omega: k_s x d_s Gaussian blocks drawn on the
+// device from opts[s].seed with stream s (rbcg_omega_fill's layout), into the context's buffer,
+// in stream order before the solve's first launch.  om[s] = the caller's block, the drawn one,
+// or null for k_s = 0.
+static int seeded_omegas(rbcg_ctx* ctx, int64_t nsys, const int64_t* dims, const int32_t* k,
+                         const double* const* omega, const rbcg_opts* opts, std::vector<const double*>& om) {
+  om.assign(nsys, nullptr);
+  size_t need = 0;
+  for (int64_t s = 0; s < nsys; ++s)
+    if (k[s] > 0 && !(omega && omega[s])) need += (size_t)k[s] * dims[s];
+  if (need > ctx->om_cap) {
+    if (ctx->om_buf) {
+      HIP_TRY(hipStreamSynchronize(ctx->stream));
+      (void)hipFree(ctx->om_buf);
+    }
+    ctx->om_buf = nullptr;
+    ctx->om_cap = 0;
+    if (hipMalloc(&ctx->om_buf, need * sizeof(double)) != hipSuccess) {
+      ctx->om_buf = nullptr;
+      return RBCG_ERR_OOM;
+    }
+    ctx->om_cap = need;
+  }
+  size_t off = 0;
+  for (int64_t s = 0; s < nsys; ++s) {
+    if (k[s] <= 0) continue;
+    if (omega && omega[s]) {
+      om[s] = omega[s];
+      continue;
+    }
+    double* dst = ctx->om_buf + off;
+    HIP_TRY(launch_gaussian(dst, dims[s], k[s], (int)dims[s], opts[s].seed, (uint32_t)s, ctx->stream));
+    om[s] = dst;
+    off += (size_t)k[s] * dims[s];
+  }
+  return RBCG_OK;
+}
+
 extern "C" int rbcg_solve(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, const double* mu,
-                          const double* const* b, const double* const* omega, const int32_t* k, double* const* x,
+                          const double* const* b, const double* const* omega_in, const int32_t* k, double* const* x,
                           const rbcg_opts* opts, rbcg_info* info) {
   if (!ctx || nsys < 1 || nsys > 65535 || !ops || !mu || !b || !k || !x || !opts || !info) return RBCG_ERR_INVALID_ARG;
   for (int64_t s = 0; s < nsys; ++s) {
@@ -2101,11 +2189,20 @@ extern "C" int rbcg_solve(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops
     if (!op || !b[s] || !x[s] || !valid_opts(&opts[s])) return RBCG_ERR_INVALID_ARG;
     if (!(mu[s] >= 0.0) || !std::isfinite(mu[s])) return RBCG_ERR_INVALID_ARG;
     if (k[s] < 0 || k[s] >= op->d || k[s] + 1 > kMaxBlock) return RBCG_ERR_INVALID_ARG;
-    if (k[s] > 0 && (!omega || !omega[s])) return RBCG_ERR_INVALID_ARG;
     if (!op_supports(op, opts[s].matvec)) return RBCG_ERR_UNSUPPORTED;
     if (op->device != ctx->device) return RBCG_ERR_INVALID_ARG;
     if (tri_forward_lds(k[s] + 1, 1) > kLdsCap) return RBCG_ERR_INVALID_ARG;
+    // one reorthogonalisation policy per call
+    if (opts[s].reorth != opts[0].reorth || opts[s].reorth_blocks != opts[0].reorth_blocks) return RBCG_ERR_INVALID_ARG;
   }
+  std::vector<const double*> om_v;
+  {
+    std::vector<int64_t> dims(nsys);
+    for (int64_t s = 0; s < nsys; ++s) dims[s] = ops[s]->d;
+    const int rc = seeded_omegas(ctx, nsys, dims.data(), k, omega_in, opts, om_v);
+    if (rc) return rc;
+  }
+  const double* const* omega = om_v.data();
   // Systems of one block width share every launch of a step; the widths are solved one after the
   // other, so that each launch is sized (and its kernels specialised) for its own width.
   std::vector<int> widths;
@@ -2192,6 +2289,8 @@ static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, c
   E.t_max = 1;
   for (int64_t s = 0; s < nsys; ++s) E.t_max = std::max(E.t_max, (int)opts[s].t_max);
   E.eta2 = opts[0].eta > 0 ? opts[0].eta * opts[0].eta : 1e-20;
+  E.reorth = opts[0].reorth;
+  E.reorth_blocks = opts[0].reorth_blocks > 0 ? opts[0].reorth_blocks : 3;
   E.P.resize(nsys);
   E.Gs.resize(nsys);
   for (int64_t s = 0; s < nsys; ++s) {
@@ -2465,17 +2564,25 @@ static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, c
 }
 
 // -------------------------------------------------------------------------------- path
-extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, const double* omega, int32_t k, int64_t L,
+extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, const double* omega_in, int32_t k, int64_t L,
                          const double* mu, double* X, const rbcg_opts* opts, rbcg_info* info) {
   if (!ctx || !op || !b || !mu || !X || !opts || !info || L < 1 || L > 256 || !valid_opts(opts))
     return RBCG_ERR_INVALID_ARG;
-  if (k < 0 || k >= op->d || k + 1 > kMaxBlock || (k > 0 && !omega)) return RBCG_ERR_INVALID_ARG;
+  if (k < 0 || k >= op->d || k + 1 > kMaxBlock) return RBCG_ERR_INVALID_ARG;
   for (int64_t l = 0; l < L; ++l)
     if (!(mu[l] >= 0.0) || !std::isfinite(mu[l])) return RBCG_ERR_INVALID_ARG;
   if (!op_supports(op, opts->matvec)) return RBCG_ERR_UNSUPPORTED;
   if (op->device != ctx->device) return RBCG_ERR_INVALID_ARG;
   const int m = k + 1;
   if (tri_forward_lds(m, 1) > kLdsCap) return RBCG_ERR_INVALID_ARG;
+  const double* omega = omega_in;
+  if (k > 0 && !omega) {   // drawn from opts->seed (stream 0)
+    std::vector<const double*> om_v;
+    const int64_t dims[1] = {op->d};
+    const int rc0 = seeded_omegas(ctx, 1, dims, &k, nullptr, opts, om_v);
+    if (rc0) return rc0;
+    omega = om_v[0];
+  }
   // refinement sweeps start from [R Omega'] with R the L residuals: needs L < m
   const bool refine = opts->rtol > 0.0;
   if (refine && opts->refine_max > 1 && L + 1 > m) return RBCG_ERR_UNSUPPORTED;
@@ -2489,6 +2596,8 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
   Engine E;
   E.t_max = opts->t_max;
   E.eta2 = opts->eta > 0 ? opts->eta * opts->eta : 1e-20;
+  E.reorth = opts->reorth;
+  E.reorth_blocks = opts->reorth_blocks > 0 ? opts->reorth_blocks : 3;
   E.maxm = m;
   E.P.resize(1);
   E.Gs.resize(1);
@@ -2936,6 +3045,8 @@ static int sqrt_driver(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, const doubl
   Engine E;
   E.t_max = opts->t_max;
   E.eta2 = opts->eta > 0 ? opts->eta * opts->eta : 1e-20;
+  E.reorth = opts->reorth;
+  E.reorth_blocks = opts->reorth_blocks > 0 ? opts->reorth_blocks : 3;
   E.maxm = m;
   E.P.resize(ngroups);
   E.Gs.resize(1);

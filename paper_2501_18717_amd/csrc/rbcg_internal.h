@@ -229,6 +229,11 @@ hipError_t launch_copy(const CopyDesc* d_desc, int nz, int maxRows, int maxN, co
 struct FillDesc { RowOp dst; const int32_t* mask; RowOp src; int32_t src_first, src_avail, m, n, active, pad_; };
 hipError_t launch_fill(const FillDesc* d_desc, int nz, int maxN, const int32_t* active, hipStream_t st);
 
+// Seeded Gaussian block out[r][c] (rows x cols, row stride ld): Philox4x32-10 counter (lo32, hi32
+// of e / 2, stream, 0) with e = r cols + c, key = seed, two 53-bit uniforms per call, Box-Muller.
+hipError_t launch_gaussian(double* out, int64_t ld, int rows, int cols, uint64_t seed, uint32_t stream,
+                           hipStream_t st);
+
 // dst (cols x ldt) = src^T for a rows x cols FP32 matrix (row-major, leading dimension ld), as
 // BF16 or FP32
 hipError_t launch_transpose_bf16(const float* src, int64_t ld, int rows, int cols, unsigned short* dst,

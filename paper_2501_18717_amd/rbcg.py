@@ -28,7 +28,8 @@ STATUS = {0: "OK", -1: "INVALID_ARG", -2: "NOT_SPD", -3: "BREAKDOWN", -4: "NO_CO
 class Opts(ctypes.Structure):
     _fields_ = [("t_max", ctypes.c_int32), ("rtol", ctypes.c_double), ("matvec", ctypes.c_int32),
                 ("refine_max", ctypes.c_int32), ("nquad", ctypes.c_int32), ("group", ctypes.c_int32),
-                ("eta", ctypes.c_double), ("sweep_tol", ctypes.c_double)]
+                ("eta", ctypes.c_double), ("sweep_tol", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("reorth", ctypes.c_int32), ("reorth_blocks", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -70,6 +71,7 @@ _invsqrt = _sig("rbcg_invsqrt_apply", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, c
 _ws_bytes = _sig("rbcg_workspace_bytes", _i64, [_vp])
 _op_apply = _sig("rbcg_op_apply", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, ctypes.c_int])
 _op_apply_noalloc = _sig("rbcg_op_apply_noalloc", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, ctypes.c_int])
+_omega_fill = _sig("rbcg_omega_fill", ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_uint32, _i64, _i64, _vp, _i64])
 _noalloc_bytes = _sig("rbcg_noalloc_scratch_bytes", _i64, [])
 _sqrt_rule = _sig("rbcg_sqrt_rule", ctypes.c_int, [ctypes.c_double, ctypes.c_double, _i32, _dp, _dp])
 _profile = _sig("rbcg_profile", ctypes.c_int, [_vp, ctypes.c_int])
@@ -119,10 +121,13 @@ def _need(t, dtype, shape=None, name="tensor"):
         raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
 
 
+REORTH = {"full": 0, "none": 1, "partial": 2}
+
+
 def opts(t_max: int, rtol: float = 0.0, matvec: str = "f64", refine_max: int = 1, nquad: int = 0, group: int = 0,
-         eta: float = 0.0, sweep_tol: float = 0.0) -> Opts:
+         eta: float = 0.0, sweep_tol: float = 0.0, seed: int = 0, reorth: str = "full", reorth_blocks: int = 0) -> Opts:
     return Opts(int(t_max), float(rtol), DTYPES[matvec], int(refine_max), int(nquad), int(group), float(eta),
-                float(sweep_tol))
+                float(sweep_tol), int(seed) & 0xFFFFFFFFFFFFFFFF, REORTH[reorth], int(reorth_blocks))
 
 
 class Context:
@@ -243,13 +248,25 @@ def op_apply_noalloc(ctx: Context, op, X, W, matvec: str = "f64"):
     _check(_op_apply_noalloc(ctx.handle, op.handle, N, _ptr(X), _ptr(W), DTYPES[matvec]), "rbcg_op_apply_noalloc")
 
 
+def omega_fill(ctx: Context, seed: int, stream: int, out):
+    """rbcg_omega_fill: out (rows x cols FP64 device tensor) = the seeded Gaussian block."""
+    import torch
+    if not out.is_cuda or out.dtype != torch.float64 or out.dim() != 2 or out.stride(1) != 1:
+        raise ValueError("out must be a 2-D FP64 device tensor with unit column stride")
+    rows, cols = out.shape
+    _check(_omega_fill(ctx.handle, ctypes.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), ctypes.c_uint32(int(stream)),
+                       rows, cols, _ptr(out), out.stride(0)), "rbcg_omega_fill")
+
+
 def noalloc_scratch_bytes() -> int:
     return int(_noalloc_bytes())
 
 
 def solve(ctx: Context, ops: Sequence, mus: Sequence[float], bs: Sequence, omegas: Sequence, xs: Sequence,
           options: Sequence[Opts], check: bool = True):
-    """rbcg_solve over len(ops) independent systems; x tensors are written in place."""
+    """rbcg_solve over len(ops) independent systems; x tensors are written in place.  An entry of
+    `omegas` is a (k, d) tensor, None (k = 0), or an int k: a k x d block drawn on the device from
+    that system's options.seed."""
     import torch
     n = len(ops)
     assert len(mus) == n and len(bs) == n and len(omegas) == n and len(xs) == n and len(options) == n
@@ -259,7 +276,9 @@ def solve(ctx: Context, ops: Sequence, mus: Sequence[float], bs: Sequence, omega
         _need(bs[i], torch.float64, (d,), "b")
         _need(xs[i], torch.float64, (d,), "x")
         om = omegas[i]
-        if om is not None and om.numel():
+        if isinstance(om, int):
+            ks.append(om)
+        elif om is not None and om.numel():
             _need(om, torch.float64, name="omega")
             if om.dim() != 2 or om.shape[1] != d:
                 raise ValueError("omega must have shape (k, d)")
@@ -269,7 +288,8 @@ def solve(ctx: Context, ops: Sequence, mus: Sequence[float], bs: Sequence, omega
     op_arr = (_vp * n)(*[o.handle for o in ops])
     mu_arr = (ctypes.c_double * n)(*[float(m) for m in mus])
     b_arr = (_vp * n)(*[_ptr(b) for b in bs])
-    om_arr = (_vp * n)(*[(_ptr(o) if (o is not None and o.numel()) else None) for o in omegas])
+    om_arr = (_vp * n)(*[(_ptr(o) if (o is not None and not isinstance(o, int) and o.numel()) else None)
+                         for o in omegas])
     k_arr = (_i32 * n)(*ks)
     x_arr = (_vp * n)(*[_ptr(x) for x in xs])
     o_arr = (Opts * n)(*options)
@@ -282,19 +302,23 @@ def solve(ctx: Context, ops: Sequence, mus: Sequence[float], bs: Sequence, omega
 
 
 def path(ctx: Context, op, b, omega, mus: Sequence[float], X, options: Opts, check: bool = True):
-    """rbcg_path: X (L x d) written in place."""
+    """rbcg_path: X (L x d) written in place.  `omega` is a (k, d) tensor, None (k = 0), or an int
+    k: a k x d block drawn on the device from options.seed."""
     import torch
     d = op.d
     L = len(mus)
     _need(b, torch.float64, (d,), "b")
     _need(X, torch.float64, (L, d), "X")
     k = 0
-    if omega is not None and omega.numel():
+    seeded = isinstance(omega, int)
+    if seeded:
+        k = omega
+    elif omega is not None and omega.numel():
         _need(omega, torch.float64, name="omega")
         k = omega.shape[0]
     mu_arr = (ctypes.c_double * L)(*[float(m) for m in mus])
     info = (Info * L)()
-    rc = _path(ctx.handle, op.handle, _ptr(b), _ptr(omega) if k else None, k, L, mu_arr, _ptr(X),
+    rc = _path(ctx.handle, op.handle, _ptr(b), _ptr(omega) if (k and not seeded) else None, k, L, mu_arr, _ptr(X),
                ctypes.byref(options), info)
     infos = [i.as_dict() for i in info]
     if check and rc not in (0, -4):

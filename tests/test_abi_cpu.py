@@ -53,7 +53,8 @@ def _header_struct(name):
 def test_binding_structs_mirror_header(cname, pyname):
     """The ctypes structures of the binding have the header's fields, in order and width."""
     from paper_2501_18717_amd import rbcg
-    width = {"int32_t": ctypes.c_int32, "double": ctypes.c_double, "int64_t": ctypes.c_int64}
+    width = {"int32_t": ctypes.c_int32, "double": ctypes.c_double, "int64_t": ctypes.c_int64,
+             "uint64_t": ctypes.c_uint64}
     want = [(n, width[t]) for n, t in _header_struct(cname)]
     got = list(getattr(rbcg, pyname)._fields_)
     assert [n for n, _ in got] == [n for n, _ in want]
@@ -78,6 +79,7 @@ def test_null_context_rejected(lib):
     assert rbcg._sqrt(None, None, 1, None, None, ctypes.byref(o), info) == -1
     assert rbcg._invsqrt(None, None, 1, None, None, ctypes.byref(o), info) == -1
     assert rbcg._solve(None, 1, None, None, None, None, None, None, None, None) == -1
+    assert rbcg._omega_fill(None, 1, 0, 4, 4, None, 4) == -1
 
 
 @pytest.mark.parametrize("lo,hi,n", [(1e-6, 244.0, 32), (1e-3, 1.0, 16), (3.6e-6, 244.0, 32), (0.5, 2.0, 8)])
