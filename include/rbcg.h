@@ -208,6 +208,35 @@ int rbcg_solve(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, const dou
 int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, const double* omega, int32_t k,
               int64_t L, const double* mu, double* X, const rbcg_opts* opts, rbcg_info* info);
 
+/* Nystrom-preconditioned CG, the comparison method of the paper, built from
+ * the same Gaussian block Omega (Sec. 2.2.2, eq. nystromBKI_def; def. PCG,
+ * Sec. 2.1; theta as in Sec. 7):
+ *   1. Q = orthonormal basis of K_s(A, Omega) (s - 1 block products of k
+ *      vectors; directions below 1e-14 of a block's largest are dropped),
+ *   2. Y = A Q (the s-th product) and the Nystrom approximation
+ *      A<K_s> = Y (Q^T Y)^+ Y^T = U^T diag(D) U (U: r orthonormal rows,
+ *      r <= s k, eigenvalues below 1e-13 of the largest dropped),
+ *   3. theta = the smallest kept D, or `theta` when > 0,
+ *   4. preconditioned CG on (A + mu I) x = b from x = 0 with
+ *      P^{-1} = (theta + mu) U^T (D + mu I)^{-1} U + (I - U^T U), until the
+ *      recursive residual reaches opts.rtol (checked every 4 iterations) or
+ *      opts.t_max iterations (rtol = 0: exactly t_max).
+ *   op       FP64 products only (opts.matvec = RBCG_F64, else UNSUPPORTED)
+ *   b, x     device, length d (FP64); x written
+ *   omega    device, k x d row-major (FP64), or NULL: drawn from opts.seed
+ *            (stream 0, see rbcg_omega_fill); 1 <= k < d, 1 <= s, s k <= 128
+ *   eig_out  host[s k] or NULL: the Nystrom eigenvalues D, descending, 0 for
+ *            dropped directions; rank_out, theta_out: host or NULL
+ *   info     one report: iters = PCG iterations, matrix_loads = s + iters + 1
+ *            (the construction, one single-vector product per iteration, the
+ *            final FP64 residual), deflated = s k - rank, relres = FP64
+ *            ||b - A_mu x|| / ||b||; status NO_CONVERGENCE when rtol > 0 and
+ *            relres misses it, NOT_SPD when a search direction has
+ *            p^T A_mu p <= 0. */
+int rbcg_nystrom_pcg(rbcg_ctx* ctx, const rbcg_op* op, const double* b, const double* omega, int32_t k,
+                     int32_t s, double mu, double theta, double* x, const rbcg_opts* opts, rbcg_info* info,
+                     double* eig_out, int32_t* rank_out, double* theta_out);
+
 /* Block-Lanczos square root Y ~ A^{1/2} B (def. blansq).  The m_s samples
  * (rows of B) are split into groups of opts.group; each group's samples form
  * one Krylov start block (every sample is augmented by the others in its

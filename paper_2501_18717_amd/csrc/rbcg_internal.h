@@ -229,6 +229,24 @@ hipError_t launch_copy(const CopyDesc* d_desc, int nz, int maxRows, int maxN, co
 struct FillDesc { RowOp dst; const int32_t* mask; RowOp src; int32_t src_first, src_avail, m, n, active, pad_; };
 hipError_t launch_fill(const FillDesc* d_desc, int nz, int maxN, const int32_t* active, hipStream_t st);
 
+// Nystrom-PCG helpers (nystrom.hip).  Symmetric eigendecomposition of an n x n matrix, n <=
+// kEighMax, in one workgroup (cyclic Jacobi): w[i] eigenvalues (unsorted), V[k][i] eigenvectors.
+constexpr int kEighMax = 128;
+hipError_t launch_sym_eigh(const double* S, int64_t lds_, int n, double* w, double* V, hipStream_t st);
+// M[a][i] = V[a][i] / sqrt(w_i) for w_i > cut max w, else 0; mode 1 also writes the kept
+// eigenvalues D, theta (smallest kept, unless theta_in > 0), coef_i = (theta + mu)/(D_i + mu) - 1
+// and the kept count.
+hipError_t launch_nys_factor(const double* w, const double* V, int r, double cut, int mode, double mu,
+                             double theta_in, double* M, double* D, double* coef, double* theta_out, int32_t* count,
+                             hipStream_t st);
+// PCG updates with device scalars sc[0] = r.z, sc[1] = r.r: step A after qneg = -(A + mu I) p,
+// scale cw = coef .* w, step B after z = P^{-1} r.
+hipError_t launch_pcg_step_a(double* x, double* r, const double* p, const double* qneg, int64_t n, double* sc,
+                             int32_t* fail, hipStream_t st);
+hipError_t launch_pcg_scale(const double* coef, const double* wv, double* cw, int r, hipStream_t st);
+hipError_t launch_pcg_step_b(const double* r, const double* z, double* p, int64_t n, double* sc, int first,
+                             hipStream_t st);
+
 // Seeded Gaussian block out[r][c] (rows x cols, row stride ld): Philox4x32-10 counter (lo32, hi32
 // of e / 2, stream, 0) with e = r cols + c, key = seed, two 53-bit uniforms per call, Box-Muller.
 hipError_t launch_gaussian(double* out, int64_t ld, int rows, int cols, uint64_t seed, uint32_t stream,

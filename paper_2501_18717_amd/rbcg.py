@@ -72,6 +72,9 @@ _ws_bytes = _sig("rbcg_workspace_bytes", _i64, [_vp])
 _op_apply = _sig("rbcg_op_apply", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, ctypes.c_int])
 _op_apply_noalloc = _sig("rbcg_op_apply_noalloc", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, ctypes.c_int])
 _omega_fill = _sig("rbcg_omega_fill", ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_uint32, _i64, _i64, _vp, _i64])
+_nystrom_pcg = _sig("rbcg_nystrom_pcg", ctypes.c_int,
+                    [_vp, _vp, _vp, _vp, _i32, _i32, ctypes.c_double, ctypes.c_double, _vp, ctypes.POINTER(Opts),
+                     ctypes.POINTER(Info), _dp, ctypes.POINTER(_i32), _dp])
 _noalloc_bytes = _sig("rbcg_noalloc_scratch_bytes", _i64, [])
 _sqrt_rule = _sig("rbcg_sqrt_rule", ctypes.c_int, [ctypes.c_double, ctypes.c_double, _i32, _dp, _dp])
 _profile = _sig("rbcg_profile", ctypes.c_int, [_vp, ctypes.c_int])
@@ -256,6 +259,33 @@ def omega_fill(ctx: Context, seed: int, stream: int, out):
     rows, cols = out.shape
     _check(_omega_fill(ctx.handle, ctypes.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), ctypes.c_uint32(int(stream)),
                        rows, cols, _ptr(out), out.stride(0)), "rbcg_omega_fill")
+
+
+def nystrom_pcg(ctx: Context, op, b, omega, s: int, mu: float, x, options: Opts, theta: float = 0.0,
+                check: bool = True):
+    """rbcg_nystrom_pcg: x written in place.  `omega` is a (k, d) tensor or an int k (drawn from
+    options.seed).  Returns (rc, info, eigenvalues (descending, s k values), rank, theta)."""
+    import torch
+    d = op.d
+    _need(b, torch.float64, (d,), "b")
+    _need(x, torch.float64, (d,), "x")
+    if isinstance(omega, int):
+        k, om = omega, None
+    else:
+        _need(omega, torch.float64, name="omega")
+        if omega.dim() != 2 or omega.shape[1] != d:
+            raise ValueError("omega must have shape (k, d)")
+        k, om = omega.shape[0], _ptr(omega)
+    r = max(1, s * k)
+    eig = (ctypes.c_double * r)()
+    rank = _i32()
+    th = ctypes.c_double()
+    info = Info()
+    rc = _nystrom_pcg(ctx.handle, op.handle, _ptr(b), om, k, s, float(mu), float(theta), _ptr(x),
+                      ctypes.byref(options), ctypes.byref(info), eig, ctypes.byref(rank), ctypes.byref(th))
+    if check and rc not in (0, -4):
+        raise RbcgError(rc, "rbcg_nystrom_pcg")
+    return rc, info.as_dict(), list(eig)[: s * k], rank.value, th.value
 
 
 def noalloc_scratch_bytes() -> int:
