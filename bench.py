@@ -18,7 +18,8 @@ step count, skipped with --no-ridge / --no-batch):
            against the same systems solved one call at a time in FP64.
 
 Printed (one JSON line): solves/s of the mixed path, the plain FP64 rate,
-the error of both against the FP64 oracle, the roofline of the dominant
+the Nystrom-PCG rate with the same Omega (the paper's comparison method),
+the error of each against the FP64 oracle, the roofline of the dominant
 kernel (the block-product GEMM, timed with HIP events on the library's
 stream over the timed region), the CPU oracle's rate on this host (with the
 CPU model and thread count), and the two sub-objects above.
@@ -203,12 +204,32 @@ def main():
     ctx.profile(False)
     log(f"fp64: {args.steps} solves in {t_64:.3f}s; {info_64}")
 
+    # ---- Nystrom PCG from the same Omega (the paper's comparison method, Sec. 2.2.2), FP64 products:
+    # rank-128 preconditioner from K_2(A, Omega), then single-vector PCG to the same rtol
+    s_ny = 2
+    x_ny = torch.zeros_like(bd)
+    o_ny = rbcg.opts(2000, rtol=rtol)
+
+    def nys():
+        return rbcg.nystrom_pcg(ctx, op, bd, omd, s_ny, mu, x_ny, o_ny, check=False)
+
+    for _ in range(args.warmup):
+        nys()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rc_ny, info_ny, _, rank_ny, theta_ny = nys()
+    torch.cuda.synchronize()
+    t_ny = time.perf_counter() - t0
+    log(f"nystrom pcg: {args.steps} solves in {t_ny:.3f}s; {info_ny}")
+
     xm = x_mix.cpu().numpy()
     x6 = x_64.cpu().numpy()
+    xn = x_ny.cpu().numpy()
 
     # ---- CPU oracle: one complete solve (t = the FP64 GPU iteration count) on this host
     cpu = None
-    err_mix = err_64 = None
+    err_mix = err_64 = err_ny = None
     if not args.no_cpu:
         from oracle import block_cg as ob
         threads = None
@@ -226,6 +247,7 @@ def main():
         rel_o = float(np.linalg.norm(b - (A @ xo + mu * xo)) / np.linalg.norm(b))
         err_mix = a_err(A, mu, xm, xo)
         err_64 = a_err(A, mu, x6, xo)
+        err_ny = a_err(A, mu, xn, xo)
         cpu = {"value": 1.0 / t_cpu, "unit": "solves/s", "cores": int(threads or os.cpu_count() or 1),
                "cpu_model": cpu_model(), "kind": "oracle",
                "sample": f"one full solve of the d=8192 k=64 system by the FP64 oracle (t={t_ref} block products, "
@@ -265,6 +287,12 @@ def main():
                   "matrix_loads": info_mix["matrix_loads"], "relres": info_mix["relres"],
                   "rel_a_err_vs_oracle": err_mix},
         "speedup_mixed_vs_fp64": t_64 / t_mix,
+        "nystrom_pcg": {"value": args.steps / t_ny, "unit": "solves/s", "ms_per_step": 1e3 * t_ny / args.steps,
+                        "s": s_ny, "rank": rank_ny, "theta": theta_ny, "status": rc_ny, "iters": info_ny["iters"],
+                        "matrix_loads": info_ny["matrix_loads"], "relres": info_ny["relres"],
+                        "rel_a_err_vs_oracle": err_ny,
+                        "note": "Nystrom PCG from the same Omega (K_2(A, Omega), rank 128), FP64 products, "
+                                "single-vector loads after the two block loads"},
         "cpu_baseline": cpu,
     }
     # free the dense system before the sub-objects
