@@ -1030,13 +1030,36 @@ __global__ __launch_bounds__(1024) void k_tri_refine(const TriDesc* __restrict__
       for (int rr = tid; rr < rows; rr += 1024) {
         if (d.mask[rr]) continue;   // masks of blocks 0 .. j - 2 are contiguous
         double s = 0.0;
-        for (int b = 0; b < m; ++b) s += H[(int64_t)rr * m + b] * y[j * m + b];
+        // four independent partial sums keep several loads in flight
+        double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        const double* hr = H + (int64_t)rr * m;
+        const double* yj = y + j * m;
+        int b = 0;
+        for (; b + 3 < m; b += 4) {
+          s += hr[b] * yj[b];
+          s1 += hr[b + 1] * yj[b + 1];
+          s2 += hr[b + 2] * yj[b + 2];
+          s3 += hr[b + 3] * yj[b + 3];
+        }
+        for (; b < m; ++b) s += hr[b] * yj[b];
+        s += (s1 + s2) + s3;
         R[rr] -= s;
       }
       const int b = tid % m, sl = tid / m;
       double s = 0.0;
       if (sl < slices)
-        for (int rr = sl; rr < rows; rr += slices) s += H[(int64_t)rr * m + b] * y[rr];
+      {
+        double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int rr = sl;
+        for (; rr + 3 * slices < rows; rr += 4 * slices) {
+          s += H[(int64_t)rr * m + b] * y[rr];
+          s1 += H[(int64_t)(rr + slices) * m + b] * y[rr + slices];
+          s2 += H[(int64_t)(rr + 2 * slices) * m + b] * y[rr + 2 * slices];
+          s3 += H[(int64_t)(rr + 3 * slices) * m + b] * y[rr + 3 * slices];
+        }
+        for (; rr < rows; rr += slices) s += H[(int64_t)rr * m + b] * y[rr];
+        s += (s1 + s2) + s3;
+      }
       tmp[tid] = s;
       __syncthreads();
       if (tid < m && !mkj[tid]) {
@@ -1047,33 +1070,45 @@ __global__ __launch_bounds__(1024) void k_tri_refine(const TriDesc* __restrict__
       __syncthreads();
     }
   }
-  // forward elimination with the stored factors U_i = B_i Sinv_i
-  for (int i = 0; i + 1 < t; ++i) {
-    const double* U = d.Xw + i * mm;
-    if (tid < m) {
-      double s = 0.0;
-      for (int u = 0; u < m; ++u) s += U[tid * m + u] * R[i * m + u];
-      R[(i + 1) * m + tid] -= s;
+  // forward elimination with the stored factors U_i = B_i Sinv_i, then backward substitution
+  // with Sinv_i.  Each m x m matrix-vector product spreads a row over tpr = 1024 / m threads
+  // (each takes every tpr-th column, so consecutive threads read consecutive elements of the
+  // row), and the row's tpr partial sums are combined through LDS.
+  double* red = tmp + 1024 + m;   // 1024 partial sums
+  const int tpr = 1024 / m;
+  const int ra = tid / tpr, rj = tid - ra * tpr;
+  auto mv_part = [&](const double* mat, bool trans, const double* xv) {
+    double acc = 0.0;
+    if (ra < m) {
+      if (trans) {
+        for (int u = rj; u < m; u += tpr) acc += mat[u * m + ra] * xv[u];
+      } else {
+        for (int u = rj; u < m; u += tpr) acc += mat[ra * m + u] * xv[u];
+      }
     }
+    red[tid] = acc;
+    __syncthreads();
+  };
+  auto row_sum = [&](int a) {
+    double acc = 0.0;
+    for (int q = 0; q < tpr; ++q) acc += red[a * tpr + q];
+    return acc;
+  };
+  for (int i = 0; i + 1 < t; ++i) {
+    mv_part(d.Xw + i * mm, false, R + i * m);
+    if (tid < m) R[(i + 1) * m + tid] -= row_sum(tid);
     __syncthreads();
   }
-  // backward substitution with Sinv_i
   for (int i = t - 1; i >= 0; --i) {
-    if (tid < m) {
-      double w = R[i * m + tid];
-      if (i + 1 < t) {
-        const double* Bi = d.Bsub + i * mm;
-        for (int u = 0; u < m; ++u) w -= Bi[u * m + tid] * R[(i + 1) * m + u];
-      }
-      tmp[tid] = w;
+    if (i + 1 < t) {
+      mv_part(d.Bsub + i * mm, true, R + (i + 1) * m);
+      if (tid < m) tmp[tid] = R[i * m + tid] - row_sum(tid);
+    } else if (tid < m) {
+      tmp[tid] = R[i * m + tid];
     }
     __syncthreads();
-    if (tid < m) {
-      const double* Si = d.Lw + i * mm;
-      double s = 0.0;
-      for (int c = 0; c < m; ++c) s += Si[tid * m + c] * tmp[c];
-      R[i * m + tid] = s;
-    }
+    mv_part(d.Lw + i * mm, false, tmp);
+    if (tid < m) R[i * m + tid] = row_sum(tid);
     __syncthreads();
   }
   for (int e = tid; e < n; e += 1024) d.Y[(int64_t)e * d.ldy] = y[e] + R[e];
@@ -1082,7 +1117,7 @@ __global__ __launch_bounds__(1024) void k_tri_refine(const TriDesc* __restrict__
 hipError_t launch_tri_refine(const TriDesc* dd, int nz, int maxm, int maxr, int t, const int32_t* act,
                              hipStream_t st) {
   if (maxr != 1 || maxm < 1 || maxm > 1024) return hipErrorNotSupported;
-  const size_t lds = ((size_t)2 * t * maxm + 1024 + maxm) * 8;
+  const size_t lds = ((size_t)2 * t * maxm + 2048 + maxm) * 8;
   if (lds > kLdsCap) return hipErrorNotSupported;
   static const hipError_t attr = set_big_lds((const void*)k_tri_refine);
   if (attr != hipSuccess) return attr;

@@ -29,9 +29,11 @@ __device__ double wg_sum(double v, double* red) {
 // round-robin ordering: each round rotates n/2 disjoint index pairs at once (the 2 x 2 symmetric
 // Schur rotation that zeroes A[p][q]: tau = (a_qq - a_pp) / (2 a_pq), t = sign(tau) / (|tau| +
 // sqrt(1 + tau^2)), c = 1 / sqrt(1 + t^2), s = t c), first on rows, then on columns and on the
-// eigenvector matrix.  Sweeps of n - 1 rounds (n + 1 - 1 for odd n, one index idle per round)
-// until the off-diagonal part is below 1e-15 of the diagonal in Frobenius norm.  S is read as
-// (S + S^T) / 2.  Out: w[i] = eigenvalue i (unsorted), V[k][i] = component k of eigenvector i.
+// eigenvector matrix.  The pairs of round r come from the circle method on N = n rounded up to
+// even (index N - 1 fixed): (r, N - 1) and ((r + i) mod (N - 1), (r - i) mod (N - 1)) for
+// 1 <= i < N / 2; N - 1 rounds meet every pair once (for odd n the pairs with index n idle).
+// Sweeps until the off-diagonal part is below 1e-15 of the diagonal in Frobenius norm.  S is read
+// as (S + S^T) / 2.  Out: w[i] = eigenvalue i (unsorted), V[k][i] = component k of eigenvector i.
 __global__ __launch_bounds__(1024) void k_sym_eigh(const double* __restrict__ S, int64_t lds_, int n,
                                                    double* __restrict__ w, double* __restrict__ V, int max_sweeps) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -39,8 +41,7 @@ __global__ __launch_bounds__(1024) void k_sym_eigh(const double* __restrict__ S,
   double* red = A + (size_t)n * n;                  // 1024
   double* cs = red + 1024;                          // pairs
   double* sn = cs + kEighMax / 2 + 1;
-  int* ring = (int*)(sn + kEighMax / 2 + 1);        // npad
-  int* pp = ring + kEighMax + 2;
+  int* pp = (int*)(sn + kEighMax / 2 + 1);
   int* qq = pp + kEighMax / 2 + 1;
   const int tid = threadIdx.x;
   const int npad = n + (n & 1);
@@ -50,7 +51,6 @@ __global__ __launch_bounds__(1024) void k_sym_eigh(const double* __restrict__ S,
     A[e] = 0.5 * (S[(int64_t)i * lds_ + j] + S[(int64_t)j * lds_ + i]);
     V[e] = i == j ? 1.0 : 0.0;
   }
-  for (int e = tid; e < npad; e += 1024) ring[e] = e;
   __syncthreads();
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     double off = 0.0, dia = 0.0;
@@ -65,7 +65,9 @@ __global__ __launch_bounds__(1024) void k_sym_eigh(const double* __restrict__ S,
     if (!(off > 1e-30 * dia)) break;
     for (int round = 0; round < npad - 1; ++round) {
       if (tid < npairs) {
-        const int p = ring[tid], q = ring[npad - 1 - tid];
+        const int L = npad - 1;
+        const int p = tid == 0 ? round : (round + tid) % L;
+        const int q = tid == 0 ? L : (round - tid + L) % L;
         double c = 1.0, s = 0.0;
         if (p < n && q < n) {
           const double apq = A[p * n + q];
@@ -107,20 +109,13 @@ __global__ __launch_bounds__(1024) void k_sym_eigh(const double* __restrict__ S,
         V[(int64_t)k * n + q] = s * vp + c * vq;
       }
       __syncthreads();
-      // next round of the tournament: position 0 stays, the others move one place
-      if (tid == 0) {
-        const int last = ring[npad - 1];
-        for (int e = npad - 1; e > 1; --e) ring[e] = ring[e - 1];
-        if (npad > 1) ring[1] = last;
-      }
-      __syncthreads();
     }
   }
   for (int i = tid; i < n; i += 1024) w[i] = A[i * n + i];
 }
 
 size_t sym_eigh_lds(int n) {
-  return ((size_t)n * n + 1024 + 2 * (kEighMax / 2 + 1)) * 8 + (size_t)(kEighMax + 2 + 2 * (kEighMax / 2 + 1)) * 4;
+  return ((size_t)n * n + 1024 + 2 * (kEighMax / 2 + 1)) * 8 + (size_t)(2 * (kEighMax / 2 + 1)) * 4;
 }
 
 hipError_t launch_sym_eigh(const double* S, int64_t lds_, int n, double* w, double* V, hipStream_t st) {

@@ -2740,6 +2740,34 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
     std::fprintf(stderr, "rbcg_path: %s %d t %d target %.1e relres [%.2e, %.2e] (smallest shift %.2e)\n", what, sweep,
                  t, target, rlo, rhi, relres[l_min]);
   };
+  // x_l (+)= Q_t y_l for the shifts al[j] (y_l = column j of Yall, ld = al.size()): one product
+  // reading the basis once when the shifts are consecutive, else one descriptor per shift
+  auto x_update = [&](const std::vector<int>& al, int Ka, double beta, std::vector<NnDesc>& nns) -> int {
+    const int La = (int)al.size();
+    bool consecutive = true;
+    for (int j = 1; j < La; ++j) consecutive = consecutive && al[j] == al[0] + j;
+    auto desc = [&](int j0, int cnt) {
+      NnDesc nn{};
+      nn.P = pr.rows(0);
+      nn.C = Yall + j0;
+      nn.ldc = La;
+      nn.Y = plain_rows(X + (size_t)al[j0] * d, d);
+      nn.O = nn.Y;
+      nn.alpha = 1.0;
+      nn.beta = beta;
+      nn.Ka = Ka;
+      nn.Mo = cnt;
+      nn.N = d;
+      nn.active = -1;
+      return nn;
+    };
+    if (consecutive) {
+      nns.push_back(desc(0, La));
+      return La;
+    }
+    for (int j = 0; j < La; ++j) nns.push_back(desc(j, 1));
+    return 1;
+  };
   for (int sweep = 0; sweeps < max_sweeps; ++sweep) {
     std::vector<CopyDesc> cps;
     int nstart;
@@ -2868,20 +2896,8 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
       td.Hoff = pr.Hoff;
       td.refine = opts->matvec == RBCG_F64 ? 1 : 0;   // as for rbcg_solve
       tds.push_back(td);
-      NnDesc nn{};
-      nn.P = pr.rows(0);
-      nn.C = Yall + j;
-      nn.ldc = La;
-      nn.Y = plain_rows(X + (size_t)l * d, d);
-      nn.O = plain_rows(X + (size_t)l * d, d);
-      nn.alpha = 1.0;
-      nn.beta = sweep == 0 ? 0.0 : 1.0;
-      nn.Ka = t * m;
-      nn.Mo = 1;
-      nn.N = d;
-      nn.active = -1;
-      nns.push_back(nn);
     }
+    const int mo = x_update(act_l, t * m, sweep == 0 ? 0.0 : 1.0, nns);
     const size_t o1 = stg.add(tds);
     const size_t o2 = stg.add(nns);
     rc = upload(ctx, stg, dscr);
@@ -2889,7 +2905,7 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
     HIP_TRY(tri_forward_any(dptr<TriDesc>(dscr, o1), La, m, 1, 0, t, st));
     HIP_TRY(launch_tri_backward(dptr<TriDesc>(dscr, o1), La, m, 1, t, nullptr, st));
     HIP_TRY(refine_projected(dptr<TriDesc>(dscr, o1), La, m, t, st));
-    HIP_TRY(launch_gemm_nn_ex(false, dptr<NnDesc>(dscr, o2), La, 1, d, nullptr, st));
+    HIP_TRY(launch_gemm_nn_ex(false, dptr<NnDesc>(dscr, o2), (int)nns.size(), mo, d, nullptr, st));
     std::vector<int32_t> fh(L);
     HIP_TRY(hipMemcpyAsync(fh.data(), failL, L * 4, hipMemcpyDeviceToHost, st));
     const std::vector<int> corrected_l = act_l;
@@ -2968,20 +2984,8 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
           td.nblk = t;
           td.refine = 2;
           tds.push_back(td);
-          NnDesc nn{};
-          nn.P = pr.rows(0);
-          nn.C = Yall + j;
-          nn.ldc = La;
-          nn.Y = plain_rows(X + (size_t)l * d, d);
-          nn.O = plain_rows(X + (size_t)l * d, d);
-          nn.alpha = 1.0;
-          nn.beta = 1.0;
-          nn.Ka = nb;
-          nn.Mo = 1;
-          nn.N = d;
-          nn.active = -1;
-          nns.push_back(nn);
         }
+        const int mo = x_update(act_l, nb, 1.0, nns);
         const size_t o0 = stg.add(std::vector<NtDesc>{nd});
         const size_t o1 = stg.add(std::vector<FinDesc>{f});
         const size_t o2 = stg.add(tds);
@@ -2991,7 +2995,7 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
         HIP_TRY(mv_f64((La + 15) / 16, pv, dptr<NtDesc>(dscr, o0), 1, nb, cs, nullptr, st));
         if (cs > 1) HIP_TRY(launch_finish(dptr<FinDesc>(dscr, o1), 1, nb, La, nullptr, st));
         HIP_TRY(launch_tri_refine(dptr<TriDesc>(dscr, o2), La, m, 1, t, nullptr, st));
-        HIP_TRY(launch_gemm_nn_ex(false, dptr<NnDesc>(dscr, o3), La, 1, d, nullptr, st));
+        HIP_TRY(launch_gemm_nn_ex(false, dptr<NnDesc>(dscr, o3), (int)nns.size(), mo, d, nullptr, st));
         const std::vector<int> stepped = act_l;
         rc = check_residuals(&all);
         if (rc) return rc;
