@@ -205,41 +205,42 @@ def main():
     log(f"fp64: {args.steps} solves in {t_64:.3f}s; {info_64}")
 
     # ---- Nystrom PCG from the same Omega (the paper's comparison method, Sec. 2.2.2), FP64 products:
-    # rank-128 preconditioner from K_2(A, Omega), then single-vector PCG to the same rtol
-    s_ny = 2
+    # preconditioner of rank 64 s from K_s(A, Omega) for s = 1 and 2, then single-vector PCG to
+    # the same rtol; each call also timed stopped after one iteration (the construction: s block
+    # loads, the basis, the r x r eigendecompositions, plus one iteration and the residual)
+    ny = {}
     x_ny = torch.zeros_like(bd)
-    o_ny = rbcg.opts(2000, rtol=rtol)
-
-    def nys():
-        return rbcg.nystrom_pcg(ctx, op, bd, omd, s_ny, mu, x_ny, o_ny, check=False)
-
-    for _ in range(args.warmup):
-        nys()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        rc_ny, info_ny, _, rank_ny, theta_ny = nys()
-    torch.cuda.synchronize()
-    t_ny = time.perf_counter() - t0
-    log(f"nystrom pcg: {args.steps} solves in {t_ny:.3f}s; {info_ny}")
-    # the same call stopped after one PCG iteration: the preconditioner's construction (2 block
-    # loads, the basis, two 128 x 128 eigendecompositions) plus one iteration and the residual
-    o_ny1 = rbcg.opts(1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        rbcg.nystrom_pcg(ctx, op, bd, omd, s_ny, mu, x_ny, o_ny1, check=False)
-    torch.cuda.synchronize()
-    t_ny1 = time.perf_counter() - t0
-    rbcg.nystrom_pcg(ctx, op, bd, omd, s_ny, mu, x_ny, o_ny, check=False)
+    for s_ny in (1, 2):
+        o_ny = rbcg.opts(2000, rtol=rtol)
+        o_ny1 = rbcg.opts(1)
+        for _ in range(args.warmup):
+            rbcg.nystrom_pcg(ctx, op, bd, omd, s_ny, mu, x_ny, o_ny, check=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            rbcg.nystrom_pcg(ctx, op, bd, omd, s_ny, mu, x_ny, o_ny1, check=False)
+        torch.cuda.synchronize()
+        t_ny1 = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            rc_ny, info_ny, _, rank_ny, theta_ny = rbcg.nystrom_pcg(ctx, op, bd, omd, s_ny, mu, x_ny, o_ny,
+                                                                    check=False)
+        torch.cuda.synchronize()
+        t_ny = time.perf_counter() - t0
+        log(f"nystrom pcg s={s_ny}: {args.steps} solves in {t_ny:.3f}s; {info_ny}")
+        ny[s_ny] = {"value": args.steps / t_ny, "unit": "solves/s", "ms_per_step": 1e3 * t_ny / args.steps,
+                    "s": s_ny, "rank": rank_ny, "theta": theta_ny, "status": rc_ny, "iters": info_ny["iters"],
+                    "matrix_loads": info_ny["matrix_loads"], "relres": info_ny["relres"],
+                    "ms_construction_plus_one_iteration": 1e3 * t_ny1 / args.steps,
+                    "x": x_ny.cpu().numpy()}
 
     xm = x_mix.cpu().numpy()
     x6 = x_64.cpu().numpy()
-    xn = x_ny.cpu().numpy()
 
     # ---- CPU oracle: one complete solve (t = the FP64 GPU iteration count) on this host
     cpu = None
-    err_mix = err_64 = err_ny = None
+    err_mix = err_64 = None
     if not args.no_cpu:
         from oracle import block_cg as ob
         threads = None
@@ -257,7 +258,8 @@ def main():
         rel_o = float(np.linalg.norm(b - (A @ xo + mu * xo)) / np.linalg.norm(b))
         err_mix = a_err(A, mu, xm, xo)
         err_64 = a_err(A, mu, x6, xo)
-        err_ny = a_err(A, mu, xn, xo)
+        for v in ny.values():
+            v["rel_a_err_vs_oracle"] = a_err(A, mu, v["x"], xo)
         cpu = {"value": 1.0 / t_cpu, "unit": "solves/s", "cores": int(threads or os.cpu_count() or 1),
                "cpu_model": cpu_model(), "kind": "oracle",
                "sample": f"one full solve of the d=8192 k=64 system by the FP64 oracle (t={t_ref} block products, "
@@ -297,13 +299,9 @@ def main():
                   "matrix_loads": info_mix["matrix_loads"], "relres": info_mix["relres"],
                   "rel_a_err_vs_oracle": err_mix},
         "speedup_mixed_vs_fp64": t_64 / t_mix,
-        "nystrom_pcg": {"value": args.steps / t_ny, "unit": "solves/s", "ms_per_step": 1e3 * t_ny / args.steps,
-                        "s": s_ny, "rank": rank_ny, "theta": theta_ny, "status": rc_ny, "iters": info_ny["iters"],
-                        "matrix_loads": info_ny["matrix_loads"], "relres": info_ny["relres"],
-                        "rel_a_err_vs_oracle": err_ny,
-                        "ms_construction_plus_one_iteration": 1e3 * t_ny1 / args.steps,
-                        "note": "Nystrom PCG from the same Omega (K_2(A, Omega), rank 128), FP64 products, "
-                                "single-vector loads after the two block loads"},
+        "nystrom_pcg": [dict({k: v for k, v in ny[s_].items() if k != "x"},
+                             note="Nystrom PCG from the same Omega (rank 64 s from K_s(A, Omega)), FP64 products, "
+                                  "single-vector loads after the s block loads") for s_ in sorted(ny)],
         "cpu_baseline": cpu,
     }
     # free the dense system before the sub-objects

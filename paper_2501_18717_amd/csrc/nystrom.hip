@@ -95,18 +95,40 @@ __global__ __launch_bounds__(1024) void k_sym_eigh(const double* __restrict__ S,
         A[q * n + k] = s * ap + c * aq;
       }
       __syncthreads();
-      // columns: A <- A J, V <- V J (consecutive threads take different pairs of one row)
-      for (int e = tid; e < npairs * n; e += 1024) {
-        const int k = e / npairs, i = e - k * npairs;
-        const int p = pp[i], q = qq[i];
-        if (p >= n || q >= n) continue;
-        const double c = cs[i], s = sn[i];
-        const double ap = A[k * n + p], aq = A[k * n + q];
-        A[k * n + p] = c * ap - s * aq;
-        A[k * n + q] = s * ap + c * aq;
-        const double vp = V[(int64_t)k * n + p], vq = V[(int64_t)k * n + q];
-        V[(int64_t)k * n + p] = c * vp - s * vq;
-        V[(int64_t)k * n + q] = s * vp + c * vq;
+      // columns: A <- A J, V <- V J (consecutive threads take different pairs of one row); the
+      // thread's eigenvector elements are all loaded before any is updated, so their global loads
+      // are in flight together
+      {
+        constexpr int QM = (kEighMax / 2 * kEighMax + 1023) / 1024;
+        double vpv[QM], vqv[QM];
+#pragma unroll
+        for (int qi = 0; qi < QM; ++qi) {
+          const int e = tid + 1024 * qi;
+          vpv[qi] = 0.0;
+          vqv[qi] = 0.0;
+          if (e < npairs * n) {
+            const int k = e / npairs, i = e - k * npairs;
+            const int p = pp[i], q = qq[i];
+            if (p < n && q < n) {
+              vpv[qi] = V[(int64_t)k * n + p];
+              vqv[qi] = V[(int64_t)k * n + q];
+            }
+          }
+        }
+#pragma unroll
+        for (int qi = 0; qi < QM; ++qi) {
+          const int e = tid + 1024 * qi;
+          if (e >= npairs * n) continue;
+          const int k = e / npairs, i = e - k * npairs;
+          const int p = pp[i], q = qq[i];
+          if (p >= n || q >= n) continue;
+          const double c = cs[i], s = sn[i];
+          const double ap = A[k * n + p], aq = A[k * n + q];
+          A[k * n + p] = c * ap - s * aq;
+          A[k * n + q] = s * ap + c * aq;
+          V[(int64_t)k * n + p] = c * vpv[qi] - s * vqv[qi];
+          V[(int64_t)k * n + q] = s * vpv[qi] + c * vqv[qi];
+        }
       }
       __syncthreads();
     }
