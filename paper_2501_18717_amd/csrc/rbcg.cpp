@@ -2338,7 +2338,7 @@ static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, c
     rys_p = a.take<double>(std::max<size_t>(rys, 1));
     mu_dev = a.take<double>(nsys);
     sq_dev = a.take<double>(nsys);
-    dscr = a.take<unsigned char>(std::max<size_t>((size_t)1 << 16, (size_t)nsys * 512));
+    dscr = a.take<unsigned char>(std::max<size_t>((size_t)1 << 16, (size_t)nsys * 2048));
   };
   Arena a0;
   carve_all(a0);
@@ -2369,11 +2369,44 @@ static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, c
   int32_t* fail_h = doneat_h + nsys;
   HIP_TRY(hipMemcpyAsync(mu_dev, mu, nsys * sizeof(double), hipMemcpyHostToDevice, st));
 
+  // squared norms of one vector per listed system (rows[s], length d_s) into host_sq[s]: one
+  // launch, one copy, one synchronisation; `pre` launches (staged in the same upload) run first
+  auto norms_of = [&](const std::vector<int64_t>& which, const std::vector<const double*>& rows, Staging& stg,
+                      const std::vector<Launch>& pre) -> int {
+    std::vector<NormDesc> nds;
+    for (int64_t s : which) {
+      NormDesc nd{};
+      nd.x = plain_rows(rows[s], E.P[s].d);
+      nd.out = sq_dev + s;
+      nd.rows = 1;
+      nd.n = E.P[s].d;
+      nd.active = -1;
+      nds.push_back(nd);
+    }
+    if (nds.empty()) return RBCG_OK;
+    const size_t o = stg.add(nds);
+    int r = upload(ctx, stg, dscr);
+    if (r) return r;
+    for (const auto& L : pre) HIP_TRY(enqueue(L, dscr, nullptr, st));
+    HIP_TRY(launch_sqnorms(dptr<NormDesc>(dscr, o), (int)nds.size(), 1, nullptr, st));
+    HIP_TRY(hipMemcpyAsync(host_sq, sq_dev, nsys * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return RBCG_OK;
+  };
   // ||b||
   std::vector<double> bnorm(nsys), relres(nsys, -1.0);
-  for (int64_t s = 0; s < nsys; ++s) {
-    rc = sqnorms(ctx, plain_rows(b[s], E.P[s].d), 1, E.P[s].d, sq_dev + s, host_sq + s, dscr);
+  {
+    std::vector<int64_t> all(nsys);
+    std::vector<const double*> rows(nsys);
+    for (int64_t s = 0; s < nsys; ++s) {
+      all[s] = s;
+      rows[s] = b[s];
+    }
+    Staging stg;
+    rc = norms_of(all, rows, stg, {});
     if (rc) return rc;
+  }
+  for (int64_t s = 0; s < nsys; ++s) {
     bnorm[s] = std::sqrt(host_sq[s]);
     if (!(bnorm[s] > 0.0) || !std::isfinite(bnorm[s])) return RBCG_ERR_INVALID_ARG;
   }
@@ -2520,18 +2553,28 @@ static int solve_group(rbcg_ctx* ctx, int64_t nsys, const rbcg_op* const* ops, c
       HIP_TRY(refine_projected(dptr<TriDesc>(dscr, o1), (int)tds.size(), E.maxm, E.t_max, st));
       HIP_TRY(launch_gemm_nn_ex(false, dptr<NnDesc>(dscr, o2), (int)nns.size(), 1, maxd, nullptr, st));
     }
-    // FP64 residuals
-    for (int64_t s = 0; s < nsys; ++s) {
-      if (!act[s]) continue;
-      const Prob& pr = E.P[s];
-      rc = residual(ctx, pr.op, 1, plain_rows(b[s], pr.d), plain_rows(x[s], pr.d), plain_rows(rbuf[s], pr.d),
-                    mu_dev + s, rplan[s], rpart_p, rys_p, dscr);
+    // FP64 residuals of every system of the sweep: all launches staged in one upload and
+    // enqueued back to back (they share the partial buffer in stream order), then their norms
+    {
+      Staging stg;
+      std::vector<Launch> out;
+      std::vector<int64_t> which;
+      std::vector<const double*> rows(nsys, nullptr);
+      for (int64_t s = 0; s < nsys; ++s) {
+        if (!act[s]) continue;
+        const Prob& pr = E.P[s];
+        emit_apply(stg, out, pr.op, 1, plain_rows(b[s], pr.d), plain_rows(x[s], pr.d), plain_rows(rbuf[s], pr.d),
+                   mu_dev + s, rplan[s], rpart_p, rys_p, FIN_RESID, 1.0);
+        which.push_back(s);
+        rows[s] = rbuf[s];
+      }
+      rc = norms_of(which, rows, stg, out);
       if (rc) return rc;
-      loads[s] += 1;
-      rc = sqnorms(ctx, plain_rows(rbuf[s], pr.d), 1, pr.d, sq_dev + s, host_sq + s, dscr);
-      if (rc) return rc;
-      relres[s] = std::sqrt(host_sq[s]) / bnorm[s];
-      if (opts[s].rtol == 0.0 || relres[s] <= opts[s].rtol) done[s] = 1;
+      for (int64_t s : which) {
+        loads[s] += 1;
+        relres[s] = std::sqrt(host_sq[s]) / bnorm[s];
+        if (opts[s].rtol == 0.0 || relres[s] <= opts[s].rtol) done[s] = 1;
+      }
     }
   }
   // directions dropped in each system's last Krylov space: the deflation masks of its blocks
