@@ -2754,16 +2754,28 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
     return RBCG_OK;
   };
   // FP64 residuals of all shifts, their norms, and the shifts still above rtol
+  // The residuals are recomputed for the range of shifts [l0, l1] that covers every shift the
+  // last correction changed (the others' iterates, residuals and norms are unchanged).
   auto check_residuals = [&](bool* all_out) -> int {
-    int r = residual(ctx, op, (int)L, RowOp{b, 0, 0, 0x3fffffff, 0}, plain_rows(X, d), plain_rows(Rbuf, ldv), mu_dev,
-                     rp, rpart, rys, dscr);
+    int l0 = (int)L, l1 = -1;
+    for (int l : act_l) {
+      l0 = std::min(l0, l);
+      l1 = std::max(l1, l);
+    }
+    if (l1 < l0) {
+      l0 = 0;
+      l1 = (int)L - 1;
+    }
+    const int nr = l1 - l0 + 1;
+    int r = residual(ctx, op, nr, RowOp{b, 0, 0, 0x3fffffff, 0}, plain_rows(X + (size_t)l0 * d, d),
+                     plain_rows(Rbuf + (size_t)l0 * ldv, ldv), mu_dev + l0, rp, rpart, rys, dscr);
     if (r) return r;
-    r = sqnorms(ctx, plain_rows(Rbuf, ldv), (int)L, d, sq_dev, host_sq, dscr);
+    r = sqnorms(ctx, plain_rows(Rbuf + (size_t)l0 * ldv, ldv), nr, d, sq_dev + l0, host_sq + l0, dscr);
     if (r) return r;
     bool all = true;
     std::vector<int> next_l;
     for (int64_t l = 0; l < L; ++l) {
-      relres[l] = std::sqrt(host_sq[l]) / bnorm;
+      if (l >= l0 && l <= l1) relres[l] = std::sqrt(host_sq[l]) / bnorm;
       if (refine && !(relres[l] <= opts->rtol)) {
         all = false;
         next_l.push_back((int)l);
