@@ -974,10 +974,18 @@ static void emit_dense_batch(Program& pg, std::vector<Launch>& out, DenseBatch& 
     C.a2 = B.maxd;
     out.push_back(C);
   }
+  // FP32 products of one block width 33, 64, 65 or 129 (the batches are split by width) run on
+  // the 32x32x2 kernel, which stores FP32 partials
+  int t2 = 0, ne = 0;
+  bool uniform = true;
+  for (const auto& d : B.nt) uniform = uniform && d.N == B.maxN;
+  const bool wide = dtype == DT_F32 && uniform && wide_shape(B.maxN, &t2, &ne);
+  if (wide)
+    for (auto& f : B.fin) f.part_f32 = 1;
   Launch L{Launch::NT};
   L.off = pg.stg.add(B.nt);
   L.nz = (int)B.nt.size();
-  L.a0 = dtype | (1 << 8) | (1 << 9) | (B.pvec ? (1 << 10) : 0);
+  L.a0 = dtype | (1 << 8) | (1 << 9) | (B.pvec ? (1 << 10) : 0) | (wide ? (1 << 11) : 0);
   L.a1 = B.maxd;
   L.a2 = B.maxN;
   L.a3 = B.splits;
