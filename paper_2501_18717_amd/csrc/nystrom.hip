@@ -34,15 +34,18 @@ __device__ double wg_sum(double v, double* red) {
 // 1 <= i < N / 2; N - 1 rounds meet every pair once (for odd n the pairs with index n idle).
 // Sweeps until the off-diagonal part is below 1e-15 of the diagonal in Frobenius norm.  S is read
 // as (S + S^T) / 2.  Out: w[i] = eigenvalue i (unsorted), V[k][i] = component k of eigenvector i.
+// VL: the eigenvector matrix is accumulated in LDS (when 2 n^2 doubles fit) and written out once.
+template <bool VL>
 __global__ __launch_bounds__(1024) void k_sym_eigh(const double* __restrict__ S, int64_t lds_, int n,
-                                                   double* __restrict__ w, double* __restrict__ V, int max_sweeps) {
+                                                   double* __restrict__ Vout, double* __restrict__ w, int max_sweeps) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* A = (double*)smem_raw;                    // n x n
   double* red = A + (size_t)n * n;                  // 1024
+  double* V = VL ? red + 1024 + 2 * (kEighMax / 2 + 1) + kEighMax + 2 : Vout;   // n x n (LDS or global)
   double* cs = red + 1024;                          // pairs
   double* sn = cs + kEighMax / 2 + 1;
   int* pp = (int*)(sn + kEighMax / 2 + 1);
-  int* qq = pp + kEighMax / 2 + 1;
+  int* qq = pp + kEighMax / 2 + 1;   // ints: 2 (kEighMax / 2 + 1) <= (kEighMax + 2) doubles of room
   const int tid = threadIdx.x;
   const int npad = n + (n & 1);
   const int npairs = npad / 2;
@@ -134,20 +137,29 @@ __global__ __launch_bounds__(1024) void k_sym_eigh(const double* __restrict__ S,
     }
   }
   for (int i = tid; i < n; i += 1024) w[i] = A[i * n + i];
+  if constexpr (VL)
+    for (int e = tid; e < n * n; e += 1024) Vout[e] = V[e];
 }
 
-size_t sym_eigh_lds(int n) {
-  return ((size_t)n * n + 1024 + 2 * (kEighMax / 2 + 1)) * 8 + (size_t)(2 * (kEighMax / 2 + 1)) * 4;
+size_t sym_eigh_lds(int n, bool vl) {
+  return ((size_t)n * n + 1024 + 2 * (kEighMax / 2 + 1) + kEighMax + 2 + (vl ? (size_t)n * n : 0)) * 8;
 }
 
 hipError_t launch_sym_eigh(const double* S, int64_t lds_, int n, double* w, double* V, hipStream_t st) {
   if (n < 1 || n > kEighMax) return hipErrorInvalidValue;
-  const size_t lds = sym_eigh_lds(n);
+  const bool vl = sym_eigh_lds(n, true) <= kLdsCap;
+  const size_t lds = sym_eigh_lds(n, vl);
   if (lds > kLdsCap) return hipErrorInvalidValue;
-  static const hipError_t attr =
-      hipFuncSetAttribute((const void*)k_sym_eigh, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsCap);
-  if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(k_sym_eigh, dim3(1), dim3(1024), lds, st, S, lds_, n, w, V, 30);
+  static const hipError_t attr0 =
+      hipFuncSetAttribute((const void*)k_sym_eigh<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsCap);
+  static const hipError_t attr1 =
+      hipFuncSetAttribute((const void*)k_sym_eigh<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsCap);
+  if (attr0 != hipSuccess) return attr0;
+  if (attr1 != hipSuccess) return attr1;
+  if (vl)
+    hipLaunchKernelGGL(k_sym_eigh<true>, dim3(1), dim3(1024), lds, st, S, lds_, n, V, w, 30);
+  else
+    hipLaunchKernelGGL(k_sym_eigh<false>, dim3(1), dim3(1024), lds, st, S, lds_, n, V, w, 30);
   return hipGetLastError();
 }
 
