@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "librbcg.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "gram_bf16.hip", "nystrom.hip", "qr_cols.hip", "tri_exact.hip", "mv_f32_wide.hip", "gemm_nt_f64.hip", "gemm_nt_f32.hip", "gemm_nt_f32f64.hip",
+SOURCES = ["kernels.hip", "gram_bf16.hip", "nystrom.hip", "qr_cols.hip", "tri_exact.hip", "mv_f32_wide.hip", "gemm_nt_f64.hip", "mv_f64_4x4.hip", "gemm_nt_f32.hip", "gemm_nt_f32f64.hip",
            "rbcg.cpp", "quadrature.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

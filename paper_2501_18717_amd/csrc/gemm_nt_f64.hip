@@ -11,7 +11,16 @@ hipError_t nt_f64_o0(int tn, const NtDesc* dd, int nz, int maxM, int splits, con
 }  // namespace rbcg
 
 namespace rbcg {
-hipError_t mv_f64(int tn, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act, hipStream_t st) {
+hipError_t mv_f64_44(int maxN, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act,
+                     hipStream_t st);
+
+// FP64 tall block product of up to 144 vectors: the 16x16x4 kernel for at most 32 of them (one
+// or two column tiles), the 4x4x4 kernel above (4-column granularity; same 64-row tiles and
+// partial layout).  The boundary is measured: at 17-32 columns the 16x16x4 kernel is the faster.
+hipError_t mv_f64(int maxN, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act,
+                  hipStream_t st) {
+  if (maxN > 32) return mv_f64_44(maxN, pvec, dd, nz, maxM, splits, act, st);
+  const int tn = (maxN + 15) / 16;
   return pvec ? dispatch_mv<DT_F64, true>(tn, dd, nz, maxM, splits, act, st)
               : dispatch_mv<DT_F64, false>(tn, dd, nz, maxM, splits, act, st);
 }

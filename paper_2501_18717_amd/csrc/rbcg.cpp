@@ -32,7 +32,7 @@
 namespace rbcg {
 bool sqrt_rule(double lo, double hi, int N, double* shifts, double* weights);
 hipError_t mv_f32(int tn, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act, hipStream_t st);
-hipError_t mv_f64(int tn, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act, hipStream_t st);
+hipError_t mv_f64(int maxN, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act, hipStream_t st);
 hipError_t mv_f32_wide(int t2, int ne, int w, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act,
                        hipStream_t st);
 hipError_t mv_f32f64(int tn, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act,
@@ -572,7 +572,7 @@ static hipError_t enqueue(const Launch& L, unsigned char* dbase, const int32_t* 
         switch (L.a0 & 0xff) {
           case DT_F32: return mv_f32(tn, pvec, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a3, act, st);
           case DT_F32F64: return mv_f32f64(tn, pvec, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a3, act, st);
-          default: return mv_f64(tn, pvec, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a3, act, st);
+          default: return mv_f64(L.a2, pvec, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a3, act, st);
         }
       }
       return launch_gemm_nt_ex(L.a0 & 0xff, (L.a0 >> 8) & 1, L.flag, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a2,
@@ -3055,7 +3055,7 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
         const size_t o3 = stg.add(nns);
         rc = upload(ctx, stg, dscr);
         if (rc) return rc;
-        HIP_TRY(mv_f64((La + 15) / 16, pv, dptr<NtDesc>(dscr, o0), 1, nb, cs, nullptr, st));
+        HIP_TRY(mv_f64(La, pv, dptr<NtDesc>(dscr, o0), 1, nb, cs, nullptr, st));
         if (cs > 1) HIP_TRY(launch_finish(dptr<FinDesc>(dscr, o1), 1, nb, La, nullptr, st));
         HIP_TRY(launch_tri_refine(dptr<TriDesc>(dscr, o2), La, m, 1, t, nullptr, st));
         HIP_TRY(launch_gemm_nn_ex(false, dptr<NnDesc>(dscr, o3), (int)nns.size(), mo, d, nullptr, st));
@@ -3524,7 +3524,7 @@ extern "C" int rbcg_nystrom_pcg(rbcg_ctx* ctx, const rbcg_op* op, const double* 
     const size_t o2 = stg.add(std::vector<FinDesc>{f});
     int r2 = upload(ctx, stg, dscr);
     if (r2) return r2;
-    HIP_TRY(mv_f64((N + 15) / 16, pvq, dptr<NtDesc>(dscr, o1), 1, M, ssm, nullptr, st));
+    HIP_TRY(mv_f64(N, pvq, dptr<NtDesc>(dscr, o1), 1, M, ssm, nullptr, st));
     if (ssm > 1) HIP_TRY(launch_finish(dptr<FinDesc>(dscr, o2), 1, M, N, nullptr, st, fin_lanes(ssm)));
     return RBCG_OK;
   };

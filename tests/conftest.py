@@ -11,6 +11,9 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: larger CPU oracle cases")
+    # progress notes of long GPU cases bypass output capture (see gpu_util.note)
+    import gpu_util
+    gpu_util.CAPTURE = config.pluginmanager.getplugin("capturemanager")
 
 
 @pytest.fixture(scope="session")

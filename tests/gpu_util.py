@@ -4,9 +4,18 @@ import sys
 import numpy as np
 
 
+# pytest's capture manager, set by conftest: notes are written with capture suspended, so the
+# progress of a long case (minutes of CPU truth computations) shows while it runs
+CAPTURE = None
+
+
 def note(msg):
     """Name the case before a GPU step (flushed, so a crash still shows it)."""
-    print(f"[gpu-case] {msg}", flush=True)
+    if CAPTURE is not None:
+        with CAPTURE.global_and_fixture_disabled():
+            print(f"[gpu-case] {msg}", flush=True)
+    else:
+        print(f"[gpu-case] {msg}", flush=True)
     sys.stdout.flush()
 
 
