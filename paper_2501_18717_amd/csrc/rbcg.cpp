@@ -95,6 +95,11 @@ struct rbcg_op {
   void* zt = nullptr;       // gram: FP32 Z^T (d x ld_zt), for the FP64 products and residuals
   int64_t ld_zt = 0;
   int device = 0;
+  // dense, host-resident (streamed): A in page-locked host memory (d x ld), copied chunk by
+  // chunk into `stage` (chunk x ld) for every product; data is null
+  const double* host = nullptr;
+  int64_t chunk = 0;
+  double* stage = nullptr;
 };
 
 #define HIP_TRY(x)                                  \
@@ -342,8 +347,39 @@ extern "C" int rbcg_op_create_gram(rbcg_ctx* ctx, rbcg_op** out, int64_t n, int6
   return RBCG_OK;
 }
 
+extern "C" int rbcg_op_create_dense_host(rbcg_ctx* ctx, rbcg_op** out, int64_t d, const double* A, int64_t lda,
+                                         int64_t chunk_rows) {
+  if (!ctx || !out || !A || d < 1 || lda < d || d > (int64_t)1 << 30) return RBCG_ERR_INVALID_ARG;
+  if (chunk_rows < 1 || chunk_rows > d || (double)chunk_rows * lda > (double)((int64_t)1 << 40))
+    return RBCG_ERR_INVALID_ARG;
+  *out = nullptr;
+  // page-locked host memory only: a pageable source would make every chunk copy synchronous
+  hipPointerAttribute_t at{};
+  if (hipPointerGetAttributes(&at, A) != hipSuccess || at.type != hipMemoryTypeHost) {
+    (void)hipGetLastError();
+    return RBCG_ERR_INVALID_ARG;
+  }
+  rbcg_op* op = new rbcg_op();
+  op->kind = RBCG_OP_DENSE;
+  op->d = d;
+  op->data = nullptr;
+  op->ld = lda;
+  op->lo_t = RBCG_F64;
+  op->device = ctx->device;
+  op->host = A;
+  op->chunk = chunk_rows;
+  if (hipMalloc(&op->stage, (size_t)chunk_rows * lda * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    delete op;
+    return RBCG_ERR_OOM;
+  }
+  *out = op;
+  return RBCG_OK;
+}
+
 extern "C" int rbcg_op_destroy(rbcg_op* op) {
   if (!op) return RBCG_ERR_INVALID_ARG;
+  if (op->stage) (void)hipFree(op->stage);
   if (op->lo) (void)hipFree(op->lo);
   if (op->lot) (void)hipFree(op->lot);
   if (op->zt) (void)hipFree(op->zt);
@@ -503,8 +539,11 @@ static const T* dptr(unsigned char* dbase, size_t off) {
 
 // One enqueued kernel launch of the step program.
 struct Launch {
-  enum Kind { NT, FIN, NN, QR, DIAG, TRIF, CONV, CVT, COPY, FILL } kind;
+  enum Kind { NT, FIN, NN, QR, DIAG, TRIF, CONV, CVT, COPY, FILL, H2D } kind;
   size_t off = 0;
+  const void* hsrc = nullptr;           // H2D: page-locked host source, device target, bytes
+  void* ddst = nullptr;
+  size_t nbytes = 0;
   int nz = 0;
   int a0 = 0, a1 = 0, a2 = 0, a3 = 0;   // kind-specific sizes
   bool flag = false;
@@ -555,6 +594,7 @@ static void prof_collect(rbcg_ctx* c) {
 
 static hipError_t enqueue(const Launch& L, unsigned char* dbase, const int32_t* act, hipStream_t st) {
   switch (L.kind) {
+    case Launch::H2D: return hipMemcpyAsync(L.ddst, L.hsrc, L.nbytes, hipMemcpyHostToDevice, st);
     case Launch::NT:
       if (L.a0 & (1 << 13))   // BF16 Gram-operator pass (FP32 split-K partials)
         return launch_gram_bf16(dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a2, L.a3, act, st);
@@ -961,7 +1001,77 @@ struct DenseBatch {
 };
 
 static bool batched_dense(const Engine& E, const MvGroup& G) {
-  return E.Gs.size() > 1 && G.op->kind == RBCG_OP_DENSE && G.N <= 144;
+  return E.Gs.size() > 1 && G.op->kind == RBCG_OP_DENSE && !G.op->host && G.N <= 144;
+}
+
+// Product with a host-resident dense operator (the out-of-core setting of Sec. 7.1.1): for every
+// row chunk of A, a copy of its rows into the operator's staging buffer, the FP64 tall kernel on
+// those rows (split-K partials) and the reduction whose epilogue (mode, as in emit_apply) writes
+// rows [r0, r0 + rows) of O.  The copies and kernels follow each other on one stream, so one
+// staging buffer serves every chunk.  X: N <= 144 rows of length d; part holds part_elems values.
+static void emit_streamed(Staging& stg, std::vector<Launch>& out, const rbcg_op* op, int N, RowOp X, RowOp O,
+                          int mode, RowOp rhs, const double* mu_dev, double alpha, double* part, size_t part_elems,
+                          int act_idx) {
+  const int d = (int)op->d;
+  const int cr = (int)op->chunk;
+  auto shift = [](RowOp o, int r0) {   // element r0 of every row
+    o.p = (const double*)o.p + r0;
+    return o;
+  };
+  for (int r0 = 0; r0 < d; r0 += cr) {
+    const int rows = std::min(cr, d - r0);
+    Launch H{Launch::H2D};
+    H.hsrc = op->host + (size_t)r0 * op->ld;
+    H.ddst = op->stage;
+    H.nbytes = (size_t)rows * op->ld * sizeof(double);
+    out.push_back(H);
+    // about 1024 workgroups of 64 rows, at least two splits (the epilogue reads partials), and
+    // no more than the partial buffer holds
+    const int tiles = (rows + 63) / 64;
+    int s = std::max(2, std::min(std::max(1, 1024 / tiles), std::max(2, d / 512)));
+    s = (int)std::min<size_t>((size_t)s, part_elems / ((size_t)rows * N));
+    NtDesc nd{};
+    nd.P = plain_rows(op->stage, op->ld);
+    nd.X = X;
+    nd.M = rows;
+    nd.N = N;
+    nd.K = d;
+    nd.active = act_idx;
+    nd.part = part;
+    nd.out = nullptr;
+    nd.out_t = DT_F64;
+    Launch L{Launch::NT};
+    L.off = stg.add(std::vector<NtDesc>{nd});
+    L.nz = 1;
+    L.a0 = DT_F64 | (1 << 9) | (op->ld % 2 == 0 ? (1 << 10) : 0);
+    L.a1 = rows;
+    L.a2 = N;
+    L.a3 = s;
+    L.prof = true;
+    L.flops = 2.0 * rows * (double)d * N;
+    L.bytes = (double)rows * d * 8.0;
+    out.push_back(L);
+    FinDesc f{};
+    f.part = part;
+    f.M = rows;
+    f.N = N;
+    f.splits = s;
+    f.mode = mode;
+    f.O = shift(O, r0);
+    f.alpha = alpha;
+    f.active = act_idx;
+    if (mode == FIN_RESID) {
+      f.rhs = shift(rhs, r0);
+      f.xin = shift(X, r0);
+      f.mu = mu_dev;
+    }
+    Launch F{Launch::FIN};
+    F.off = stg.add(std::vector<FinDesc>{f});
+    F.nz = 1;
+    F.a1 = rows;
+    F.a2 = N;
+    out.push_back(F);
+  }
 }
 
 static void emit_dense_batch(Program& pg, std::vector<Launch>& out, DenseBatch& B, int dtype) {
@@ -1057,6 +1167,18 @@ static void add_matvec(Program& pg, std::vector<Launch>& out, Engine& E, int j) 
       B.splits = G.splits2;   // common to all batched dense groups (size_partials)
       B.flops += 2.0 * d * (double)d * G.N;
       B.bytes += (double)d * d * (G.mv_t == RBCG_F32 ? 4.0 : 8.0);
+      continue;
+    }
+    if (op->kind == RBCG_OP_DENSE && op->host) {   // FP64 products streamed from host memory
+      const int nch = (G.N + 143) / 144;
+      const int cw = (G.N + nch - 1) / nch;
+      for (int c0 = 0; c0 < G.N; c0 += cw) {
+        RowOp Xc = Xb, Oc = Wb;
+        Xc.p = (const double*)Xb.p + (size_t)c0 * Xb.ld;
+        Oc.p = (const double*)Wb.p + (size_t)c0 * Wb.ld;
+        emit_streamed(pg.stg, out, op, std::min(cw, G.N - c0), Xc, Oc, FIN_TRANS, RowOp{}, nullptr, 1.0, G.part,
+                      G.part_elems, act_idx);
+      }
       continue;
     }
     if (op->kind == RBCG_OP_DENSE) {
@@ -1513,7 +1635,10 @@ static void size_partials(Engine& E, const rbcg_ctx* ctx) {
     const int d = (int)G.op->d;
     int tiles = (d + 15) / 16, t2w = 0, new_ = 0;
     int Kp = (G.op->kind == RBCG_OP_GRAM && G.mv_t == RBCG_BF16) ? (int)G.op->n : d;
-    if (G.op->kind == RBCG_OP_GRAM && G.mv_t != RBCG_BF16) {
+    if (G.op->host) {
+      // streamed operator: partials of one row chunk at a time (at most 4 d N values in all)
+      G.splits2 = 4;
+    } else if (G.op->kind == RBCG_OP_GRAM && G.mv_t != RBCG_BF16) {
       // FP64 path: the second pass W = Z^T (Z X) on the tall kernel, split over n
       G.splits2 = gram64_splits(d, G.op->n);
     } else if (G.op->kind == RBCG_OP_DENSE && G.mv_t == RBCG_F32 && wide_shape(G.N, &t2w, &new_)) {
@@ -1530,7 +1655,7 @@ static void size_partials(Engine& E, const rbcg_ctx* ctx) {
       G.splits2 = pick_splits(tiles, 1, Kp);
     }
     G.tune.clear();
-    if (ctx && E.Gs.size() == 1 && G.op->kind == RBCG_OP_DENSE && G.N <= 144) {
+    if (ctx && E.Gs.size() == 1 && G.op->kind == RBCG_OP_DENSE && !G.op->host && G.N <= 144) {
       const auto key = std::make_tuple(G.mv_t, (int64_t)d, G.N);
       const auto it = ctx->tuned_splits.find(key);
       if (it != ctx->tuned_splits.end()) {
@@ -1841,6 +1966,15 @@ static void emit_apply(Staging& stg, std::vector<Launch>& out, const rbcg_op* op
   const bool pv1 = op->ld % 4 == 0 && ((uintptr_t)op->data % 16) == 0;
   const int nch = (rows + 143) / 144;
   const int cw = (rows + nch - 1) / nch;
+  if (dense && op->host) {   // streamed from host memory, chunk by chunk
+    for (int c0 = 0; c0 < rows; c0 += cw) {
+      const int nc = std::min(cw, rows - c0);
+      emit_streamed(stg, out, op, nc, rows_from(X, c0), rows_from(R, c0), mode,
+                    mode == FIN_RESID ? rows_from(rhs, c0) : RowOp{}, mu_dev ? mu_dev + c0 : nullptr, alpha, part,
+                    rp.part_elems, -1);
+    }
+    return;
+  }
   for (int c0 = 0; c0 < rows; c0 += cw) {
     const int nc = std::min(cw, rows - c0);
     NtDesc n2{};
@@ -2625,6 +2759,7 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
   if (!ctx || !op || !b || !mu || !X || !opts || !info || L < 1 || L > 256 || !valid_opts(opts))
     return RBCG_ERR_INVALID_ARG;
   if (k < 0 || k >= op->d || k + 1 > kMaxBlock) return RBCG_ERR_INVALID_ARG;
+  if (op->host) return RBCG_ERR_UNSUPPORTED;   // streamed operators: solve, op_apply, Nystrom PCG
   for (int64_t l = 0; l < L; ++l)
     if (!(mu[l] >= 0.0) || !std::isfinite(mu[l])) return RBCG_ERR_INVALID_ARG;
   if (!op_supports(op, opts->matvec)) return RBCG_ERR_UNSUPPORTED;
@@ -3394,11 +3529,13 @@ static int sqrt_driver(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, const doubl
 
 extern "C" int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, const double* B, double* Y,
                                const rbcg_opts* opts, rbcg_info* info) {
+  if (op && op->host) return RBCG_ERR_UNSUPPORTED;
   return sqrt_driver(ctx, op, ms, B, Y, opts, info, false);
 }
 
 extern "C" int rbcg_invsqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, const double* B, double* Y,
                                   const rbcg_opts* opts, rbcg_info* info) {
+  if (op && op->host) return RBCG_ERR_UNSUPPORTED;
   return sqrt_driver(ctx, op, ms, B, Y, opts, info, true);
 }
 
