@@ -96,10 +96,15 @@ struct rbcg_op {
   int64_t ld_zt = 0;
   int device = 0;
   // dense, host-resident (streamed): A in page-locked host memory (d x ld), copied chunk by
-  // chunk into `stage` (chunk x ld) for every product; data is null
+  // chunk into two alternating staging buffers (chunk x ld each) on the handle's copy stream for
+  // every product; data is null.  copied[b] marks chunk data in stage[b], freed[b] the end of the
+  // kernel that read it.
   const double* host = nullptr;
   int64_t chunk = 0;
-  double* stage = nullptr;
+  double* stage[2] = {nullptr, nullptr};
+  hipStream_t copy_st = nullptr;
+  hipEvent_t copied[2] = {nullptr, nullptr};
+  hipEvent_t freed[2] = {nullptr, nullptr};
 };
 
 #define HIP_TRY(x)                                  \
@@ -368,10 +373,17 @@ extern "C" int rbcg_op_create_dense_host(rbcg_ctx* ctx, rbcg_op** out, int64_t d
   op->device = ctx->device;
   op->host = A;
   op->chunk = chunk_rows;
-  if (hipMalloc(&op->stage, (size_t)chunk_rows * lda * sizeof(double)) != hipSuccess) {
-    (void)hipGetLastError();
-    delete op;
-    return RBCG_ERR_OOM;
+  hipError_t e = hipSuccess;
+  for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+    e = hipMalloc(&op->stage[b], (size_t)chunk_rows * lda * sizeof(double));
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&op->copied[b], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&op->freed[b], hipEventDisableTiming);
+  }
+  // default priority; non-blocking, so a context on the null stream does not serialise with it
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&op->copy_st, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    rbcg_op_destroy(op);
+    return fail_hip(e, "streamed operator set-up");
   }
   *out = op;
   return RBCG_OK;
@@ -379,7 +391,15 @@ extern "C" int rbcg_op_create_dense_host(rbcg_ctx* ctx, rbcg_op** out, int64_t d
 
 extern "C" int rbcg_op_destroy(rbcg_op* op) {
   if (!op) return RBCG_ERR_INVALID_ARG;
-  if (op->stage) (void)hipFree(op->stage);
+  if (op->copy_st) {
+    (void)hipStreamSynchronize(op->copy_st);
+    (void)hipStreamDestroy(op->copy_st);
+  }
+  for (int b = 0; b < 2; ++b) {
+    if (op->copied[b]) (void)hipEventDestroy(op->copied[b]);
+    if (op->freed[b]) (void)hipEventDestroy(op->freed[b]);
+    if (op->stage[b]) (void)hipFree(op->stage[b]);
+  }
   if (op->lo) (void)hipFree(op->lo);
   if (op->lot) (void)hipFree(op->lot);
   if (op->zt) (void)hipFree(op->zt);
@@ -539,11 +559,16 @@ static const T* dptr(unsigned char* dbase, size_t off) {
 
 // One enqueued kernel launch of the step program.
 struct Launch {
-  enum Kind { NT, FIN, NN, QR, DIAG, TRIF, CONV, CVT, COPY, FILL, H2D } kind;
+  enum Kind { NT, FIN, NN, QR, DIAG, TRIF, CONV, CVT, COPY, FILL, H2D, FREED } kind;
   size_t off = 0;
-  const void* hsrc = nullptr;           // H2D: page-locked host source, device target, bytes
+  // H2D: chunk copy from page-locked host memory on the operator's copy stream (after `freed`,
+  // then `copied` recorded and waited for on the launch stream); FREED: `freed` recorded on the
+  // launch stream once the kernel reading the staging buffer is issued
+  const void* hsrc = nullptr;
   void* ddst = nullptr;
   size_t nbytes = 0;
+  hipStream_t cst = nullptr;
+  hipEvent_t copied = nullptr, freed = nullptr;
   int nz = 0;
   int a0 = 0, a1 = 0, a2 = 0, a3 = 0;   // kind-specific sizes
   bool flag = false;
@@ -594,7 +619,14 @@ static void prof_collect(rbcg_ctx* c) {
 
 static hipError_t enqueue(const Launch& L, unsigned char* dbase, const int32_t* act, hipStream_t st) {
   switch (L.kind) {
-    case Launch::H2D: return hipMemcpyAsync(L.ddst, L.hsrc, L.nbytes, hipMemcpyHostToDevice, st);
+    case Launch::H2D: {
+      hipError_t e = hipStreamWaitEvent(L.cst, L.freed, 0);
+      if (e == hipSuccess) e = hipMemcpyAsync(L.ddst, L.hsrc, L.nbytes, hipMemcpyHostToDevice, L.cst);
+      if (e == hipSuccess) e = hipEventRecord(L.copied, L.cst);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, L.copied, 0);
+      return e;
+    }
+    case Launch::FREED: return hipEventRecord(L.freed, st);
     case Launch::NT:
       if (L.a0 & (1 << 13))   // BF16 Gram-operator pass (FP32 split-K partials)
         return launch_gram_bf16(dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a2, L.a3, act, st);
@@ -1005,10 +1037,11 @@ static bool batched_dense(const Engine& E, const MvGroup& G) {
 }
 
 // Product with a host-resident dense operator (the out-of-core setting of Sec. 7.1.1): for every
-// row chunk of A, a copy of its rows into the operator's staging buffer, the FP64 tall kernel on
-// those rows (split-K partials) and the reduction whose epilogue (mode, as in emit_apply) writes
-// rows [r0, r0 + rows) of O.  The copies and kernels follow each other on one stream, so one
-// staging buffer serves every chunk.  X: N <= 144 rows of length d; part holds part_elems values.
+// row chunk of A, a copy of its rows into one of the operator's two staging buffers (on its copy
+// stream, so the next chunk, or the next product's first chunks, copy while this one computes
+// and while the step's other kernels run), the FP64 tall kernel on those rows (split-K partials)
+// and the reduction whose epilogue (mode, as in emit_apply) writes rows [r0, r0 + rows) of O.
+// X: N <= 144 rows of length d; part holds part_elems values.
 static void emit_streamed(Staging& stg, std::vector<Launch>& out, const rbcg_op* op, int N, RowOp X, RowOp O,
                           int mode, RowOp rhs, const double* mu_dev, double alpha, double* part, size_t part_elems,
                           int act_idx) {
@@ -1020,10 +1053,14 @@ static void emit_streamed(Staging& stg, std::vector<Launch>& out, const rbcg_op*
   };
   for (int r0 = 0; r0 < d; r0 += cr) {
     const int rows = std::min(cr, d - r0);
+    const int sb = (r0 / cr) & 1;   // staging buffer of this chunk
     Launch H{Launch::H2D};
     H.hsrc = op->host + (size_t)r0 * op->ld;
-    H.ddst = op->stage;
+    H.ddst = op->stage[sb];
     H.nbytes = (size_t)rows * op->ld * sizeof(double);
+    H.cst = op->copy_st;
+    H.copied = op->copied[sb];
+    H.freed = op->freed[sb];
     out.push_back(H);
     // about 1024 workgroups of 64 rows, at least two splits (the epilogue reads partials), and
     // no more than the partial buffer holds
@@ -1031,7 +1068,7 @@ static void emit_streamed(Staging& stg, std::vector<Launch>& out, const rbcg_op*
     int s = std::max(2, std::min(std::max(1, 1024 / tiles), std::max(2, d / 512)));
     s = (int)std::min<size_t>((size_t)s, part_elems / ((size_t)rows * N));
     NtDesc nd{};
-    nd.P = plain_rows(op->stage, op->ld);
+    nd.P = plain_rows(op->stage[sb], op->ld);
     nd.X = X;
     nd.M = rows;
     nd.N = N;
@@ -1051,6 +1088,9 @@ static void emit_streamed(Staging& stg, std::vector<Launch>& out, const rbcg_op*
     L.flops = 2.0 * rows * (double)d * N;
     L.bytes = (double)rows * d * 8.0;
     out.push_back(L);
+    Launch Fr{Launch::FREED};
+    Fr.freed = op->freed[sb];
+    out.push_back(Fr);
     FinDesc f{};
     f.part = part;
     f.M = rows;
