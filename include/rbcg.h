@@ -112,18 +112,20 @@ int rbcg_op_create_gram(rbcg_ctx* ctx, rbcg_op** op, int64_t n, int64_t d, const
  * the number of matrix-loads).  A_host is d x d, row-major, FP64, leading
  * dimension lda >= d, in page-locked host memory (hipHostMalloc, or a pinned
  * torch tensor); pageable memory is rejected with RBCG_ERR_INVALID_ARG.
- * chunk_rows (1 <= chunk_rows <= d) rows are copied per chunk into a device
- * staging buffer of chunk_rows * lda doubles that the handle allocates (freed by
- * rbcg_op_destroy); the FP64 block-product kernel then forms those rows of
- * A X.  Chunk copies and kernels are ordered on the context's stream.
- * Supported by rbcg_solve (plain FP64 products), rbcg_op_apply /
- * rbcg_op_apply_noalloc (matvec RBCG_F64) and rbcg_nystrom_pcg; rbcg_path,
- * rbcg_sqrt_apply and rbcg_invsqrt_apply return RBCG_ERR_UNSUPPORTED, and so
- * do low-precision products (the handle holds no FP32 copy).
- * A converged solve may still stream one product issued ahead of the host's
- * convergence check. */
+ * chunk_rows (1 <= chunk_rows <= d) rows are copied per chunk, on a copy
+ * stream the handle owns, into one of two device staging buffers of
+ * chunk_rows * lda doubles; the block-product kernel then forms those rows of
+ * A X while the next chunk copies.  `lo` = RBCG_F32 also builds an FP32 copy
+ * (RNE, rows padded to 64 values) in page-locked host memory the handle
+ * allocates, which low-precision products stream (half the bytes per load);
+ * FP64 residuals always stream A itself.  Everything the handle allocates is
+ * freed by rbcg_op_destroy.  Supported by rbcg_solve, rbcg_op_apply /
+ * rbcg_op_apply_noalloc and rbcg_nystrom_pcg; rbcg_path, rbcg_sqrt_apply and
+ * rbcg_invsqrt_apply return RBCG_ERR_UNSUPPORTED, and so do FP32 products
+ * without the FP32 copy.  A converged solve may still stream one product
+ * issued ahead of the host's convergence check. */
 int rbcg_op_create_dense_host(rbcg_ctx* ctx, rbcg_op** op, int64_t d, const double* A_host /*host, pinned*/,
-                              int64_t lda, int64_t chunk_rows);
+                              int64_t lda, int64_t chunk_rows, int lo);
 int rbcg_op_destroy(rbcg_op* op);
 
 /* ---------------------------------------------------------------------- options */

@@ -101,6 +101,7 @@ struct rbcg_op {
   // kernel that read it.
   const double* host = nullptr;
   int64_t chunk = 0;
+  float* host_lo = nullptr;       // FP32 copy (RNE) in page-locked host memory, d x ld_lo (lo F32)
   double* stage[2] = {nullptr, nullptr};
   hipStream_t copy_st = nullptr;
   hipEvent_t copied[2] = {nullptr, nullptr};
@@ -353,8 +354,9 @@ extern "C" int rbcg_op_create_gram(rbcg_ctx* ctx, rbcg_op** out, int64_t n, int6
 }
 
 extern "C" int rbcg_op_create_dense_host(rbcg_ctx* ctx, rbcg_op** out, int64_t d, const double* A, int64_t lda,
-                                         int64_t chunk_rows) {
+                                         int64_t chunk_rows, int lo) {
   if (!ctx || !out || !A || d < 1 || lda < d || d > (int64_t)1 << 30) return RBCG_ERR_INVALID_ARG;
+  if (lo != RBCG_F64 && lo != RBCG_F32) return RBCG_ERR_INVALID_ARG;
   if (chunk_rows < 1 || chunk_rows > d || (double)chunk_rows * lda > (double)((int64_t)1 << 40))
     return RBCG_ERR_INVALID_ARG;
   *out = nullptr;
@@ -369,13 +371,27 @@ extern "C" int rbcg_op_create_dense_host(rbcg_ctx* ctx, rbcg_op** out, int64_t d
   op->d = d;
   op->data = nullptr;
   op->ld = lda;
-  op->lo_t = RBCG_F64;
+  op->lo_t = lo;
   op->device = ctx->device;
   op->host = A;
   op->chunk = chunk_rows;
   hipError_t e = hipSuccess;
+  if (lo == RBCG_F32) {   // FP32 copy on the host, rows padded to 64 values (16-byte aligned rows)
+    op->ld_lo = round_up(d, 64);
+    e = hipHostMalloc((void**)&op->host_lo, (size_t)d * op->ld_lo * sizeof(float), hipHostMallocDefault);
+    if (e == hipSuccess) {
+      for (int64_t i = 0; i < d; ++i) {
+        const double* src = A + i * lda;
+        float* dst = op->host_lo + i * op->ld_lo;
+        for (int64_t j = 0; j < d; ++j) dst[j] = (float)src[j];   // round to nearest even
+        for (int64_t j = d; j < op->ld_lo; ++j) dst[j] = 0.f;
+      }
+    }
+  }
+  // a staging buffer holds one chunk of either copy (FP32 rows are at most twice as short)
+  const size_t stage_bytes = (size_t)chunk_rows * std::max<size_t>(lda * sizeof(double), op->ld_lo * sizeof(float));
   for (int b = 0; b < 2 && e == hipSuccess; ++b) {
-    e = hipMalloc(&op->stage[b], (size_t)chunk_rows * lda * sizeof(double));
+    e = hipMalloc(&op->stage[b], stage_bytes);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&op->copied[b], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&op->freed[b], hipEventDisableTiming);
   }
@@ -400,6 +416,7 @@ extern "C" int rbcg_op_destroy(rbcg_op* op) {
     if (op->freed[b]) (void)hipEventDestroy(op->freed[b]);
     if (op->stage[b]) (void)hipFree(op->stage[b]);
   }
+  if (op->host_lo) (void)hipHostFree(op->host_lo);
   if (op->lo) (void)hipFree(op->lo);
   if (op->lot) (void)hipFree(op->lot);
   if (op->zt) (void)hipFree(op->zt);
@@ -1041,12 +1058,17 @@ static bool batched_dense(const Engine& E, const MvGroup& G) {
 // stream, so the next chunk, or the next product's first chunks, copy while this one computes
 // and while the step's other kernels run), the FP64 tall kernel on those rows (split-K partials)
 // and the reduction whose epilogue (mode, as in emit_apply) writes rows [r0, r0 + rows) of O.
-// X: N <= 144 rows of length d; part holds part_elems values.
+// X: N <= 144 rows of length d (FP32 when f32: the FP32 copy of A streams and the FP32 kernels
+// run, the wide 32x32x2 one for its widths); part holds part_elems values.
 static void emit_streamed(Staging& stg, std::vector<Launch>& out, const rbcg_op* op, int N, RowOp X, RowOp O,
                           int mode, RowOp rhs, const double* mu_dev, double alpha, double* part, size_t part_elems,
-                          int act_idx) {
+                          int act_idx, bool f32 = false) {
   const int d = (int)op->d;
   const int cr = (int)op->chunk;
+  const int64_t lds = f32 ? op->ld_lo : op->ld;   // staged row length
+  const size_t esz = f32 ? sizeof(float) : sizeof(double);
+  int t2 = 0, ne = 0;
+  const bool wide = f32 && wide_shape(N, &t2, &ne);
   auto shift = [](RowOp o, int r0) {   // element r0 of every row
     o.p = (const double*)o.p + r0;
     return o;
@@ -1055,9 +1077,9 @@ static void emit_streamed(Staging& stg, std::vector<Launch>& out, const rbcg_op*
     const int rows = std::min(cr, d - r0);
     const int sb = (r0 / cr) & 1;   // staging buffer of this chunk
     Launch H{Launch::H2D};
-    H.hsrc = op->host + (size_t)r0 * op->ld;
+    H.hsrc = f32 ? (const void*)(op->host_lo + (size_t)r0 * lds) : (const void*)(op->host + (size_t)r0 * lds);
     H.ddst = op->stage[sb];
-    H.nbytes = (size_t)rows * op->ld * sizeof(double);
+    H.nbytes = (size_t)rows * lds * esz;
     H.cst = op->copy_st;
     H.copied = op->copied[sb];
     H.freed = op->freed[sb];
@@ -1068,7 +1090,7 @@ static void emit_streamed(Staging& stg, std::vector<Launch>& out, const rbcg_op*
     int s = std::max(2, std::min(std::max(1, 1024 / tiles), std::max(2, d / 512)));
     s = (int)std::min<size_t>((size_t)s, part_elems / ((size_t)rows * N));
     NtDesc nd{};
-    nd.P = plain_rows(op->stage[sb], op->ld);
+    nd.P = plain_rows(op->stage[sb], lds);
     nd.X = X;
     nd.M = rows;
     nd.N = N;
@@ -1080,13 +1102,14 @@ static void emit_streamed(Staging& stg, std::vector<Launch>& out, const rbcg_op*
     Launch L{Launch::NT};
     L.off = stg.add(std::vector<NtDesc>{nd});
     L.nz = 1;
-    L.a0 = DT_F64 | (1 << 9) | (op->ld % 2 == 0 ? (1 << 10) : 0);
+    L.a0 = f32 ? (DT_F32 | (1 << 9) | (1 << 10) | (wide ? (1 << 11) : 0))
+               : (DT_F64 | (1 << 9) | (op->ld % 2 == 0 ? (1 << 10) : 0));
     L.a1 = rows;
     L.a2 = N;
     L.a3 = s;
     L.prof = true;
     L.flops = 2.0 * rows * (double)d * N;
-    L.bytes = (double)rows * d * 8.0;
+    L.bytes = (double)rows * d * (double)esz;
     out.push_back(L);
     Launch Fr{Launch::FREED};
     Fr.freed = op->freed[sb];
@@ -1100,6 +1123,7 @@ static void emit_streamed(Staging& stg, std::vector<Launch>& out, const rbcg_op*
     f.O = shift(O, r0);
     f.alpha = alpha;
     f.active = act_idx;
+    f.part_f32 = wide ? 1 : 0;   // the 32x32x2 kernel stores FP32 partials
     if (mode == FIN_RESID) {
       f.rhs = shift(rhs, r0);
       f.xin = shift(X, r0);
@@ -1209,15 +1233,36 @@ static void add_matvec(Program& pg, std::vector<Launch>& out, Engine& E, int j) 
       B.bytes += (double)d * d * (G.mv_t == RBCG_F32 ? 4.0 : 8.0);
       continue;
     }
-    if (op->kind == RBCG_OP_DENSE && op->host) {   // FP64 products streamed from host memory
+    if (op->kind == RBCG_OP_DENSE && op->host) {   // products streamed from host memory
+      const bool f32 = G.mv_t == RBCG_F32;
+      RowOp Xs = Xb;
+      if (f32) {   // FP32 copy of the block (unless the block's last factor application wrote it)
+        if (!fused_q32(E)) {
+          CvtDesc c{};
+          c.src = Xb;
+          c.dst = plain_rows(G.xlo, G.ld_xlo);
+          c.rows = G.N;
+          c.cols = d;
+          c.src_t = DT_F64;
+          c.dst_t = DT_F32;
+          c.active = act_idx;
+          Launch C{Launch::CVT};
+          C.off = pg.stg.add(std::vector<CvtDesc>{c});
+          C.nz = 1;
+          C.a1 = G.N;
+          C.a2 = d;
+          out.push_back(C);
+        }
+        Xs = plain_rows(G.xlo, G.ld_xlo);
+      }
       const int nch = (G.N + 143) / 144;
       const int cw = (G.N + nch - 1) / nch;
       for (int c0 = 0; c0 < G.N; c0 += cw) {
-        RowOp Xc = Xb, Oc = Wb;
-        Xc.p = (const double*)Xb.p + (size_t)c0 * Xb.ld;
+        RowOp Xc = Xs, Oc = Wb;
+        Xc.p = (const unsigned char*)Xs.p + (size_t)c0 * Xs.ld * (f32 ? sizeof(float) : sizeof(double));
         Oc.p = (const double*)Wb.p + (size_t)c0 * Wb.ld;
         emit_streamed(pg.stg, out, op, std::min(cw, G.N - c0), Xc, Oc, FIN_TRANS, RowOp{}, nullptr, 1.0, G.part,
-                      G.part_elems, act_idx);
+                      G.part_elems, act_idx, f32);
       }
       continue;
     }
@@ -1844,7 +1889,71 @@ static int upload(rbcg_ctx* ctx, const Staging& stg, unsigned char* dst) {
 
 // Run the start block and up to t_max Lanczos steps; stops early once every problem's monitor
 // has converged.  Returns the number of steps enqueued.
+// Step loop when a product streams the operator from host memory: a matrix-load then costs
+// milliseconds of host-link time, so the host learns each step's convergence (its monitor runs
+// right after the step) before it issues the next product, and no product is streamed past
+// convergence.  Only the next product's first two chunk copies (one per staging buffer) are
+// issued ahead, so the link keeps working while the monitor runs; the step list then skips them.
+static int run_steps_streamed(rbcg_ctx* ctx, Engine& E, Program& pg, unsigned char* dbase, int* steps_run) {
+  hipStream_t st = ctx->stream;
+  const int np = (int)E.P.size();
+  for (const auto& L : pg.steps[0]) HIP_TRY(enqueue(L, dbase, E.active, st));
+  auto run = [&](const Launch& L) -> hipError_t {
+    hipError_t e = prof_begin(ctx, L, st);
+    if (e == hipSuccess) e = enqueue(L, dbase, E.active, st);
+    if (e == hipSuccess) e = prof_end(ctx, L, st);
+    return e;
+  };
+  const int tlim = E.t_run > 0 ? std::min(E.t_run, E.t_max) : E.t_max;
+  int ahead = 0;   // chunk copies of this step's product already issued
+  int j = 0;
+  for (; j < tlim; ++j) {
+    int skipped = 0;
+    for (const auto& L : pg.steps[j + 1]) {
+      if (L.kind == Launch::H2D && skipped < ahead) {
+        ++skipped;
+        continue;
+      }
+      HIP_TRY(run(L));
+    }
+    ahead = 0;
+    const bool mon = !pg.mon[j].empty();
+    if (mon) {
+      HIP_TRY(hipEventRecord(ctx->ev_mon, st));
+      HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->ev_mon, 0));
+      for (const auto& L : pg.mon[j]) HIP_TRY(enqueue(L, dbase, E.active, ctx->side));
+    }
+    if (j + 1 < tlim) {
+      const auto& nx = pg.steps[j + 2];
+      const int pe = (int)pg.prod_end.size() > j + 2 ? pg.prod_end[j + 2] : (int)nx.size();
+      for (int i = 0; i < pe && ahead < 2; ++i)
+        if (nx[i].kind == Launch::H2D) {
+          HIP_TRY(enqueue(nx[i], dbase, E.active, st));
+          ++ahead;
+        }
+    }
+    if (!mon) continue;
+    HIP_TRY(hipStreamSynchronize(ctx->side));
+    bool any = false;
+    for (int p = 0; p < np; ++p) any |= __atomic_load_n(E.done_h + p, __ATOMIC_ACQUIRE) != 0;
+    if (!any) {
+      ++j;
+      break;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipStreamSynchronize(ctx->side));
+  prof_collect(ctx);
+  *steps_run = j;
+  return RBCG_OK;
+}
+
 static int run_steps(rbcg_ctx* ctx, Engine& E, Program& pg, unsigned char* dbase, int* steps_run) {
+  if (E.done_h) {
+    bool streamed = false;
+    for (const auto& G : E.Gs) streamed |= G.op->host != nullptr;
+    if (streamed) return run_steps_streamed(ctx, E, pg, dbase, steps_run);
+  }
   hipStream_t st = ctx->stream;
   const int np = (int)E.P.size();
   for (const auto& L : pg.steps[0]) HIP_TRY(enqueue(L, dbase, E.active, st));
@@ -2138,6 +2247,7 @@ static bool valid_opts(const rbcg_opts* o) {
 }
 
 static bool op_supports(const rbcg_op* op, int mv) {
+  if (op->host) return mv == RBCG_F64 || (mv == RBCG_F32 && op->host_lo);
   if (mv == RBCG_F64) return true;
   if (op->kind == RBCG_OP_DENSE) return mv == RBCG_F32 && op->lo_t == RBCG_F32 && op->lo;
   return mv == RBCG_BF16 && op->lo_t == RBCG_BF16 && op->lo && op->lot;

@@ -59,7 +59,8 @@ _version = _sig("rbcg_version", ctypes.c_int, [])
 _create = _sig("rbcg_create", ctypes.c_int, [ctypes.POINTER(_vp), _vp])
 _destroy = _sig("rbcg_destroy", ctypes.c_int, [_vp])
 _op_dense = _sig("rbcg_op_create_dense", ctypes.c_int, [_vp, ctypes.POINTER(_vp), _i64, _vp, _i64, ctypes.c_int])
-_op_dense_host = _sig("rbcg_op_create_dense_host", ctypes.c_int, [_vp, ctypes.POINTER(_vp), _i64, _vp, _i64, _i64])
+_op_dense_host = _sig("rbcg_op_create_dense_host", ctypes.c_int,
+                      [_vp, ctypes.POINTER(_vp), _i64, _vp, _i64, _i64, ctypes.c_int])
 _op_gram = _sig("rbcg_op_create_gram", ctypes.c_int, [_vp, ctypes.POINTER(_vp), _i64, _i64, _vp, _i64, ctypes.c_int])
 _op_destroy = _sig("rbcg_op_destroy", ctypes.c_int, [_vp])
 _solve = _sig("rbcg_solve", ctypes.c_int, [_vp, _i64, ctypes.POINTER(_vp), _dp, ctypes.POINTER(_vp),
@@ -209,9 +210,10 @@ class DenseOperator:
 
 class DenseHostOperator(DenseOperator):
     """A (d x d, FP64, symmetric) kept in page-locked host memory; every product streams it to
-    the GPU in chunks of `chunk_rows` rows (plain FP64 products only)."""
+    the GPU in chunks of `chunk_rows` rows.  lo="f32" also keeps a pinned FP32 copy on the host,
+    which FP32 products stream."""
 
-    def __init__(self, ctx: Context, A, chunk_rows: int):
+    def __init__(self, ctx: Context, A, chunk_rows: int, lo: str = "f64"):
         import torch
         if not isinstance(A, torch.Tensor) or A.is_cuda or A.dtype != torch.float64 or not A.is_contiguous():
             raise ValueError("A must be a contiguous FP64 CPU tensor")
@@ -221,7 +223,7 @@ class DenseHostOperator(DenseOperator):
         if A.dim() != 2 or A.shape[1] != d:
             raise ValueError("A must be square")
         h = _vp()
-        _check(_op_dense_host(ctx.handle, ctypes.byref(h), d, _ptr(A), d, int(chunk_rows)),
+        _check(_op_dense_host(ctx.handle, ctypes.byref(h), d, _ptr(A), d, int(chunk_rows), DTYPES[lo]),
                "rbcg_op_create_dense_host")
         self._h, self.A, self.d, self.ctx = h, A, d, ctx
 

@@ -80,7 +80,7 @@ def test_null_context_rejected(lib):
     assert rbcg._invsqrt(None, None, 1, None, None, ctypes.byref(o), info) == -1
     assert rbcg._solve(None, 1, None, None, None, None, None, None, None, None) == -1
     assert rbcg._omega_fill(None, 1, 0, 4, 4, None, 4) == -1
-    assert rbcg._op_dense_host(None, ctypes.byref(h), 8, None, 8, 4) == -1
+    assert rbcg._op_dense_host(None, ctypes.byref(h), 8, None, 8, 4, 0) == -1
 
 
 @pytest.mark.parametrize("lo,hi,n", [(1e-6, 244.0, 32), (1e-3, 1.0, 16), (3.6e-6, 244.0, 32), (0.5, 2.0, 8)])

@@ -5,7 +5,10 @@ chunks, and every block product loads each chunk once).  Through the C ABI:
 - rbcg_op_apply streams A in chunks of `chunk_rows` rows; the product must
   equal the exact FP64 product to 1e-13 (relative, max norm) for ragged chunk
   counts, an odd leading dimension (no 16-byte rows), widths across the
-  column-chunk boundary of 144, and a single chunk;
+  column-chunk boundary of 144, and a single chunk; the streamed FP32 copy
+  gives fl32(A) fl32(X) to 2e-5;
+- mixed precision with streamed FP32 chunks and FP64 refinement reaches
+  rtol 1e-10 and the dense solution to 1e-8;
 - rbcg_solve with the streamed operator gives the oracle's bcg_t (eq. bcg_alg)
   to the plain-FP64 bound max(1e-12, 0.1 kappa u), converges to rtol exactly
   as the device-resident operator does, and also runs batched beside a
@@ -23,6 +26,7 @@ import pytest
 import synth
 from oracle import block_cg as ob
 from oracle import krylov as ok
+from oracle import truth as ot
 
 from gpu_util import a_err, fp64_bound, note, to_dev
 
@@ -65,6 +69,57 @@ def test_streamed_block_product(R, d, chunk, N):
         rbcg.op_apply_noalloc(ctx, op, to_dev(X), W, "f64")
         err2 = np.abs(W.cpu().numpy() - ref).max() / np.abs(ref).max()
         assert err2 <= 1e-13
+
+
+@pytest.mark.parametrize("d,chunk,N", [(777, 100, 65), (777, 100, 17), (1000, 64, 129), (777, 250, 200)])
+def test_streamed_fp32_block_product(R, d, chunk, N):
+    """FP32 copy streamed from host memory: the product equals the exact product of the
+    rounded operands fl32(A) fl32(X) to 2e-5 (FP32 accumulation), as the device-resident FP32
+    product does."""
+    import torch
+    rbcg, ctx = R
+    note(f"streamed f32 op_apply d={d} chunk={chunk} N={N}")
+    A = synth.dense_problem(3, d, 1.0, 4, 1e-3)["A"]
+    X = synth.rng(6, 0).standard_normal((N, d))
+    op = rbcg.DenseHostOperator(ctx, _pinned(A), chunk, lo="f32")
+    W = torch.full((N, d), float("nan"), dtype=torch.float64, device="cuda")
+    rbcg.op_apply(ctx, op, to_dev(X), W, "f32")
+    A32 = A.astype(np.float32).astype(np.float64)
+    X32 = X.astype(np.float32).astype(np.float64)
+    ref = X32 @ A32.T
+    err = np.abs(W.cpu().numpy() - ref).max() / np.abs(ref).max()
+    note(f"  rel err {err:.2e}")
+    assert err <= 2e-5
+    # the same handle still streams FP64 for FP64 products
+    rbcg.op_apply(ctx, op, to_dev(X), W, "f64")
+    ref64 = X @ A.T
+    assert np.abs(W.cpu().numpy() - ref64).max() / np.abs(ref64).max() <= 1e-13
+
+
+def test_streamed_mixed_solve_reaches_target(R):
+    """FP32 chunks + FP64 refinement (FP64 residuals from the FP64 host matrix) reach rtol 1e-10
+    and the dense solution to 1e-8 in the A_mu-norm, with the sweep and load counts of the
+    device-resident mixed solve."""
+    import torch
+    rbcg, ctx = R
+    P = synth.dense_problem(4, 1500, 1.5, 16, 1e-4)
+    note("streamed mixed solve d=1500 chunk=256 k=16 rtol 1e-10")
+    hop = rbcg.DenseHostOperator(ctx, _pinned(P["A"]), 256, lo="f32")
+    dop = rbcg.DenseOperator(ctx, to_dev(P["A"]), lo="f32")
+    b, om = to_dev(P["b"]), to_dev(P["omega"])
+    o = rbcg.opts(60, rtol=1e-10, matvec="f32", refine_max=8)
+    xh, xd = torch.zeros_like(b), torch.zeros_like(b)
+    rc, ih = rbcg.solve(ctx, [hop], [P["mu"]], [b], [om], [xh], [o], check=False)
+    assert rc == 0, ih
+    rc, idv = rbcg.solve(ctx, [dop], [P["mu"]], [b], [om], [xd], [o], check=False)
+    assert rc == 0, idv
+    xt = ot.solve_dense(P["A"], P["mu"], P["b"])
+    eh = a_err(P["A"], P["mu"], xh.cpu().numpy(), xt)
+    note(f"  sweeps {ih[0]['refine_sweeps']} loads {ih[0]['matrix_loads']} relres {ih[0]['relres']:.2e} "
+         f"err {eh:.2e}; device-resident sweeps {idv[0]['refine_sweeps']} loads {idv[0]['matrix_loads']}")
+    assert ih[0]["relres"] <= 1e-10 and ih[0]["precision_used"] == 1
+    assert eh <= 1e-8
+    assert abs(ih[0]["matrix_loads"] - idv[0]["matrix_loads"]) <= 2
 
 
 @pytest.fixture(scope="module")
@@ -164,8 +219,8 @@ def test_streamed_operator_rejections(R):
     # pageable host memory: rejected before any copy
     Ah = np.ascontiguousarray(P["A"])
     h = ctypes.c_void_p()
-    assert rbcg._op_dense_host(ctx.handle, ctypes.byref(h), 256, Ah.ctypes.data, 256, 64) == -1
+    assert rbcg._op_dense_host(ctx.handle, ctypes.byref(h), 256, Ah.ctypes.data, 256, 64, 0) == -1
     # chunk sizes out of range
     Ap = _pinned(P["A"])
-    assert rbcg._op_dense_host(ctx.handle, ctypes.byref(h), 256, Ap.data_ptr(), 256, 0) == -1
-    assert rbcg._op_dense_host(ctx.handle, ctypes.byref(h), 256, Ap.data_ptr(), 256, 257) == -1
+    assert rbcg._op_dense_host(ctx.handle, ctypes.byref(h), 256, Ap.data_ptr(), 256, 0, 0) == -1
+    assert rbcg._op_dense_host(ctx.handle, ctypes.byref(h), 256, Ap.data_ptr(), 256, 257, 0) == -1
