@@ -2,7 +2,9 @@
 benchmark uses (same library calls, same sizes).
 
 * dense d = 8192, k = 64, mu = 1e-4, rtol 1e-10: plain FP64 and FP32-MFMA +
-  FP64 refinement, both against the oracle's block-CG solution.
+  FP64 refinement, both against the oracle's block-CG solution; the same two
+  solves with A streamed from page-locked host memory in 8 chunks of 1024
+  rows (the out-of-core benchmark's configuration), against the same iterate.
 * ridge path n = 200000, d = 4096, k = 128, 64 shifts: BF16 block products
   with FP64 refinement against an FP64 ridge truth (thin QR of Z plus the SVD
   of its triangular factor); the plain FP64 path at t = 32 (exact termination,
@@ -68,6 +70,24 @@ def test_dense_d8192_fp64_and_mixed(R):
     kappa = (1.0 + mu) / (8192 ** -1.5 + mu)
     assert e64 < fp64_bound(kappa)
     assert emx < 1e-8
+    # the same solves with A in page-locked host memory, streamed in the benchmark's 8 chunks of
+    # 1024 rows (FP64, and FP32 chunks with FP64 refinement), against the same oracle iterate
+    note("full dense d=8192: A streamed from host memory")
+    hop = rbcg.DenseHostOperator(ctx, torch.from_numpy(A).pin_memory(), 1024, lo="f32")
+    xs64 = torch.zeros_like(bd)
+    xsmx = torch.zeros_like(bd)
+    rc, infos64 = rbcg.solve(ctx, [hop], [mu], [bd], [omd], [xs64], [rbcg.opts(48, rtol=1e-10, refine_max=3)])
+    assert rc == 0, infos64
+    rc, infosmx = rbcg.solve(ctx, [hop], [mu], [bd], [omd], [xsmx],
+                             [rbcg.opts(48, rtol=1e-10, matvec="f32", refine_max=8)])
+    assert rc == 0, infosmx
+    es64 = a_err(A, mu, xs64.cpu().numpy(), Xo[0])
+    esmx = a_err(A, mu, xsmx.cpu().numpy(), Xo[0])
+    note(f"streamed fp64 iters {infos64[0]['iters']} err {es64:.2e}; streamed mixed loads "
+         f"{infosmx[0]['matrix_loads']} err {esmx:.2e}")
+    assert infos64[0]["iters"] == t
+    assert es64 < fp64_bound(kappa)
+    assert esmx < 1e-8
 
 
 def test_ridge_path_full_bf16_refined(R):
