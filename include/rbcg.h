@@ -122,8 +122,9 @@ int rbcg_op_create_gram(rbcg_ctx* ctx, rbcg_op** op, int64_t n, int64_t d, const
  * freed by rbcg_op_destroy.  Supported by rbcg_solve, rbcg_op_apply /
  * rbcg_op_apply_noalloc and rbcg_nystrom_pcg; rbcg_path, rbcg_sqrt_apply and
  * rbcg_invsqrt_apply return RBCG_ERR_UNSUPPORTED, and so do FP32 products
- * without the FP32 copy.  A converged solve may still stream one product
- * issued ahead of the host's convergence check. */
+ * without the FP32 copy.  The staging buffers belong to the handle: calls
+ * that use one streamed handle at the same time (from several contexts or
+ * threads) race. */
 int rbcg_op_create_dense_host(rbcg_ctx* ctx, rbcg_op** op, int64_t d, const double* A_host /*host, pinned*/,
                               int64_t lda, int64_t chunk_rows, int lo);
 int rbcg_op_destroy(rbcg_op* op);

@@ -67,8 +67,6 @@ struct rbcg_ctx {
   // further width, driven from its own host thread
   std::vector<rbcg_ctx*> children;
   bool owns_stream = false;
-  // autotuned split counts of dense block products: (precision, d, N) -> splits
-  std::map<std::tuple<int, int64_t, int>, int> tuned_splits;
   hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;   // tuning timers
   // pinned staging of descriptor uploads: the copy runs asynchronously on the stream; the next
   // upload waits for it before reusing the buffer
@@ -1691,6 +1689,25 @@ static void build_program(Program& pg, Engine& E, const std::vector<double>& tol
   }
 }
 
+// Split counts the autotuner chose for dense block products, per (device, precision, d, N).  One
+// table for the process: a later context, or the child context of a batch width class, reuses a
+// shape's timing instead of repeating it (the choice depends on the device and the shape only).
+static std::mutex g_tuned_mu;
+static std::map<std::tuple<int, int, int64_t, int>, int> g_tuned;
+
+static bool tuned_lookup(int dev, int mv, int64_t d, int N, int* splits) {
+  std::lock_guard<std::mutex> lk(g_tuned_mu);
+  const auto it = g_tuned.find(std::make_tuple(dev, mv, d, N));
+  if (it == g_tuned.end()) return false;
+  *splits = it->second;
+  return true;
+}
+
+static void tuned_store(int dev, int mv, int64_t d, int N, int splits) {
+  std::lock_guard<std::mutex> lk(g_tuned_mu);
+  g_tuned[std::make_tuple(dev, mv, d, N)] = splits;
+}
+
 // Partial-buffer sizes of the per-problem products (max over all steps) and of the groups.
 // Split counts worth timing for a dense block product around the heuristic `base`: base / 2,
 // base, 2 base, each at least 2 and leaving at least 512 values of k per split.
@@ -1741,10 +1758,9 @@ static void size_partials(Engine& E, const rbcg_ctx* ctx) {
     }
     G.tune.clear();
     if (ctx && E.Gs.size() == 1 && G.op->kind == RBCG_OP_DENSE && !G.op->host && G.N <= 144) {
-      const auto key = std::make_tuple(G.mv_t, (int64_t)d, G.N);
-      const auto it = ctx->tuned_splits.find(key);
-      if (it != ctx->tuned_splits.end()) {
-        G.splits2 = it->second;
+      int tuned = 0;
+      if (tuned_lookup(ctx->device, G.mv_t, d, G.N, &tuned)) {
+        G.splits2 = tuned;
       } else {
         G.tune = split_candidates(d, G.splits2);
         if (G.tune.size() < 2) G.tune.clear();
@@ -2424,7 +2440,7 @@ static int tune_products(rbcg_ctx* ctx, Engine& E, unsigned char* ddesc) {
     if (heur_ms > 0.f && best_ms > 0.95f * heur_ms) best = heuristic;
     G.splits2 = best;
     G.tune.clear();
-    ctx->tuned_splits[std::make_tuple(G.mv_t, G.op->d, G.N)] = best;
+    tuned_store(ctx->device, G.mv_t, G.op->d, G.N, best);
   }
   return RBCG_OK;
 }
