@@ -1,5 +1,6 @@
 // FP64 tall block product on the 4x4x4 FP64 MFMA (four independent 4x4x4 blocks per
-// instruction): out(i, c) = sum_k P[i][k] X[c][k] for many rows i and 33 <= N <= 144 vectors c.
+// instruction): out(i, c) = sum_k P[i][k] X[c][k] for many rows i and 33 <= N <= 144 vectors c,
+// P in FP64, or in FP32 widened to FP64 in registers (the Gram operator's FP64 products).
 // On gfx950 this instruction issues FP64 multiply-adds at the rate of the 16x16x4 one, and its
 // 4-column granularity wastes less of a width such as 65 (68 columns instead of 80).
 //
@@ -23,7 +24,7 @@
 
 namespace rbcg {
 
-template <int CG, int KC, bool PVEC>
+template <int CG, int KC, bool PVEC, typename PT>
 __global__ __launch_bounds__(256) void k_mv_tall44(const NtDesc* __restrict__ descs, int splits,
                                                    const int32_t* __restrict__ act) {
   static_assert(KC == 16 || KC == 32, "chunk of 4 or 8 values of k per lane");
@@ -78,28 +79,35 @@ __global__ __launch_bounds__(256) void k_mv_tall44(const NtDesc* __restrict__ de
     }
   };
 
-  // this lane's row of P (A operand)
+  // this lane's row of P (A operand; FP32 values are widened to FP64 in registers)
   const int prow = i0 + wave * 16 + 4 * b + x;
   const bool pval = prow < d.M;
-  const gmem_t<const double> pp = gmem((const double*)d.P.p) + (pval ? row_off(d.P, prow) : 0);
+  const gmem_t<const PT> pp = gmem((const PT*)d.P.p) + (pval ? row_off(d.P, prow) : 0);
   double ar[KPL];
   auto load_a = [&](int kc) {
     const int k = kc + KPL * q;
     if (pval && k + KPL <= ke) {   // whole run in range: no per-element checks
-      if constexpr (PVEC) {
+      if constexpr (PVEC && sizeof(PT) == 8) {
 #pragma unroll
         for (int t = 0; t < KPL / 2; ++t) {
           const v2d u = *(gmem_t<const v2d>)(pp + k + 2 * t);
           ar[2 * t] = u[0];
           ar[2 * t + 1] = u[1];
         }
+      } else if constexpr (PVEC) {
+#pragma unroll
+        for (int t = 0; t < KPL / 4; ++t) {
+          const v4f u = *(gmem_t<const v4f>)(pp + k + 4 * t);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) ar[4 * t + e] = (double)u[e];
+        }
       } else {
 #pragma unroll
-        for (int e = 0; e < KPL; ++e) ar[e] = pp[k + e];
+        for (int e = 0; e < KPL; ++e) ar[e] = (double)pp[k + e];
       }
     } else {
 #pragma unroll
-      for (int e = 0; e < KPL; ++e) ar[e] = (pval && k + e < ke) ? pp[k + e] : 0.0;
+      for (int e = 0; e < KPL; ++e) ar[e] = (pval && k + e < ke) ? (double)pp[k + e] : 0.0;
     }
   };
 
@@ -150,10 +158,10 @@ __global__ __launch_bounds__(256) void k_mv_tall44(const NtDesc* __restrict__ de
   }
 }
 
-template <int CG, bool PVEC, int KC = 32>
+template <int CG, bool PVEC, typename PT, int KC = 32>
 static hipError_t launch_44(const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act, hipStream_t st) {
   const size_t lds = (size_t)2 * 4 * CG * (KC + 4) * sizeof(double);
-  auto kern = k_mv_tall44<CG, KC, PVEC>;
+  auto kern = k_mv_tall44<CG, KC, PVEC, PT>;
   static const hipError_t attr =
       lds > 64 * 1024 ? hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
                       : hipSuccess;
@@ -163,22 +171,29 @@ static hipError_t launch_44(const NtDesc* dd, int nz, int maxM, int splits, cons
   return hipGetLastError();
 }
 
-template <bool PVEC>
+template <bool PVEC, typename PT>
 static hipError_t dispatch_44(int maxN, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act,
                               hipStream_t st) {
-  if (maxN <= 36) return launch_44<9, PVEC>(dd, nz, maxM, splits, act, st);
-  if (maxN <= 48) return launch_44<12, PVEC>(dd, nz, maxM, splits, act, st);
-  if (maxN <= 68) return launch_44<17, PVEC>(dd, nz, maxM, splits, act, st);
-  if (maxN <= 100) return launch_44<25, PVEC>(dd, nz, maxM, splits, act, st);
-  if (maxN <= 132) return launch_44<33, PVEC>(dd, nz, maxM, splits, act, st);
-  if (maxN <= 144) return launch_44<36, PVEC>(dd, nz, maxM, splits, act, st);
+  if (maxN <= 36) return launch_44<9, PVEC, PT>(dd, nz, maxM, splits, act, st);
+  if (maxN <= 48) return launch_44<12, PVEC, PT>(dd, nz, maxM, splits, act, st);
+  if (maxN <= 68) return launch_44<17, PVEC, PT>(dd, nz, maxM, splits, act, st);
+  if (maxN <= 100) return launch_44<25, PVEC, PT>(dd, nz, maxM, splits, act, st);
+  if (maxN <= 132) return launch_44<33, PVEC, PT>(dd, nz, maxM, splits, act, st);
+  if (maxN <= 144) return launch_44<36, PVEC, PT>(dd, nz, maxM, splits, act, st);
   return hipErrorInvalidValue;
 }
 
 hipError_t mv_f64_44(int maxN, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act,
                      hipStream_t st) {
-  return pvec ? dispatch_44<true>(maxN, dd, nz, maxM, splits, act, st)
-              : dispatch_44<false>(maxN, dd, nz, maxM, splits, act, st);
+  return pvec ? dispatch_44<true, double>(maxN, dd, nz, maxM, splits, act, st)
+              : dispatch_44<false, double>(maxN, dd, nz, maxM, splits, act, st);
+}
+
+// P in FP32 (Z or its transposed copy for the Gram operator's FP64 products), FP64 arithmetic.
+hipError_t mv_f32f64_44(int maxN, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act,
+                        hipStream_t st) {
+  return pvec ? dispatch_44<true, float>(maxN, dd, nz, maxM, splits, act, st)
+              : dispatch_44<false, float>(maxN, dd, nz, maxM, splits, act, st);
 }
 
 }  // namespace rbcg

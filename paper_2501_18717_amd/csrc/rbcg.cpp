@@ -35,7 +35,7 @@ hipError_t mv_f32(int tn, bool pvec, const NtDesc* dd, int nz, int maxM, int spl
 hipError_t mv_f64(int maxN, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act, hipStream_t st);
 hipError_t mv_f32_wide(int t2, int ne, int w, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act,
                        hipStream_t st);
-hipError_t mv_f32f64(int tn, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act,
+hipError_t mv_f32f64(int maxN, bool pvec, const NtDesc* dd, int nz, int maxM, int splits, const int32_t* act,
                      hipStream_t st);
 constexpr int DT_F32F64 = 3;   // FP32 values of P, FP64 arithmetic
 }
@@ -658,7 +658,7 @@ static hipError_t enqueue(const Launch& L, unsigned char* dbase, const int32_t* 
         const bool pvec = (L.a0 >> 10) & 1;
         switch (L.a0 & 0xff) {
           case DT_F32: return mv_f32(tn, pvec, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a3, act, st);
-          case DT_F32F64: return mv_f32f64(tn, pvec, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a3, act, st);
+          case DT_F32F64: return mv_f32f64(L.a2, pvec, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a3, act, st);
           default: return mv_f64(L.a2, pvec, dptr<NtDesc>(dbase, L.off), L.nz, L.a1, L.a3, act, st);
         }
       }
