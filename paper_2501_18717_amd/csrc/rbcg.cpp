@@ -522,7 +522,10 @@ static int gram64_splits(int d, int64_t n) {
 // dense d = 8192, m = 65 workload, 256 beats 512 and 1024.
 static int proj_splits(int M, int nz, int K) {
   const int tiles = (M + 63) / 64;
-  const int want = std::max(1, 256 / std::max(1, tiles * nz));
+  // about 256 workgroups in all, and ranges of k no longer than 4096 (several problems side by
+  // side already fill the chip; a single long range then leaves one workgroup per CU to wait on
+  // its loads)
+  const int want = std::max(std::max(1, 256 / std::max(1, tiles * nz)), (K + 4095) / 4096);
   const int cap = std::max(1, K / 128);
   return std::max(1, std::min(want, std::min(cap, 64)));
 }
