@@ -3413,8 +3413,8 @@ static int sqrt_driver(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, const doubl
   const int m = (int)std::min<int64_t>(gs, ms);
   if (tri_forward_lds(m, m) > kLdsCap || tri_backward_lds(m, m) > kLdsCap) return RBCG_ERR_INVALID_ARG;
   const int ngroups = (int)((ms + m - 1) / m);
-  // the block products of all groups are fused into one product of N = ngroups * m vectors,
-  // and the general NT product kernel takes at most 16 column tiles of 16
+  // the block products of all groups are fused into one product of N = ngroups * m vectors (run
+  // as column chunks of at most 144); the workspace is sized, and the path tested, up to 256
   if (ngroups * m > 256) return RBCG_ERR_UNSUPPORTED;
   hipStream_t st = ctx->stream;
   const int d = (int)op->d;
