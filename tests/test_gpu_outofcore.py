@@ -178,6 +178,30 @@ def test_streamed_solve_to_rtol_and_batched_beside_device_operator(R, c_mid):
     assert a_err(P["A"], P["mu"], xh.cpu().numpy(), xd.cpu().numpy()) <= 1e-9
 
 
+def test_two_systems_share_one_streamed_operator(R, c_mid):
+    """Two right-hand sides of one streamed operator in one call (their products take turns in
+    the handle's staging buffers): both reach rtol and match the single-system solves."""
+    import torch
+    rbcg, ctx = R
+    P = c_mid
+    note("two systems on one streamed operator d=1500 chunk=300")
+    op = rbcg.DenseHostOperator(ctx, _pinned(P["A"]), 300)
+    b1 = to_dev(P["b"])
+    b2 = to_dev(synth.rng(9, 1).standard_normal(1500))
+    om = to_dev(P["omega"])
+    o = rbcg.opts(60, rtol=1e-10)
+    x1, x2 = torch.zeros_like(b1), torch.zeros_like(b1)
+    rc, info = rbcg.solve(ctx, [op, op], [P["mu"], 10 * P["mu"]], [b1, b2], [om, om], [x1, x2], [o, o],
+                          check=False)
+    assert rc == 0, info
+    assert info[0]["relres"] <= 1e-10 and info[1]["relres"] <= 1e-10
+    for bb, mu, xb in ((b1, P["mu"], x1), (b2, 10 * P["mu"], x2)):
+        xs = torch.zeros_like(bb)
+        rc, _ = rbcg.solve(ctx, [op], [mu], [bb], [om], [xs], [o], check=False)
+        assert rc == 0
+        assert a_err(P["A"], mu, xb.cpu().numpy(), xs.cpu().numpy()) <= 1e-9
+
+
 def test_streamed_nystrom_pcg_matches_definition(R):
     import torch
     rbcg, ctx = R
