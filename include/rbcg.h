@@ -119,10 +119,11 @@ int rbcg_op_create_gram(rbcg_ctx* ctx, rbcg_op** op, int64_t n, int64_t d, const
  * (RNE, rows padded to 64 values) in page-locked host memory the handle
  * allocates, which low-precision products stream (half the bytes per load);
  * FP64 residuals always stream A itself.  Everything the handle allocates is
- * freed by rbcg_op_destroy.  Supported by rbcg_solve, rbcg_op_apply /
- * rbcg_op_apply_noalloc and rbcg_nystrom_pcg; rbcg_path, rbcg_sqrt_apply and
- * rbcg_invsqrt_apply return RBCG_ERR_UNSUPPORTED, and so do FP32 products
- * without the FP32 copy.  The staging buffers belong to the handle: calls
+ * freed by rbcg_op_destroy.  Every call that takes an operator accepts it;
+ * FP32 products without the FP32 copy return RBCG_ERR_UNSUPPORTED.  rbcg_solve
+ * learns each step's convergence before it streams the next product;
+ * rbcg_path, rbcg_sqrt_apply and rbcg_invsqrt_apply keep their step loop,
+ * which may stream one product past convergence.  The staging buffers belong to the handle: calls
  * that use one streamed handle at the same time (from several contexts or
  * threads) race. */
 int rbcg_op_create_dense_host(rbcg_ctx* ctx, rbcg_op** op, int64_t d, const double* A_host /*host, pinned*/,

@@ -2928,7 +2928,6 @@ extern "C" int rbcg_path(rbcg_ctx* ctx, const rbcg_op* op, const double* b, cons
   if (!ctx || !op || !b || !mu || !X || !opts || !info || L < 1 || L > 256 || !valid_opts(opts))
     return RBCG_ERR_INVALID_ARG;
   if (k < 0 || k >= op->d || k + 1 > kMaxBlock) return RBCG_ERR_INVALID_ARG;
-  if (op->host) return RBCG_ERR_UNSUPPORTED;   // streamed operators: solve, op_apply, Nystrom PCG
   for (int64_t l = 0; l < L; ++l)
     if (!(mu[l] >= 0.0) || !std::isfinite(mu[l])) return RBCG_ERR_INVALID_ARG;
   if (!op_supports(op, opts->matvec)) return RBCG_ERR_UNSUPPORTED;
@@ -3698,13 +3697,11 @@ static int sqrt_driver(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, const doubl
 
 extern "C" int rbcg_sqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, const double* B, double* Y,
                                const rbcg_opts* opts, rbcg_info* info) {
-  if (op && op->host) return RBCG_ERR_UNSUPPORTED;
   return sqrt_driver(ctx, op, ms, B, Y, opts, info, false);
 }
 
 extern "C" int rbcg_invsqrt_apply(rbcg_ctx* ctx, const rbcg_op* op, int64_t ms, const double* B, double* Y,
                                   const rbcg_opts* opts, rbcg_info* info) {
-  if (op && op->host) return RBCG_ERR_UNSUPPORTED;
   return sqrt_driver(ctx, op, ms, B, Y, opts, info, true);
 }
 

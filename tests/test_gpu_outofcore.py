@@ -15,8 +15,10 @@ chunks, and every block product loads each chunk once).  Through the C ABI:
   device-resident system;
 - Nystrom PCG (Sec. 2.2.2) with the streamed operator reproduces the
   preconditioned-CG definition to 1e-9, as with the device operator;
-- the entry points that do not stream reject it (RBCG_ERR_UNSUPPORTED), and
-  pageable host memory is rejected (RBCG_ERR_INVALID_ARG).
+- the ridge-type path and the (inverse) square root with the streamed operator
+  give the device-resident operator's results;
+- FP32 products without the handle's FP32 copy are rejected
+  (RBCG_ERR_UNSUPPORTED), and so is pageable host memory (RBCG_ERR_INVALID_ARG).
 """
 import ctypes
 
@@ -222,6 +224,44 @@ def test_streamed_nystrom_pcg_matches_definition(R):
         assert err < 1e-9
 
 
+def test_streamed_path_and_sampling_match_device_operator(R):
+    """The path (every shift) and the square root / inverse square root with the streamed
+    operator give the device-resident operator's results: the same arithmetic, with products
+    summed chunk by chunk (FP64 path at fixed t: 5e-12, about kappa u for kappa ~ 8e3; FP32
+    chunks + FP64 refinement, both at rtol 1e-10: 1e-8; sampling: 1e-10 relative)."""
+    import torch
+    rbcg, ctx = R
+    P = synth.dense_problem(6, 1200, 1.5, 16, 1e-4)
+    mus = [1e-4, 1e-3, 1e-2, 1e-1]
+    hop = rbcg.DenseHostOperator(ctx, _pinned(P["A"]), 256, lo="f32")
+    dop = rbcg.DenseOperator(ctx, to_dev(P["A"]), lo="f32")
+    b, om = to_dev(P["b"]), to_dev(P["omega"])
+    for o, tol in ((rbcg.opts(12), 5e-12), (rbcg.opts(40, rtol=1e-10, matvec="f32", refine_max=8), 1e-8)):
+        note(f"streamed path d=1200 chunk=256 L=4 matvec={o.matvec}")
+        Xh = torch.zeros((len(mus), 1200), dtype=torch.float64, device="cuda")
+        Xd = torch.zeros_like(Xh)
+        rc, ih = rbcg.path(ctx, hop, b, om, mus, Xh, o, check=False)
+        assert rc == 0, ih
+        rc, idv = rbcg.path(ctx, dop, b, om, mus, Xd, o, check=False)
+        assert rc == 0, idv
+        worst = max(a_err(P["A"], mu, Xh[l].cpu().numpy(), Xd[l].cpu().numpy()) for l, mu in enumerate(mus))
+        note(f"  streamed vs device-resident, worst shift {worst:.2e}")
+        assert worst <= tol
+    Bs = synth.rng(7, 2).standard_normal((40, 1200))
+    for inverse in (False, True):
+        fn = rbcg.invsqrt_apply if inverse else rbcg.sqrt_apply
+        note(f"streamed {'inverse ' if inverse else ''}square root, 40 samples in groups of 16")
+        Yh = torch.zeros((40, 1200), dtype=torch.float64, device="cuda")
+        Yd = torch.zeros_like(Yh)
+        rc, _ = fn(ctx, hop, to_dev(Bs), Yh, rbcg.opts(10, nquad=16, group=16), check=False)
+        assert rc == 0
+        rc, _ = fn(ctx, dop, to_dev(Bs), Yd, rbcg.opts(10, nquad=16, group=16), check=False)
+        assert rc == 0
+        rel = float((torch.linalg.norm(Yh - Yd, dim=1) / torch.linalg.norm(Yd, dim=1)).max())
+        note(f"  streamed vs device-resident {rel:.2e}")
+        assert rel <= 1e-10
+
+
 def test_streamed_operator_rejections(R):
     import torch
     rbcg, ctx = R
@@ -229,13 +269,6 @@ def test_streamed_operator_rejections(R):
     op = rbcg.DenseHostOperator(ctx, _pinned(P["A"]), 64)
     b = to_dev(P["b"])
     om = to_dev(P["omega"])
-    X = torch.zeros((2, 256), dtype=torch.float64, device="cuda")
-    rc, _ = rbcg.path(ctx, op, b, om, [1e-3, 1e-2], X, rbcg.opts(4), check=False)
-    assert rc == -7
-    B = torch.zeros((4, 256), dtype=torch.float64, device="cuda")
-    Y = torch.zeros_like(B)
-    rc, _ = rbcg.sqrt_apply(ctx, op, B, Y, rbcg.opts(4, nquad=4, group=4), check=False)
-    assert rc == -7
     x = torch.zeros_like(b)
     rc, _ = rbcg.solve(ctx, [op], [1e-3], [b], [om], [x], [rbcg.opts(8, rtol=1e-8, matvec="f32", refine_max=3)],
                        check=False)
