@@ -13,10 +13,12 @@
 // only when the accumulation error stays well below it along the small singular directions,
 // whose sums cancel heavily.
 //
-// Workgroup: 4 waves (256 threads), one workgroup per CU and one wave per SIMD, so the
-// accumulators can live in the accumulation registers.  Wave w owns 64 rows of P (RT = 4 tiles of
-// 16) and every column tile of X, so a workgroup covers 256 rows.  Per chunk of 64 values of k,
-// each lane streams 32 bytes of each of its 4 rows of P (row r16 of the tile, k = 16 q .. 16 q +
+// Workgroup: 8 waves (512 threads), one workgroup per CU (its double-buffered X image takes 111 KB
+// of LDS) and two waves per SIMD.  Wave w owns 32 rows of P (RT = 2 tiles of 16) and every column
+// tile of X, so a workgroup covers 256 rows; with 4 waves of 64 rows each the accumulators filled
+// the accumulation registers and one wave per SIMD streamed Z (measured 1.03 ms per pass at the
+// ridge workload's 129 columns, against 0.89 ms with 8 waves).  Per chunk of 64 values of k,
+// each lane streams 32 bytes of each of its RT rows of P (row r16 of the tile, k = 16 q .. 16 q +
 // 15, q = lane / 16) into registers, and the workgroup stages the X chunk (3 parts x 16 NT
 // columns x 64 k, BF16) into a double-buffered LDS image; both are loaded one chunk ahead, their
 // loads in flight while the MFMAs of the current chunk run.  The image is laid out [part][k-group
@@ -35,8 +37,10 @@ namespace rbcg {
 
 namespace {
 
-constexpr int kGramRT = 4;                   // row tiles of 16 per wave
-constexpr int kGramRows = 16 * kGramRT * 4;  // rows of P per workgroup
+constexpr int kGramW = 8;                    // waves per workgroup
+constexpr int kGramThreads = 64 * kGramW;
+constexpr int kGramRT = 16 / kGramW;         // row tiles of 16 per wave
+constexpr int kGramRows = 16 * kGramRT * kGramW;  // rows of P per workgroup (256)
 constexpr int kGramKC = 64;                  // k values per chunk
 constexpr int kGramSplitK = 512;             // target k values per split (FP32 chain length)
 constexpr int kParts = 3;
@@ -47,15 +51,15 @@ struct GramLds {
   static constexpr int CS = NR + 1;              // column slots per (part, group), one of padding
   static constexpr int BUF = kParts * 8 * CS;    // 16-byte slots of one buffer
   static constexpr int ITEMS = kParts * 8 * NR;  // 16-byte items staged per chunk
-  static constexpr int XP = (ITEMS + 255) / 256;
+  static constexpr int XP = (ITEMS + kGramThreads - 1) / kGramThreads;
   static constexpr size_t BYTES = (size_t)2 * BUF * 16;
-  static_assert((size_t)4 * 16 * NR * 4 <= BYTES, "epilogue image must fit");
+  static_assert((size_t)kGramW * 16 * NR * 4 <= BYTES, "epilogue image must fit");
 };
 
 }  // namespace
 
 template <int NT>
-__global__ __launch_bounds__(256, 1) void k_gram_bf16(const NtDesc* __restrict__ descs, int splits,
+__global__ __launch_bounds__(kGramThreads, 1) void k_gram_bf16(const NtDesc* __restrict__ descs, int splits,
                                                       const int32_t* __restrict__ act) {
   typedef GramLds<NT> L;
   const NtDesc d = descs[blockIdx.z];
@@ -83,7 +87,7 @@ __global__ __launch_bounds__(256, 1) void k_gram_bf16(const NtDesc* __restrict__
   auto load_x = [&](int kc) {
 #pragma unroll
     for (int t = 0; t < L::XP; ++t) {
-      const int it = tid + 256 * t;
+      const int it = tid + kGramThreads * t;
       v8u v = v8u{0, 0, 0, 0, 0, 0, 0, 0};
       if (it < L::ITEMS) {
         const int g = it & 7, pc = it >> 3;
@@ -105,7 +109,7 @@ __global__ __launch_bounds__(256, 1) void k_gram_bf16(const NtDesc* __restrict__
   auto store_x = [&](int buf) {
 #pragma unroll
     for (int t = 0; t < L::XP; ++t) {
-      const int it = tid + 256 * t;
+      const int it = tid + kGramThreads * t;
       if (it < L::ITEMS) {
         const int g = it & 7, pc = it >> 3;
         const int p = pc / L::NR, c = pc - p * L::NR;
@@ -258,7 +262,7 @@ static hipError_t launch_gram_bf16_t(const NtDesc* dd, int nz, int maxM, int spl
   const int ntiles = (maxM + kGramRows - 1) / kGramRows;
   const int total = ntiles * splits;
   const int per = (total + 7) / 8;
-  hipLaunchKernelGGL(kern, dim3(8 * per, 1, nz), dim3(256), lds, st, dd, splits, act);
+  hipLaunchKernelGGL(kern, dim3(8 * per, 1, nz), dim3(kGramThreads), lds, st, dd, splits, act);
   return hipGetLastError();
 }
 
